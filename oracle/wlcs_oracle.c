@@ -1,0 +1,184 @@
+/*
+ * Test infrastructure: the CPU oracle for alignment plots.
+ *
+ * Only the test suite, the smoke entry point and the CPU-baseline leg of the
+ * benchmark load this library.  The product path never calls it, and this file
+ * shares no code, header, table or helper with the HIP path.
+ *
+ * What it computes (Section 2 of Krusche & Tiskin, "Computing alignment plots
+ * efficiently"): for strings x (length m) and y (length n) and a window length
+ * w, the alignment plot is the matrix
+ *
+ *     WLCS(i, j) = LLCS(x_i .. x_{i+w-1}, y_j .. y_{j+w-1})
+ *
+ * for i in 1..m-w and j in 1..n-w (1-based, as the paper defines the plot), that
+ * is, the length of a longest common subsequence of every pair of w-windows.
+ * Stored 0-based: out[i*ld + j] holds WLCS(i+1, j+1) for 0 <= i < m-w,
+ * 0 <= j < n-w.  With full_range != 0 the plot covers every window,
+ * 0 <= i <= m-w and 0 <= j <= n-w.
+ *
+ * How: the paper's baseline, the standard dynamic program (Wagner-Fischer /
+ * Needleman-Wunsch with LCS scores: match 1, mismatch 0, gap 0; Section 2),
+ * run independently for every window pair, O(m n w^2) in total.  Nothing here
+ * uses seaweeds: the oracle is the plain definition written out.
+ *
+ *     L[p][0] = L[0][q] = 0
+ *     L[p][q] = L[p-1][q-1] + 1                  if a[p-1] == b[q-1]
+ *             = max(L[p-1][q], L[p][q-1])        otherwise
+ *     LLCS(a, b) = L[|a|][|b|]
+ *
+ * Characters are compared as raw bytes.  Parallelism is over independent rows
+ * of the plot only (plain POSIX threads, static partition); each entry is
+ * evaluated by the recurrence above in its textbook order.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL -1
+#define ORACLE_ENOMEM -2
+
+/* LLCS of a (length la) and b (length lb) by the full (la+1) x (lb+1) table.
+ * tab must hold (la+1)*(lb+1) ints.  Standard dynamic program, Section 2. */
+static int llcs_table(const uint8_t *a, int la, const uint8_t *b, int lb, int *tab)
+{
+    const int cols = lb + 1;
+    for (int q = 0; q <= lb; ++q) tab[q] = 0;          /* L[0][q] = 0 */
+    for (int p = 1; p <= la; ++p) {
+        tab[p * cols] = 0;                               /* L[p][0] = 0 */
+        for (int q = 1; q <= lb; ++q) {
+            int v;
+            if (a[p - 1] == b[q - 1]) {
+                v = tab[(p - 1) * cols + (q - 1)] + 1;
+            } else {
+                int up = tab[(p - 1) * cols + q];
+                int left = tab[p * cols + (q - 1)];
+                v = up > left ? up : left;
+            }
+            tab[p * cols + q] = v;
+        }
+    }
+    return tab[la * cols + lb];
+}
+
+int oracle_llcs(const uint8_t *a, int64_t la, const uint8_t *b, int64_t lb)
+{
+    if (la < 0 || lb < 0 || (la > 0 && !a) || (lb > 0 && !b)) return ORACLE_EINVAL;
+    if (la > 4096 || lb > 4096) return ORACLE_EINVAL;
+    int *tab = (int *)malloc(sizeof(int) * (size_t)(la + 1) * (size_t)(lb + 1));
+    if (!tab) return ORACLE_ENOMEM;
+    int r = llcs_table(a, (int)la, b, (int)lb, tab);
+    free(tab);
+    return r;
+}
+
+/* Number of windows along a string of length len for window w: the paper's
+ * plot takes len - w of them (i in 1..len-w); full_range takes all len - w + 1. */
+static int64_t n_windows(int64_t len, int32_t w, int full_range)
+{
+    int64_t k = len - w + (full_range ? 1 : 0);
+    return k > 0 ? k : 0;
+}
+
+typedef struct {
+    const uint8_t *x, *y;
+    int32_t w;
+    int64_t rows, cols;
+    const int64_t *row_ids;   /* NULL: rows 0..rows-1; else the listed x-windows */
+    uint8_t *out;
+    int64_t ld;
+    int64_t r0, r1;           /* this worker's range of output rows */
+} rows_job;
+
+static void *rows_worker(void *arg)
+{
+    rows_job *jb = (rows_job *)arg;
+    const int w = jb->w;
+    int *tab = (int *)malloc(sizeof(int) * (size_t)(w + 1) * (size_t)(w + 1));
+    if (!tab) return (void *)1;
+    for (int64_t r = jb->r0; r < jb->r1; ++r) {
+        int64_t i = jb->row_ids ? jb->row_ids[r] : r;
+        for (int64_t j = 0; j < jb->cols; ++j)
+            jb->out[r * jb->ld + j] = (uint8_t)llcs_table(jb->x + i, w, jb->y + j, w, tab);
+    }
+    free(tab);
+    return NULL;
+}
+
+static int run_rows(const uint8_t *x, const uint8_t *y, int32_t w, int64_t rows, int64_t cols,
+                    const int64_t *row_ids, uint8_t *out, int64_t ld, int nthreads)
+{
+    if (rows == 0 || cols == 0) return ORACLE_OK;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (nthreads > rows) nthreads = (int)rows;
+    rows_job jobs[256];
+    pthread_t th[256];
+    int started[256];
+    int status = ORACLE_OK;
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (rows_job){x, y, w, rows, cols, row_ids, out, ld,
+                             rows * t / nthreads, rows * (t + 1) / nthreads};
+        started[t] = (t > 0) && pthread_create(&th[t], NULL, rows_worker, &jobs[t]) == 0;
+        if (t > 0 && !started[t]) status = ORACLE_ENOMEM;
+    }
+    if (rows_worker(&jobs[0]) != NULL) status = ORACLE_ENOMEM;
+    for (int t = 1; t < nthreads; ++t) {
+        if (!started[t]) {
+            if (rows_worker(&jobs[t]) != NULL) status = ORACLE_ENOMEM;
+            continue;
+        }
+        void *ret = NULL;
+        pthread_join(th[t], &ret);
+        if (ret != NULL) status = ORACLE_ENOMEM;
+    }
+    return status;
+}
+
+/* Whole alignment plot into host memory out (rows x cols, row stride ld). */
+int oracle_wlcs(const uint8_t *x, int64_t m, const uint8_t *y, int64_t n, int32_t w,
+                int32_t full_range, uint8_t *out, int64_t ld, int32_t nthreads)
+{
+    if (m < 0 || n < 0 || w < 1 || w > 255) return ORACLE_EINVAL;
+    int64_t rows = n_windows(m, w, full_range), cols = n_windows(n, w, full_range);
+    if (rows == 0 || cols == 0) return ORACLE_OK;
+    if (!x || !y || !out || ld < cols) return ORACLE_EINVAL;
+    return run_rows(x, y, w, rows, cols, NULL, out, ld, nthreads);
+}
+
+/* Selected rows of the plot: out row r holds x-window row_ids[r] against every
+ * y-window (cols entries, stride ld). */
+int oracle_wlcs_rows(const uint8_t *x, int64_t m, const uint8_t *y, int64_t n, int32_t w,
+                     int32_t full_range, const int64_t *row_ids, int64_t nrows,
+                     uint8_t *out, int64_t ld, int32_t nthreads)
+{
+    if (m < 0 || n < 0 || w < 1 || w > 255 || nrows < 0) return ORACLE_EINVAL;
+    int64_t rows = n_windows(m, w, full_range), cols = n_windows(n, w, full_range);
+    if (nrows == 0 || cols == 0) return ORACLE_OK;
+    if (!x || !y || !out || !row_ids || ld < cols) return ORACLE_EINVAL;
+    for (int64_t r = 0; r < nrows; ++r)
+        if (row_ids[r] < 0 || row_ids[r] >= rows) return ORACLE_EINVAL;
+    return run_rows(x, y, w, nrows, cols, row_ids, out, ld, nthreads);
+}
+
+/* Individual entries: out[k] = WLCS at (ii[k], jj[k]) (0-based window starts). */
+int oracle_wlcs_at(const uint8_t *x, int64_t m, const uint8_t *y, int64_t n, int32_t w,
+                   const int64_t *ii, const int64_t *jj, int64_t count, uint8_t *out)
+{
+    if (m < 0 || n < 0 || w < 1 || w > 255 || count < 0) return ORACLE_EINVAL;
+    if (count == 0) return ORACLE_OK;
+    if (!x || !y || !ii || !jj || !out) return ORACLE_EINVAL;
+    int *tab = (int *)malloc(sizeof(int) * (size_t)(w + 1) * (size_t)(w + 1));
+    if (!tab) return ORACLE_ENOMEM;
+    for (int64_t k = 0; k < count; ++k) {
+        if (ii[k] < 0 || jj[k] < 0 || ii[k] + w > m || jj[k] + w > n) {
+            free(tab);
+            return ORACLE_EINVAL;
+        }
+        out[k] = (uint8_t)llcs_table(x + ii[k], w, y + jj[k], w, tab);
+    }
+    free(tab);
+    return ORACLE_OK;
+}

@@ -1,0 +1,254 @@
+"""Host-side models of the seaweed method, checked against the oracle (no GPU).
+
+These pin the readings of the paper that the HIP kernels are built on, with
+tiny pure-Python models that share nothing with either the oracle or the
+kernels:
+
+* the combing rule of the seaweed algorithm (Section 2, Algorithm 1, whose
+  figures are lost: the rule is read from the prose): seaweeds start at the
+  top of every column and the left of every row; in a match cell the two
+  seaweeds turn, in a mismatch cell they cross unless they have crossed
+  before.  Labelled by start column (left starts lowest), a mismatch cell sends
+  the larger label down and the smaller one right;
+* Theorem 2.1 in its string-substring form: LLCS(x, y[a:b]) equals b - a minus
+  the number of seaweeds that start and end inside columns [a, b);
+* Theorem 3.1's window count: WLCS(j) = w - d(j), with d(j) the seaweeds that
+  start and leave the bottom within window j; the count is kept with a ring of
+  pending start marks, O(1) per column;
+* the relabelling freedom the kernels use: restarting the combing at any
+  column, and clamping labels that are older than every open window (the bit
+  bound of Propositions 3.3 and 3.4), leave every count unchanged;
+* the branch-free cell form of the kernels: with Z = 0 on a match and Z at
+  least every label on a mismatch, bottom = max(s, min(t, Z)) and
+  right = s xor t xor bottom.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import workloads
+
+LEFT = -1  # every seaweed entering from the left boundary; below all top labels
+
+
+def comb(xw, y, start=0):
+    """Comb one strip (rows xw, columns y[start:]) and return, per column l,
+    the start label of the seaweed leaving its bottom, plus the labels in flight
+    to the right after every column."""
+    w = len(xw)
+    h = [LEFT] * w
+    exits, flight = [], []
+    for l in range(start, len(y)):
+        t = l
+        for k in range(w):
+            s = h[k]
+            if xw[k] == y[l]:
+                h[k], t = t, s          # match: the seaweeds turn
+            else:
+                h[k], t = min(s, t), max(s, t)  # cross unless crossed already
+        exits.append(t)
+        flight.append(list(h))
+    return exits, flight
+
+
+def plot_by_count(x, y, w, full=False):
+    """Whole plot from per-strip combing and the sliding count."""
+    rows = max(len(x) - w + (1 if full else 0), 0)
+    cols = max(len(y) - w + (1 if full else 0), 0)
+    out = np.zeros((rows, cols), dtype=np.uint8)
+    for i in range(rows):
+        exits, _ = comb(x[i:i + w], y)
+        for j in range(cols):
+            d = sum(1 for l in range(j, j + w) if exits[l] >= j)
+            out[i, j] = w - d
+    return out
+
+
+def ring_count(exits, w, ncols):
+    """The kernels' O(1)-per-column count: a running total plus a ring of w
+    pending marks keyed by start column."""
+    ring = [0] * w     # bit p <-> start column (l - w + 1 + p) after the shift
+    cur, out = 0, []
+    for l in range(len(exits)):
+        f = ring[0]                                # mark for start l - w
+        ring = ring[1:] + [0]
+        p = exits[l] - (l - w + 1)                 # w-1-span of the exit
+        valid = exits[l] != LEFT and 0 <= p < w   # left starts never count
+        if valid:
+            ring[p] = 1
+        cur += int(valid) - f
+        if l >= w - 1 and l - w + 1 < ncols:
+            out.append(w - cur)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_theorem_2_1_all_substrings(oracle_mod, seed):
+    g = workloads.rng(200 + seed)
+    for _ in range(6):
+        w = int(g.integers(1, 7))
+        xw = workloads.iid(g, w, workloads.DNA).tobytes()
+        y = workloads.iid(g, int(g.integers(1, 14)), workloads.DNA).tobytes()
+        exits, _ = comb(xw, y)
+        for a in range(len(y) + 1):
+            for b in range(a, len(y) + 1):
+                inside = sum(1 for l in range(a, b) if exits[l] >= a)
+                assert oracle_mod.llcs(xw, y[a:b]) == (b - a) - inside
+
+
+def test_exits_form_permutation():
+    g = workloads.rng(210)
+    for _ in range(20):
+        w = int(g.integers(1, 9))
+        xw = workloads.iid(g, w, b"AB").tobytes()
+        y = workloads.iid(g, 30, b"AB").tobytes()
+        exits, flight = comb(xw, y)
+        tops = [e for e in exits if e != LEFT]
+        assert len(set(tops)) == len(tops)
+        assert all(e <= l for l, e in enumerate(exits))
+        # every seaweed (w from the left, one per column from the top) either
+        # left through the bottom or is still in flight at the right edge
+        assert sorted(exits + flight[-1]) == [LEFT] * w + list(range(len(y)))
+
+
+def test_exhaustive_binary_windows(oracle_mod):
+    for w in range(1, 4):
+        for x in itertools.product(b"AB", repeat=w + 2):
+            x = bytes(x)
+            for y in itertools.product(b"AB", repeat=w + 3):
+                y = bytes(y)
+                np.testing.assert_array_equal(plot_by_count(x, y, w), oracle_mod.wlcs(x, y, w))
+
+
+@pytest.mark.parametrize("w,alpha", [(1, workloads.DNA), (5, workloads.DNA),
+                                     (16, workloads.DNA), (9, workloads.PROTEIN)])
+def test_count_plot_equals_oracle(oracle_mod, w, alpha):
+    g = workloads.rng(220 + w)
+    x, y = workloads.iid(g, w + 25, alpha), workloads.iid(g, w + 40, alpha)
+    x, y = x.tobytes(), y.tobytes()
+    for full in (False, True):
+        np.testing.assert_array_equal(plot_by_count(x, y, w, full), oracle_mod.wlcs(x, y, w, full))
+
+
+@pytest.mark.parametrize("w", [1, 3, 8, 16])
+def test_ring_count_equals_direct(oracle_mod, w):
+    g = workloads.rng(230 + w)
+    x, y = workloads.iid(g, w + 12, workloads.DNA).tobytes(), \
+        workloads.iid(g, w + 60, workloads.DNA).tobytes()
+    want = oracle_mod.wlcs(x, y, w)
+    for i in range(want.shape[0]):
+        exits, _ = comb(x[i:i + w], y)
+        assert ring_count(exits, w, want.shape[1]) == list(want[i])
+
+
+@pytest.mark.parametrize("w", [2, 7, 16])
+def test_in_flight_formula(oracle_mod, w):
+    # after column j+w-1, WLCS(i, j) = number of seaweeds in flight that
+    # started at or after column j
+    g = workloads.rng(240 + w)
+    x, y = workloads.iid(g, w + 5, workloads.DNA).tobytes(), \
+        workloads.iid(g, w + 30, workloads.DNA).tobytes()
+    want = oracle_mod.wlcs(x, y, w)
+    for i in range(want.shape[0]):
+        _, flight = comb(x[i:i + w], y)
+        got = [sum(1 for v in flight[j + w - 1] if v >= j) for j in range(want.shape[1])]
+        assert got == list(want[i])
+
+
+@pytest.mark.parametrize("w", [3, 8, 16])
+def test_tile_restart(oracle_mod, w):
+    # combing afresh from column c gives every window that starts at c or later
+    g = workloads.rng(250 + w)
+    x, y = workloads.iid(g, w + 3, workloads.DNA).tobytes(), \
+        workloads.iid(g, 90, workloads.DNA).tobytes()
+    want = oracle_mod.wlcs(x, y, w)
+    for i in range(want.shape[0]):
+        for c in (0, 1, 17, 40):
+            exits, _ = comb(x[i:i + w], y, start=c)
+            rel = [e - c if e != LEFT else LEFT for e in exits]
+            got = ring_count(rel, w, want.shape[1] - c)
+            assert got == list(want[i, c:])
+
+
+def test_label_clamp_is_exact(oracle_mod):
+    """Collapsing all labels older than the oldest open window into one value,
+    at arbitrary columns, changes no count (monotone relabelling commutes with
+    the max/min of the combing rule)."""
+    g = workloads.rng(260)
+    w = 6
+    x, y = workloads.iid(g, 10, workloads.DNA).tobytes(), \
+        workloads.iid(g, 120, workloads.DNA).tobytes()
+    want = oracle_mod.wlcs(x, y, w)
+    for i in range(want.shape[0]):
+        xw = x[i:i + w]
+        h = [LEFT] * w
+        exits = []
+        for l in range(len(y)):
+            if l % 13 == 0:
+                floor = l - w           # starts < floor can no longer count
+                h = [v if v >= floor else LEFT for v in h]
+            t = l
+            for k in range(w):
+                s = h[k]
+                if xw[k] == y[l]:
+                    h[k], t = t, s
+                else:
+                    h[k], t = min(s, t), max(s, t)
+            exits.append(t)
+        assert ring_count(exits, w, want.shape[1]) == list(want[i])
+
+
+def test_clamp_too_tight_fails(oracle_mod):
+    """Negative control: clamping labels that an open window still needs
+    (floor one column too high) must break some count."""
+    g = workloads.rng(261)
+    w = 6
+    bad_found = False
+    for trial in range(20):
+        x, y = workloads.iid(g, 10, workloads.DNA).tobytes(), \
+            workloads.iid(g, 80, workloads.DNA).tobytes()
+        want = oracle_mod.wlcs(x, y, w)
+        for i in range(want.shape[0]):
+            h = [LEFT] * w
+            exits = []
+            for l in range(len(y)):
+                floor = l - w + 2
+                h = [v if v >= floor else LEFT for v in h]
+                t = l
+                for k in range(w):
+                    s = h[k]
+                    if x[i + k] == y[l]:
+                        h[k], t = t, s
+                    else:
+                        h[k], t = min(s, t), max(s, t)
+                exits.append(t)
+            if ring_count(exits, w, want.shape[1]) != list(want[i]):
+                bad_found = True
+                break
+        if bad_found:
+            break
+    assert bad_found
+
+
+def test_branch_free_cell_form():
+    """The packed-16-bit cell: codes f(a) = a << 11 for x and g(b) = (32-b) << 11
+    for y add (mod 2^16) to 0 iff a == b and to >= 2^11 otherwise, so with
+    labels below 2^11, bottom = max(s, min(t, Z)), right = s ^ t ^ bottom."""
+    for a in range(32):
+        for b in range(32):
+            z = ((a << 11) + (((32 - b) & 31) << 11)) & 0xFFFF
+            assert (z == 0) == (a == b)
+            assert a == b or z >= 2048
+    g = workloads.rng(270)
+    s = g.integers(0, 2048, 5000)
+    t = g.integers(0, 2048, 5000)
+    match = g.random(5000) < 0.3
+    for sv, tv, mv in zip(s, t, match):
+        z = 0 if mv else 0xF800
+        bottom = max(sv, min(tv, z))
+        right = sv ^ tv ^ bottom
+        if mv:
+            assert (bottom, right) == (sv, tv)
+        else:
+            assert (bottom, right) == (max(sv, tv), min(sv, tv))
