@@ -1,0 +1,183 @@
+"""Benchmark: alignment plot throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dna-50k-w64]
+
+A step is one pass of the whole hot path over the workload: the windowed
+seaweed plot (every strip combed, counted, stored, with the thresholded dot-plot
+bitmap) of a device-resident, encoded pair.  The default workload is the DNA
+pair of 50,000 x 50,000 letters with w = 64 and 20 planted homologies, bitmap at
+WLCS >= 48.  Prints one JSON line on stdout; progress goes to stderr.
+
+Beside the headline number it measures, in the same run: the plain per-window
+dynamic program on the same GPU (the paper's O(m n w^2) baseline), the CPU
+oracle on a bounded sample of rows on the host cores, and the kernel's
+roofline position.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# HIP events over the timed region; per-cell operation count of the method
+# (equality test, min, max and the two-way exchange of the seaweed cell)
+OPS_PER_CELL = 5
+# MI355X: 256 CUs x 64 lanes x 2 packed 16-bit elements x 2.4 GHz
+PEAK_U16_OPS = 256 * 64 * 2 * 2.4e9
+METRIC = "window-cells/s (m*n*w/s) vs plain DP on same GPU; p50/p99 job latency"
+
+WORKLOADS = {"dna-50k-w64": 2, "dna-1k-w16": 1, "protein-30k-w128": 3}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="dna-50k-w64", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-dp", action="store_true", help="skip the GPU DP baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU sample time")
+    ap.add_argument("--tile", type=int, default=0, help="override the seaweed tile (windows)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_0909_2000_amd as wl
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    p = workloads.config(WORKLOADS[args.workload])
+    m, n, w = p.m, p.n, p.w
+    rows, cols = m - w, n - w
+    log(f"workload {p.name}: m={m} n={n} w={w} -> {rows}x{cols} plot")
+
+    ctx = wl.Context(0)
+    if args.tile:
+        ctx.set_tile(1, 255, args.tile)
+    stream = torch.cuda.current_stream(dev)
+    t0 = time.perf_counter()
+    pair = ctx.pair(p.x, p.y, alphabet=p.alphabet)
+    torch.cuda.synchronize()
+    encode_ms = (time.perf_counter() - t0) * 1e3
+    out = torch.empty((rows, cols), dtype=torch.uint8, device=dev)
+    thr = p.threshold
+    bm = torch.empty((rows, (cols + 63) // 64), dtype=torch.int64, device=dev) if thr else None
+
+    def step():
+        pair.plot(w, threshold=thr, out=out, bitmap_out=bm, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    # timed region: K steps, HIP events on the launch stream around each one
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in evs]
+    ms_per_step = wall * 1e3 / args.steps
+    nominal = float(m) * n * w
+    value = nominal / (ms_per_step / 1e3)
+    log(f"seaweed: {ms_per_step:.3f} ms/step, {value:.3e} window-cells/s")
+
+    avg_kernel_ms = float(np.mean(kern_ms))
+    cells = float(rows) * n * w  # cells the method combs: m-w strips of w x n
+    achieved = cells * OPS_PER_CELL / (avg_kernel_ms / 1e3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_U16_OPS / 1e12,
+                "unit": "TOP/s", "frac": achieved / PEAK_U16_OPS, "traffic": None,
+                "ops_per_cell": OPS_PER_CELL, "cells_per_launch": cells,
+                "avg_launch_ms": avg_kernel_ms}
+
+    # parity spot check of the timed output (whole rows against the oracle)
+    import oracle
+    sample_rows = np.array([0, rows // 3, rows - 1])
+    want = oracle.wlcs_rows(p.x, p.y, w, sample_rows)
+    got = out[torch.as_tensor(sample_rows, device=dev)].cpu().numpy()
+    parity = bool(np.array_equal(got, want))
+    log(f"parity on {len(sample_rows)} sampled rows: {parity}")
+
+    dp = None
+    if not args.no_dp:
+        # plain per-window DP on the same GPU, the same plot (one untimed run
+        # on a slice first, then one timed full run)
+        small = ctx.pair(p.x[: 64 + w], p.y, alphabet=p.alphabet)
+        small.plot_dp(w, out=out[:64])
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        pair.plot_dp(w, threshold=thr, out=out, bitmap_out=bm, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        dp_ms = a.elapsed_time(b)
+        dp_ok = bool(np.array_equal(out[torch.as_tensor(sample_rows, device=dev)].cpu().numpy(), want))
+        dp = {"value": nominal / (dp_ms / 1e3), "unit": "window-cells/s", "ms": dp_ms,
+              "speedup_seaweed_over_dp": dp_ms / ms_per_step, "parity": dp_ok}
+        log(f"GPU DP: {dp_ms:.1f} ms, seaweed speedup {dp_ms / ms_per_step:.1f}x")
+
+    cpu = None
+    if not args.no_cpu:
+        # the oracle as it stands, on whole rows of the same plot, sized to
+        # about cpu-seconds of host time
+        threads = oracle.default_threads()
+        t0 = time.perf_counter()
+        oracle.wlcs_rows(p.x, p.y, w, [rows // 2], nthreads=1)
+        one_row = time.perf_counter() - t0
+        nrows = max(threads, int(args.cpu_seconds * threads / max(one_row, 1e-3)))
+        nrows = min(nrows, rows)
+        ids = np.linspace(0, rows - 1, nrows).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.wlcs_rows(p.x, p.y, w, ids, nthreads=threads)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": nrows * float(n) * w / cpu_s, "unit": "window-cells/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{nrows} of {rows} plot rows (x-windows spread evenly), each against all "
+                         f"{cols} y-windows, plain per-window DP, {cpu_s:.1f} s"}
+        log(f"CPU oracle: {cpu['value']:.3e} window-cells/s on {threads} threads")
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "window-cells/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16",
+        "data": "synthetic",
+        "config": {"workload": p.name, "m": m, "n": n, "w": w, "rows": rows, "cols": cols,
+                   "threshold": thr, "outputs": "uint8 plot + bitmap" if thr else "uint8 plot",
+                   "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "gpu_dp_baseline": dp,
+        "encode_ms": encode_ms, "parity_sampled_rows": parity,
+        "kernel_ms": {"min": float(np.min(kern_ms)), "median": float(np.median(kern_ms)),
+                      "max": float(np.max(kern_ms))},
+    }
+    print(json.dumps(rec), flush=True)
+    pair.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,145 @@
+/*
+ * wlcs.h - C ABI of the MI355X (gfx950) alignment-plot library.
+ *
+ * An alignment plot (Krusche & Tiskin, "Computing alignment plots
+ * efficiently", Section 2) of strings x (length m) and y (length n) for window
+ * length w is the matrix WLCS(i, j), the length of a longest common
+ * subsequence of the w-windows x_i..x_{i+w-1} and y_j..y_{j+w-1}, for
+ * i in 1..m-w and j in 1..n-w.  This library computes it on the GPU in
+ * O(m n w) work by the windowed seaweed algorithm (Theorem 3.1: one strip of
+ * height w per x-window, combed column by column, with a sliding count of the
+ * seaweeds that start and end inside each y-window), and also offers the
+ * plain per-window dynamic program (O(m n w^2), the paper's baseline) on the
+ * same device for comparison.
+ *
+ * Conventions shared by every entry point:
+ *   - Output layout: row-major, 0-based.  Row i (0 <= i < rows) is the x-window
+ *     starting at x[i], column j (0 <= j < cols) the y-window starting at y[j].
+ *     rows = m - w and cols = n - w (the paper's ranges 1..m-w, 1..n-w); with
+ *     WLCS_FULL_RANGE, rows = m - w + 1 and cols = n - w + 1 (every window).
+ *     If rows <= 0 or cols <= 0 the plot is empty and the call succeeds
+ *     without touching any output.
+ *   - Letters are bytes.  alphabet lists sigma distinct bytes (1 <= sigma <=
+ *     WLCS_MAX_SIGMA); two letters match iff they are the same byte.  A byte of
+ *     x or y outside the alphabet is an error (no wildcard semantics).
+ *   - Strings x and y are caller-owned HOST buffers; the call reads them before
+ *     it returns.  Outputs are caller-owned DEVICE buffers on the context's
+ *     device, written asynchronously on `stream` (a hipStream_t, or NULL for
+ *     the default stream).  Results are valid once the stream reaches the point
+ *     of the call; the library keeps no reference to caller memory after that.
+ *   - Every function returns WLCS_OK (0) or a negative status.  Argument
+ *     errors are reported before anything is enqueued; nothing throws across
+ *     the ABI and the library never aborts the process.
+ *   - A context belongs to one device and must not be used from two threads
+ *     at once without external locking.
+ */
+#ifndef WLCS_H
+#define WLCS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WLCS_OK 0
+#define WLCS_EINVAL (-1)    /* null pointer where one is needed, ld too small, bad flags */
+#define WLCS_ERANGE (-2)    /* w outside 1..WLCS_MAX_W, negative or oversized lengths */
+#define WLCS_EALPHABET (-3) /* bad alphabet, or a string byte outside it */
+#define WLCS_EHIP (-4)      /* HIP runtime or launch failure (wlcs_ctx_last_hip_error) */
+#define WLCS_ENOMEM (-5)    /* host or device allocation failed */
+
+#define WLCS_MAX_W 255         /* WLCS values must fit the uint8 output */
+#define WLCS_MAX_SIGMA 64      /* letters per alphabet */
+#define WLCS_MAX_LEN 100000000 /* longest string accepted (bytes) */
+
+/* flags */
+#define WLCS_FULL_RANGE 1u /* every window: (m-w+1) x (n-w+1) instead of (m-w) x (n-w) */
+
+typedef struct wlcs_ctx wlcs_ctx;
+
+/* Create a context on HIP device `device` (ordinal).  *out receives the handle.
+ * The context owns device scratch, pinned staging buffers and tuning. */
+int wlcs_ctx_create(int device, wlcs_ctx **out);
+
+/* Wait for the context's outstanding staging copies and free everything it
+ * owns.  NULL is accepted. */
+int wlcs_ctx_destroy(wlcs_ctx *ctx);
+
+/* Last HIP error code (hipError_t as int) seen by the context, 0 if none. */
+int wlcs_ctx_last_hip_error(const wlcs_ctx *ctx);
+
+/* Human-readable text for a status code (static storage). */
+const char *wlcs_status_str(int status);
+
+/* Seaweed tiling knobs (the tuner sets these; 0 restores the built-in choice).
+ * tile_windows: y-windows each lane covers per tile; a multiple of 64 in
+ * 64..32768.  Every x-window is combed afresh from the first column of each
+ * tile, so a tile of T windows combs T + w - 1 columns (Theorem 3.1 applied to
+ * the strip restricted to those columns).  Applies to windows w with
+ * w_lo <= w <= w_hi. */
+int wlcs_ctx_set_tile(wlcs_ctx *ctx, int32_t w_lo, int32_t w_hi, int32_t tile_windows);
+
+/* Alignment plot by the windowed seaweed algorithm (Theorem 3.1, with the
+ * combing rule of Section 2 and the bit bounds of Propositions 3.3-3.4).
+ *
+ *   x, m, y, n, w     host strings and window length (1 <= w <= WLCS_MAX_W).
+ *   alphabet, sigma   the letters (see conventions).
+ *   wlcs, ld          uint8 output, rows x cols, row stride ld >= cols
+ *                     (elements).  May be NULL if only the epilogues are wanted.
+ *   bitmap, ld_words  thresholded dot plot (Section 1: a dot marks a window
+ *                     pair whose similarity clears a threshold): bit j%64 of
+ *                     word j/64 of row i is set iff WLCS(i, j) >= threshold;
+ *                     ceil(cols/64) uint64 words per row, padding bits written
+ *                     as 0, row stride ld_words >= ceil(cols/64).  NULL skips.
+ *   indel, ld_indel   uint16 indel distance 2w - 2*WLCS(i, j) (LCS alignment
+ *                     with gap score 0, Section 2), row stride ld_indel >= cols.
+ *                     NULL skips.
+ *   flags             0 or WLCS_FULL_RANGE.
+ *   stream            hipStream_t the work is enqueued on.
+ * At least one of wlcs, bitmap, indel must be non-NULL (unless the plot is
+ * empty).  threshold is used only with a bitmap and must be in 0..255. */
+int wlcs_plot(wlcs_ctx *ctx, const uint8_t *x, int64_t m, const uint8_t *y, int64_t n,
+              int32_t w, const uint8_t *alphabet, int32_t sigma, uint8_t *wlcs, int64_t ld,
+              uint64_t *bitmap, int64_t ld_words, int32_t threshold, uint16_t *indel,
+              int64_t ld_indel, uint32_t flags, void *stream);
+
+/* The same plot by the plain per-window dynamic program of Section 2 (every
+ * window pair solved independently, O(w^2) each): the paper's baseline, run
+ * on the GPU for comparison.  Same arguments, outputs and errors. */
+int wlcs_plot_dp(wlcs_ctx *ctx, const uint8_t *x, int64_t m, const uint8_t *y, int64_t n,
+                 int32_t w, const uint8_t *alphabet, int32_t sigma, uint8_t *wlcs, int64_t ld,
+                 uint64_t *bitmap, int64_t ld_words, int32_t threshold, uint16_t *indel,
+                 int64_t ld_indel, uint32_t flags, void *stream);
+
+/* ---- device-resident pairs --------------------------------------------
+ * A pair holds x and y on the device, already mapped to letter codes, so that
+ * repeated plots (several windows, benchmarking, a serving loop) start from
+ * inputs resident in HBM.  The pair owns its device memory (allocated with
+ * hipMalloc on the context's device) until wlcs_pair_destroy. */
+typedef struct wlcs_pair wlcs_pair;
+
+/* Copy host strings x (m bytes) and y (n bytes) to the device and encode them
+ * (letters checked against the alphabet on the host first, as in wlcs_plot).
+ * The encoding runs on `stream`; the host strings may be reused on return. */
+int wlcs_pair_create(wlcs_ctx *ctx, const uint8_t *x, int64_t m, const uint8_t *y, int64_t n,
+                     const uint8_t *alphabet, int32_t sigma, void *stream, wlcs_pair **out);
+
+/* Free a pair's device memory (waits for the device to finish using it).
+ * NULL is accepted. */
+int wlcs_pair_destroy(wlcs_pair *pair);
+
+/* wlcs_plot / wlcs_plot_dp on a resident pair: same window, output, flag and
+ * error conventions; the pair must belong to ctx's device. */
+int wlcs_pair_plot(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, uint8_t *wlcs, int64_t ld,
+                   uint64_t *bitmap, int64_t ld_words, int32_t threshold, uint16_t *indel,
+                   int64_t ld_indel, uint32_t flags, void *stream);
+int wlcs_pair_plot_dp(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, uint8_t *wlcs, int64_t ld,
+                      uint64_t *bitmap, int64_t ld_words, int32_t threshold, uint16_t *indel,
+                      int64_t ld_indel, uint32_t flags, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WLCS_H */

@@ -68,6 +68,15 @@ def _bytes(s) -> np.ndarray:
     return a
 
 
+def default_threads() -> int:
+    """Host threads for the oracle: the CPUs this process may run on, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def _p(a: np.ndarray, t=ctypes.c_uint8):
     return a.ctypes.data_as(ctypes.POINTER(t))
 
@@ -93,7 +102,7 @@ def wlcs(x, y, w: int, full_range: bool = False, nthreads: int | None = None) ->
     rows, cols = n_windows(x.size, w, full_range), n_windows(y.size, w, full_range)
     out = np.zeros((rows, cols), dtype=np.uint8)
     if rows and cols:
-        nt = nthreads or os.cpu_count() or 1
+        nt = nthreads or default_threads()
         r = _load().oracle_wlcs(_p(x), x.size, _p(y), y.size, w, int(full_range), _p(out),
                                 cols, nt)
         if r != 0:
@@ -109,7 +118,7 @@ def wlcs_rows(x, y, w: int, rows, full_range: bool = False,
     cols = n_windows(y.size, w, full_range)
     out = np.zeros((ids.size, cols), dtype=np.uint8)
     if ids.size and cols:
-        nt = nthreads or os.cpu_count() or 1
+        nt = nthreads or default_threads()
         r = _load().oracle_wlcs_rows(_p(x), x.size, _p(y), y.size, w, int(full_range),
                                      _p(ids, ctypes.c_int64), ids.size, _p(out), cols, nt)
         if r != 0:

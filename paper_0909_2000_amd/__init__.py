@@ -1,0 +1,291 @@
+"""Alignment plots on MI355X (gfx950): Python binding of libwlcs.so.
+
+The library (C ABI in ``include/wlcs.h``) computes the alignment plot of
+Krusche & Tiskin ("Computing alignment plots efficiently"): WLCS(i, j), the LLCS
+of every pair of w-windows of x and y, by the windowed seaweed algorithm of
+Theorem 3.1 in hand-written HIP kernels.  This module only marshals arguments:
+PyTorch provides the device memory and the stream; every step of the computation
+runs in the library's kernels.  There is no CPU fallback: if the library is not
+built, importing works but every call raises ``WlcsUnavailable``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loaded before libwlcs.so so that both share one HIP runtime
+
+__all__ = ["Context", "Pair", "WlcsError", "WlcsUnavailable", "plot", "plot_dp", "n_windows",
+           "library_path", "exported_symbols", "DNA", "PROTEIN"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwlcs.so")
+
+DNA = b"ACGT"
+PROTEIN = b"ACDEFGHIKLMNPQRSTVWY"
+
+WLCS_FULL_RANGE = 1
+_STATUS = {0: "ok", -1: "invalid argument", -2: "window or length out of range",
+           -3: "bad alphabet or letter outside the alphabet", -4: "HIP runtime error",
+           -5: "out of memory"}
+
+
+class WlcsUnavailable(RuntimeError):
+    """libwlcs.so is not built or cannot be loaded."""
+
+
+class WlcsError(RuntimeError):
+    def __init__(self, status: int, where: str, hip_error: int = 0):
+        self.status = status
+        self.hip_error = hip_error
+        msg = f"{where}: {_STATUS.get(status, 'unknown status')} ({status})"
+        if hip_error:
+            msg += f", hip error {hip_error}"
+        super().__init__(msg)
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise WlcsUnavailable(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "or python -m paper_0909_2000_amd.build")
+    try:
+        lib = ctypes.CDLL(LIB_PATH)
+    except OSError as e:
+        raise WlcsUnavailable(f"cannot load {LIB_PATH}: {e}") from e
+    vp, u8p = ctypes.c_void_p, ctypes.c_void_p
+    i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    lib.wlcs_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    lib.wlcs_ctx_destroy.argtypes = [vp]
+    lib.wlcs_ctx_last_hip_error.argtypes = [vp]
+    lib.wlcs_status_str.argtypes = [ctypes.c_int]
+    lib.wlcs_status_str.restype = ctypes.c_char_p
+    lib.wlcs_ctx_set_tile.argtypes = [vp, i32, i32, i32]
+    plot_args = [vp, u8p, i64, u8p, i64, i32, u8p, i32, vp, i64, vp, i64, i32, vp, i64, u32, vp]
+    lib.wlcs_plot.argtypes = plot_args
+    lib.wlcs_plot_dp.argtypes = plot_args
+    lib.wlcs_pair_create.argtypes = [vp, u8p, i64, u8p, i64, u8p, i32, vp, ctypes.POINTER(vp)]
+    lib.wlcs_pair_destroy.argtypes = [vp]
+    pair_args = [vp, vp, i32, vp, i64, vp, i64, i32, vp, i64, u32, vp]
+    lib.wlcs_pair_plot.argtypes = pair_args
+    lib.wlcs_pair_plot_dp.argtypes = pair_args
+    for f in ("wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_ctx_set_tile",
+              "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot",
+              "wlcs_pair_plot_dp"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> list:
+    """Names of the C ABI entry points the binding uses."""
+    return ["wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_status_str",
+            "wlcs_ctx_set_tile", "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy",
+            "wlcs_pair_plot", "wlcs_pair_plot_dp"]
+
+
+def n_windows(length: int, w: int, full_range: bool = False) -> int:
+    return max(length - w + (1 if full_range else 0), 0)
+
+
+def _as_bytes(s) -> np.ndarray:
+    if isinstance(s, str):
+        s = s.encode("ascii")
+    if isinstance(s, (bytes, bytearray, memoryview)):
+        return np.frombuffer(bytes(s), dtype=np.uint8)
+    if isinstance(s, torch.Tensor):
+        s = s.cpu().numpy()
+    return np.ascontiguousarray(s, dtype=np.uint8)
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)
+
+
+class Context:
+    """One library context on one device (default: the current torch device)."""
+
+    def __init__(self, device: int | None = None):
+        lib = _load()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        st = lib.wlcs_ctx_create(self.device, ctypes.byref(h))
+        if st != 0:
+            raise WlcsError(st, "wlcs_ctx_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _load().wlcs_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tile(self, w_lo: int, w_hi: int, tile: int):
+        st = _load().wlcs_ctx_set_tile(self._h, w_lo, w_hi, tile)
+        if st != 0:
+            raise WlcsError(st, "wlcs_ctx_set_tile")
+
+    def _outputs(self, rows, cols, threshold, indel, out, bitmap_out, indel_out, want_plot):
+        dev = torch.device("cuda", self.device)
+        if out is None and want_plot:
+            out = torch.empty((rows, cols), dtype=torch.uint8, device=dev)
+        words = (cols + 63) // 64
+        if threshold is not None and bitmap_out is None:
+            bitmap_out = torch.empty((rows, words), dtype=torch.int64, device=dev)
+        if indel and indel_out is None:
+            indel_out = torch.empty((rows, cols), dtype=torch.int16, device=dev)
+        for t in (out, bitmap_out, indel_out):
+            if t is not None and (t.device != dev or t.dim() != 2 or t.stride(1) != 1):
+                raise ValueError("outputs must be 2-D row-major tensors on the context's device")
+        return out, bitmap_out, indel_out
+
+    @staticmethod
+    def _out_args(out, bitmap_out, indel_out, threshold):
+        return (ctypes.c_void_p(out.data_ptr()) if out is not None else None,
+                out.stride(0) if out is not None else 0,
+                ctypes.c_void_p(bitmap_out.data_ptr()) if bitmap_out is not None else None,
+                bitmap_out.stride(0) if bitmap_out is not None else 0,
+                int(threshold) if threshold is not None else 0,
+                ctypes.c_void_p(indel_out.data_ptr()) if indel_out is not None else None,
+                indel_out.stride(0) if indel_out is not None else 0)
+
+    @staticmethod
+    def _result(out, bitmap_out, indel_out):
+        res = {"wlcs": out}
+        if bitmap_out is not None:
+            res["bitmap"] = bitmap_out
+        if indel_out is not None:
+            res["indel"] = indel_out
+        return res
+
+    def _stream(self, stream):
+        return stream if stream is not None else torch.cuda.current_stream(torch.device("cuda", self.device))
+
+    def _call(self, fn: str, x, y, w: int, alphabet, threshold, indel: bool, full_range: bool,
+              out, bitmap_out, indel_out, want_plot: bool, stream):
+        lib = _load()
+        xa, ya = _as_bytes(x), _as_bytes(y)
+        alpha = _as_bytes(alphabet)
+        rows, cols = n_windows(xa.size, w, full_range), n_windows(ya.size, w, full_range)
+        out, bitmap_out, indel_out = self._outputs(rows, cols, threshold, indel, out, bitmap_out,
+                                                   indel_out, want_plot)
+        stream = self._stream(stream)
+        flags = WLCS_FULL_RANGE if full_range else 0
+        st = getattr(lib, fn)(self._h, _ptr(xa), xa.size, _ptr(ya), ya.size, int(w), _ptr(alpha),
+                              alpha.size, *self._out_args(out, bitmap_out, indel_out, threshold),
+                              flags, ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise WlcsError(st, fn, lib.wlcs_ctx_last_hip_error(self._h))
+        return self._result(out, bitmap_out, indel_out)
+
+    def pair(self, x, y, alphabet=DNA, stream=None) -> "Pair":
+        """Upload and encode x and y once; plot them any number of times."""
+        return Pair(self, x, y, alphabet, stream)
+
+    def plot(self, x, y, w: int, alphabet=DNA, threshold: int | None = None, indel: bool = False,
+             full_range: bool = False, out=None, bitmap_out=None, indel_out=None,
+             want_plot: bool = True, stream=None) -> dict:
+        """Alignment plot by the seaweed kernels.  Returns a dict with 'wlcs'
+        (uint8 rows x cols), and 'bitmap' (int64 words holding the uint64 bit
+        rows) and 'indel' (int16 holding uint16 2w-2*WLCS) when asked for."""
+        return self._call("wlcs_plot", x, y, w, alphabet, threshold, indel, full_range, out,
+                          bitmap_out, indel_out, want_plot, stream)
+
+    def plot_dp(self, x, y, w: int, alphabet=DNA, threshold: int | None = None, indel: bool = False,
+                full_range: bool = False, out=None, bitmap_out=None, indel_out=None,
+                want_plot: bool = True, stream=None) -> dict:
+        """The same plot by the plain per-window dynamic program on the GPU."""
+        return self._call("wlcs_plot_dp", x, y, w, alphabet, threshold, indel, full_range, out,
+                          bitmap_out, indel_out, want_plot, stream)
+
+
+class Pair:
+    """x and y resident on the device as letter codes (wlcs_pair)."""
+
+    def __init__(self, ctx: Context, x, y, alphabet=DNA, stream=None):
+        lib = _load()
+        xa, ya, alpha = _as_bytes(x), _as_bytes(y), _as_bytes(alphabet)
+        self.ctx, self.m, self.n = ctx, int(xa.size), int(ya.size)
+        h = ctypes.c_void_p()
+        st = lib.wlcs_pair_create(ctx.handle, _ptr(xa), xa.size, _ptr(ya), ya.size, _ptr(alpha),
+                                  alpha.size, ctypes.c_void_p(ctx._stream(stream).cuda_stream),
+                                  ctypes.byref(h))
+        if st != 0:
+            raise WlcsError(st, "wlcs_pair_create", lib.wlcs_ctx_last_hip_error(ctx.handle))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _load().wlcs_pair_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _run(self, fn, w, threshold, indel, full_range, out, bitmap_out, indel_out, want_plot,
+             stream):
+        lib = _load()
+        rows, cols = n_windows(self.m, w, full_range), n_windows(self.n, w, full_range)
+        c = self.ctx
+        out, bitmap_out, indel_out = c._outputs(rows, cols, threshold, indel, out, bitmap_out,
+                                                indel_out, want_plot)
+        stream = c._stream(stream)
+        st = getattr(lib, fn)(c.handle, self._h, int(w),
+                              *c._out_args(out, bitmap_out, indel_out, threshold),
+                              WLCS_FULL_RANGE if full_range else 0,
+                              ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise WlcsError(st, fn, lib.wlcs_ctx_last_hip_error(c.handle))
+        return c._result(out, bitmap_out, indel_out)
+
+    def plot(self, w, threshold=None, indel=False, full_range=False, out=None, bitmap_out=None,
+             indel_out=None, want_plot=True, stream=None) -> dict:
+        return self._run("wlcs_pair_plot", w, threshold, indel, full_range, out, bitmap_out,
+                         indel_out, want_plot, stream)
+
+    def plot_dp(self, w, threshold=None, indel=False, full_range=False, out=None, bitmap_out=None,
+                indel_out=None, want_plot=True, stream=None) -> dict:
+        return self._run("wlcs_pair_plot_dp", w, threshold, indel, full_range, out, bitmap_out,
+                         indel_out, want_plot, stream)
+
+
+_default_ctx = {}
+
+
+def _ctx(device=None) -> Context:
+    d = torch.cuda.current_device() if device is None else int(device)
+    if d not in _default_ctx:
+        _default_ctx[d] = Context(d)
+    return _default_ctx[d]
+
+
+def plot(x, y, w: int, alphabet=DNA, threshold=None, indel=False, full_range=False, **kw) -> dict:
+    return _ctx(kw.pop("device", None)).plot(x, y, w, alphabet, threshold, indel, full_range, **kw)
+
+
+def plot_dp(x, y, w: int, alphabet=DNA, threshold=None, indel=False, full_range=False, **kw) -> dict:
+    return _ctx(kw.pop("device", None)).plot_dp(x, y, w, alphabet, threshold, indel, full_range, **kw)

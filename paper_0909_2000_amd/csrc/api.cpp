@@ -1,0 +1,454 @@
+// Host runtime of the alignment-plot library: the C ABI declared in
+// include/wlcs.h.  Validates arguments before anything is enqueued, stages the
+// host strings through pinned buffers, and enqueues the encoding kernel and the
+// plot kernels on the caller's stream.  Per-call device scratch is taken with
+// stream-ordered allocation, so calls on different streams never share it.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "../../include/wlcs.h"
+#include "kernels.hpp"
+
+namespace {
+
+constexpr int kSlots = 4;  // pinned staging buffers per context
+
+struct Slot {
+    uint8_t* buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+struct TileRule {
+    int32_t lo, hi, tile;
+};
+
+}  // namespace
+
+struct wlcs_ctx {
+    int device = 0;
+    int cus = 256;
+    int last_hip = 0;
+    Slot slots[kSlots];
+    int next_slot = 0;
+    TileRule rules[16];
+    int nrules = 0;
+};
+
+namespace {
+
+// Switch to the context's device for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int fail(wlcs_ctx* ctx, hipError_t e) {
+    if (ctx) ctx->last_hip = (int)e;
+    return e == hipErrorOutOfMemory ? WLCS_ENOMEM : WLCS_EHIP;
+}
+
+int64_t n_windows(int64_t len, int32_t w, bool full) {
+    const int64_t k = len - w + (full ? 1 : 0);
+    return k > 0 ? k : 0;
+}
+
+int waves_per_cu(int wc) { return wc <= 64 ? 16 : wc == 128 ? 8 : 4; }
+
+// Tile length for the seaweed kernel: among multiples of 64, take the one that
+// minimises (rounds of resident waves) x (columns each wave combs), the larger
+// tile on ties.  A context rule set by wlcs_ctx_set_tile overrides it.
+int32_t choose_tile(const wlcs_ctx* ctx, int64_t rows, int64_t cols, int32_t w) {
+    for (int r = ctx->nrules - 1; r >= 0; --r)
+        if (w >= ctx->rules[r].lo && w <= ctx->rules[r].hi) return ctx->rules[r].tile;
+    const int64_t nblocks = (rows + 63) / 64;
+    const int64_t slots = (int64_t)ctx->cus * waves_per_cu(wlcs::w_class(w));
+    const int64_t cap = std::max<int64_t>(64, (cols + 63) / 64 * 64);
+    int32_t best = 64;
+    double best_cost = 1e300;
+    for (int32_t t = 64; t <= 16384; t *= 2) {
+        if (t > cap && t > 64) break;
+        const int64_t ntiles = (cols + t - 1) / t;
+        const int64_t units = nblocks * ((ntiles + 1) / 2);
+        const int64_t rounds = (units + slots - 1) / slots;
+        const double cost = (double)rounds * (double)(t + w - 1);
+        if (cost <= best_cost) {
+            best_cost = cost;
+            best = t;
+        }
+    }
+    return best;
+}
+
+struct Prepared {
+    int64_t rows = 0, cols = 0;
+    uint8_t* raw = nullptr;  // device: x bytes then y bytes
+    uint16_t* xf = nullptr;
+    uint16_t* yg = nullptr;
+};
+
+int validate(const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, int32_t w, const uint8_t* alphabet,
+             int32_t sigma, uint8_t map[256]) {
+    if (w < 1 || w > WLCS_MAX_W) return WLCS_ERANGE;
+    if (m < 0 || n < 0 || m > WLCS_MAX_LEN || n > WLCS_MAX_LEN) return WLCS_ERANGE;
+    if (!alphabet || sigma < 1 || sigma > WLCS_MAX_SIGMA) return WLCS_EALPHABET;
+    memset(map, 0xFF, 256);
+    for (int c = 0; c < sigma; ++c) {
+        if (map[alphabet[c]] != 0xFF) return WLCS_EALPHABET;  // repeated letter
+        map[alphabet[c]] = (uint8_t)c;
+    }
+    if ((m > 0 && !x) || (n > 0 && !y)) return WLCS_EINVAL;
+    for (int64_t i = 0; i < m; ++i)
+        if (map[x[i]] == 0xFF) return WLCS_EALPHABET;
+    for (int64_t i = 0; i < n; ++i)
+        if (map[y[i]] == 0xFF) return WLCS_EALPHABET;
+    return WLCS_OK;
+}
+
+// Copy x and y into a pinned slot, then to device memory, and encode them into
+// the padded code arrays the kernels read.
+int upload(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, const uint8_t map[256],
+           int64_t xf_len, int64_t yg_len, hipStream_t stream, Prepared& p) {
+    const size_t need = (size_t)(m + n);
+    if (need == 0) return WLCS_OK;
+    Slot& sl = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
+    hipError_t e;
+    if (sl.pending) {
+        if ((e = hipEventSynchronize(sl.done)) != hipSuccess) return fail(ctx, e);
+        sl.pending = false;
+    }
+    if (sl.cap < need) {
+        if (sl.buf) (void)hipHostFree(sl.buf);
+        sl.buf = nullptr;
+        sl.cap = 0;
+        if ((e = hipHostMalloc((void**)&sl.buf, std::max<size_t>(need, 1 << 16), hipHostMallocDefault)) !=
+            hipSuccess)
+            return fail(ctx, e);
+        sl.cap = std::max<size_t>(need, 1 << 16);
+    }
+    memcpy(sl.buf, x, (size_t)m);
+    memcpy(sl.buf + m, y, (size_t)n);
+    if ((e = hipMallocAsync((void**)&p.raw, need, stream)) != hipSuccess) return fail(ctx, e);
+    if (xf_len > 0 && (e = hipMallocAsync((void**)&p.xf, (size_t)xf_len * 2, stream)) != hipSuccess)
+        return fail(ctx, e);
+    if (yg_len > 0 && (e = hipMallocAsync((void**)&p.yg, (size_t)yg_len * 2, stream)) != hipSuccess)
+        return fail(ctx, e);
+    if ((e = hipMemcpyAsync(p.raw, sl.buf, need, hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return fail(ctx, e);
+    if ((e = hipEventRecord(sl.done, stream)) != hipSuccess) return fail(ctx, e);
+    sl.pending = true;
+    if (xf_len > 0 && (e = wlcs::launch_encode(p.raw, m, map, 1, p.xf, xf_len, stream)) != hipSuccess)
+        return fail(ctx, e);
+    if (yg_len > 0 && (e = wlcs::launch_encode(p.raw + m, n, map, 0, p.yg, yg_len, stream)) != hipSuccess)
+        return fail(ctx, e);
+    return WLCS_OK;
+}
+
+void release(Prepared& p, hipStream_t stream) {
+    if (p.raw) (void)hipFreeAsync(p.raw, stream);
+    if (p.xf) (void)hipFreeAsync(p.xf, stream);
+    if (p.yg) (void)hipFreeAsync(p.yg, stream);
+    p = Prepared();
+}
+
+enum class Path { Seaweed, Dp };
+
+// Code-array lengths (16-bit elements) the kernels read for a plot: x is read
+// up to 64 strips past the last block plus a window, y up to two tiles past
+// the last one (seaweed) or one 128-window chunk (DP), plus a window.
+void needed_lengths(Path path, int64_t rows, int64_t cols, int32_t w, int32_t tile, int64_t& xf_len,
+                    int64_t& yg_len) {
+    const int wc = wlcs::w_class(w);
+    xf_len = (rows + 63) / 64 * 64 + wc + 64;
+    if (path == Path::Seaweed) {
+        const int64_t ntiles = (cols + tile - 1) / tile;
+        const int64_t npairs = (ntiles + 1) / 2;
+        yg_len = 2 * npairs * tile + wc + 64;
+    } else {
+        yg_len = (cols + 127) / 128 * 128 + wc + 64;
+    }
+}
+
+// Host-side checks shared by every plot entry point (no device access).
+int check_outputs(int64_t rows, int64_t cols, uint8_t* out, int64_t ld, uint64_t* bitmap, int64_t ld_words,
+                  int32_t threshold, uint16_t* indel, int64_t ld_indel) {
+    if (rows > 0 && cols > 0) {
+        if (!out && !bitmap && !indel) return WLCS_EINVAL;
+        if (out && ld < cols) return WLCS_EINVAL;
+        if (bitmap && (ld_words < (cols + 63) / 64 || threshold < 0 || threshold > 255)) return WLCS_EINVAL;
+        if (indel && ld_indel < cols) return WLCS_EINVAL;
+    }
+    return WLCS_OK;
+}
+
+wlcs::PlotArgs make_args(int64_t rows, int64_t cols, int32_t w, uint8_t* out, int64_t ld, uint64_t* bitmap,
+                         int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel) {
+    wlcs::PlotArgs a{};
+    a.rows = rows;
+    a.cols = cols;
+    a.w = w;
+    a.threshold = threshold;
+    a.wlcs = out;
+    a.ld = ld;
+    a.bitmap32 = (uint32_t*)bitmap;
+    a.ld_words32 = ld_words * 2;
+    a.indel = indel;
+    a.ld_indel = ld_indel;
+    return a;
+}
+
+int plot_common(Path path, wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, int32_t w,
+                const uint8_t* alphabet, int32_t sigma, uint8_t* out, int64_t ld, uint64_t* bitmap,
+                int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel, uint32_t flags,
+                void* stream_) {
+    // every argument is checked on the host before the context is touched
+    if (flags & ~WLCS_FULL_RANGE) return WLCS_EINVAL;
+    uint8_t map[256];
+    int st = validate(x, m, y, n, w, alphabet, sigma, map);
+    if (st != WLCS_OK) return st;
+    const bool full = (flags & WLCS_FULL_RANGE) != 0;
+    const int64_t rows = n_windows(m, w, full), cols = n_windows(n, w, full);
+    st = check_outputs(rows, cols, out, ld, bitmap, ld_words, threshold, indel, ld_indel);
+    if (st != WLCS_OK) return st;
+    if (!ctx) return WLCS_EINVAL;
+    if (rows == 0 || cols == 0) return WLCS_OK;
+
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
+    hipStream_t stream = (hipStream_t)stream_;
+
+    wlcs::PlotArgs a = make_args(rows, cols, w, out, ld, bitmap, ld_words, threshold, indel, ld_indel);
+    a.tile = path == Path::Seaweed ? choose_tile(ctx, rows, cols, w) : 64;
+    a.npairs = (int32_t)(((cols + a.tile - 1) / a.tile + 1) / 2);
+    int64_t xf_len, yg_len;
+    needed_lengths(path, rows, cols, w, a.tile, xf_len, yg_len);
+    Prepared p;
+    st = upload(ctx, x, m, y, n, map, xf_len, yg_len, stream, p);
+    if (st != WLCS_OK) {
+        release(p, stream);
+        return st;
+    }
+    a.xf = p.xf;
+    a.yg = p.yg;
+    hipError_t e = path == Path::Seaweed ? wlcs::launch_seaweed(a, stream) : wlcs::launch_dp(a, stream);
+    release(p, stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    return WLCS_OK;
+}
+
+}  // namespace
+
+// A device-resident, encoded pair of strings.
+struct wlcs_pair {
+    int device = 0;
+    int64_t m = 0, n = 0;
+    uint16_t* xf = nullptr;  // capacity xf_cap
+    uint16_t* yg = nullptr;  // capacity yg_cap
+    int64_t xf_cap = 0, yg_cap = 0;
+};
+
+namespace {
+
+constexpr int32_t kMaxTile = 32768;
+
+int pair_plot_common(Path path, wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, uint8_t* out, int64_t ld,
+                     uint64_t* bitmap, int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel,
+                     uint32_t flags, void* stream_) {
+    if (flags & ~WLCS_FULL_RANGE) return WLCS_EINVAL;
+    if (!pair) return WLCS_EINVAL;
+    if (w < 1 || w > WLCS_MAX_W) return WLCS_ERANGE;
+    const bool full = (flags & WLCS_FULL_RANGE) != 0;
+    const int64_t rows = n_windows(pair->m, w, full), cols = n_windows(pair->n, w, full);
+    int st = check_outputs(rows, cols, out, ld, bitmap, ld_words, threshold, indel, ld_indel);
+    if (st != WLCS_OK) return st;
+    if (!ctx || ctx->device != pair->device) return WLCS_EINVAL;
+    if (rows == 0 || cols == 0) return WLCS_OK;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
+    wlcs::PlotArgs a = make_args(rows, cols, w, out, ld, bitmap, ld_words, threshold, indel, ld_indel);
+    a.tile = path == Path::Seaweed ? choose_tile(ctx, rows, cols, w) : 64;
+    a.npairs = (int32_t)(((cols + a.tile - 1) / a.tile + 1) / 2);
+    int64_t xf_len, yg_len;
+    needed_lengths(path, rows, cols, w, a.tile, xf_len, yg_len);
+    if (xf_len > pair->xf_cap || yg_len > pair->yg_cap) return WLCS_EINVAL;  // cannot happen for valid tiles
+    a.xf = pair->xf;
+    a.yg = pair->yg;
+    hipStream_t stream = (hipStream_t)stream_;
+    hipError_t e = path == Path::Seaweed ? wlcs::launch_seaweed(a, stream) : wlcs::launch_dp(a, stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    return WLCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wlcs_ctx_create(int device, wlcs_ctx** out) {
+    if (!out) return WLCS_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return WLCS_EINVAL;
+    wlcs_ctx* ctx = new (std::nothrow) wlcs_ctx();
+    if (!ctx) return WLCS_ENOMEM;
+    ctx->device = device;
+    DeviceGuard guard(device);
+    if (!guard.ok) {
+        delete ctx;
+        return WLCS_EHIP;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        ctx->cus = cus;
+    for (int i = 0; i < kSlots; ++i) {
+        hipError_t e = hipEventCreateWithFlags(&ctx->slots[i].done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            ctx->last_hip = (int)e;
+            wlcs_ctx_destroy(ctx);
+            return WLCS_EHIP;
+        }
+    }
+    *out = ctx;
+    return WLCS_OK;
+}
+
+int wlcs_ctx_destroy(wlcs_ctx* ctx) {
+    if (!ctx) return WLCS_OK;
+    DeviceGuard guard(ctx->device);
+    int st = WLCS_OK;
+    for (int i = 0; i < kSlots; ++i) {
+        Slot& sl = ctx->slots[i];
+        if (sl.pending && hipEventSynchronize(sl.done) != hipSuccess) st = WLCS_EHIP;
+        if (sl.buf) (void)hipHostFree(sl.buf);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    delete ctx;
+    return st;
+}
+
+int wlcs_ctx_last_hip_error(const wlcs_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+
+const char* wlcs_status_str(int status) {
+    switch (status) {
+        case WLCS_OK: return "ok";
+        case WLCS_EINVAL: return "invalid argument";
+        case WLCS_ERANGE: return "window or length out of range";
+        case WLCS_EALPHABET: return "bad alphabet or letter outside the alphabet";
+        case WLCS_EHIP: return "HIP runtime error";
+        case WLCS_ENOMEM: return "out of memory";
+        default: return "unknown status";
+    }
+}
+
+int wlcs_ctx_set_tile(wlcs_ctx* ctx, int32_t w_lo, int32_t w_hi, int32_t tile_windows) {
+    if (!ctx || w_lo < 1 || w_hi < w_lo || w_hi > WLCS_MAX_W) return WLCS_EINVAL;
+    if (tile_windows == 0) {  // drop rules covering this range
+        int k = 0;
+        for (int r = 0; r < ctx->nrules; ++r)
+            if (!(ctx->rules[r].lo >= w_lo && ctx->rules[r].hi <= w_hi)) ctx->rules[k++] = ctx->rules[r];
+        ctx->nrules = k;
+        return WLCS_OK;
+    }
+    if (tile_windows < 64 || tile_windows > 32768 || tile_windows % 64) return WLCS_EINVAL;
+    if (ctx->nrules == 16) return WLCS_ENOMEM;
+    ctx->rules[ctx->nrules++] = TileRule{w_lo, w_hi, tile_windows};
+    return WLCS_OK;
+}
+
+int wlcs_plot(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, int32_t w,
+              const uint8_t* alphabet, int32_t sigma, uint8_t* wlcs, int64_t ld, uint64_t* bitmap,
+              int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel, uint32_t flags,
+              void* stream) {
+    return plot_common(Path::Seaweed, ctx, x, m, y, n, w, alphabet, sigma, wlcs, ld, bitmap, ld_words, threshold,
+                       indel, ld_indel, flags, stream);
+}
+
+int wlcs_plot_dp(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, int32_t w,
+                 const uint8_t* alphabet, int32_t sigma, uint8_t* wlcs, int64_t ld, uint64_t* bitmap,
+                 int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel, uint32_t flags,
+                 void* stream) {
+    return plot_common(Path::Dp, ctx, x, m, y, n, w, alphabet, sigma, wlcs, ld, bitmap, ld_words, threshold,
+                       indel, ld_indel, flags, stream);
+}
+
+int wlcs_pair_create(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n,
+                     const uint8_t* alphabet, int32_t sigma, void* stream_, wlcs_pair** out) {
+    if (!out) return WLCS_EINVAL;
+    *out = nullptr;
+    uint8_t map[256];
+    int st = validate(x, m, y, n, 1, alphabet, sigma, map);
+    if (st != WLCS_OK) return st;
+    if (!ctx) return WLCS_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
+    hipStream_t stream = (hipStream_t)stream_;
+    wlcs_pair* pr = new (std::nothrow) wlcs_pair();
+    if (!pr) return WLCS_ENOMEM;
+    pr->device = ctx->device;
+    pr->m = m;
+    pr->n = n;
+    // room for any window (<= 256 capacity) and any tile (<= kMaxTile)
+    pr->xf_cap = m + 64 + 256 + 64;
+    pr->yg_cap = n + 2 * (int64_t)kMaxTile + 128 + 256 + 64;
+    hipError_t e = hipMalloc((void**)&pr->xf, (size_t)pr->xf_cap * 2);
+    if (e == hipSuccess) e = hipMalloc((void**)&pr->yg, (size_t)pr->yg_cap * 2);
+    if (e != hipSuccess) {
+        wlcs_pair_destroy(pr);
+        return fail(ctx, e);
+    }
+    Prepared p;
+    st = upload(ctx, x, m, y, n, map, 0, 0, stream, p);  // raw bytes only
+    if (st == WLCS_OK) {
+        e = wlcs::launch_encode(p.raw, m, map, 1, pr->xf, pr->xf_cap, stream);
+        if (e == hipSuccess) e = wlcs::launch_encode(p.raw + m, n, map, 0, pr->yg, pr->yg_cap, stream);
+        if (e != hipSuccess) st = fail(ctx, e);
+    }
+    release(p, stream);
+    if (st != WLCS_OK) {
+        (void)hipStreamSynchronize(stream);
+        wlcs_pair_destroy(pr);
+        return st;
+    }
+    *out = pr;
+    return WLCS_OK;
+}
+
+int wlcs_pair_destroy(wlcs_pair* pair) {
+    if (!pair) return WLCS_OK;
+    DeviceGuard guard(pair->device);
+    int st = WLCS_OK;
+    if (pair->xf && hipFree(pair->xf) != hipSuccess) st = WLCS_EHIP;
+    if (pair->yg && hipFree(pair->yg) != hipSuccess) st = WLCS_EHIP;
+    delete pair;
+    return st;
+}
+
+int wlcs_pair_plot(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, uint8_t* wlcs, int64_t ld, uint64_t* bitmap,
+                   int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel, uint32_t flags,
+                   void* stream) {
+    return pair_plot_common(Path::Seaweed, ctx, pair, w, wlcs, ld, bitmap, ld_words, threshold, indel, ld_indel,
+                            flags, stream);
+}
+
+int wlcs_pair_plot_dp(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, uint8_t* wlcs, int64_t ld,
+                      uint64_t* bitmap, int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel,
+                      uint32_t flags, void* stream) {
+    return pair_plot_common(Path::Dp, ctx, pair, w, wlcs, ld, bitmap, ld_words, threshold, indel, ld_indel,
+                            flags, stream);
+}
+
+}  // extern "C"

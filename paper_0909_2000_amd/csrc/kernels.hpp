@@ -1,0 +1,74 @@
+// Internal interface between the host runtime and the gfx950 kernels.
+//
+// Letter codes.  Every letter of the alphabet gets a code c in [0, 64).  The
+// kernels never compare letters directly: x letters are stored as
+// f(c) = c << 10 and y letters as g(c) = ((64 - c) mod 64) << 10, so that the
+// 16-bit sum f(a) + g(b) is 0 when a == b and at least 1024 otherwise.  With
+// seaweed labels kept below 1024, one packed add gives a value Z that sits
+// below every label on a match and above every label on a mismatch, which
+// turns the seaweed cell into max/min operations (seaweed.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wlcs {
+
+constexpr int kCodeShift = 10;
+constexpr uint16_t f_code(uint32_t c) { return (uint16_t)(c << kCodeShift); }
+constexpr uint16_t g_code(uint32_t c) { return (uint16_t)(((64u - c) & 63u) << kCodeShift); }
+
+// Windows between two relabellings of the seaweed labels (a multiple of 32).
+constexpr int kRebase = 512;
+
+// One plot's worth of kernel arguments (host side).
+struct PlotArgs {
+    const uint16_t* xf;      // f-codes of x, padded (see host runtime)
+    const uint16_t* yg;      // g-codes of y, padded
+    int64_t rows;            // x-windows (strips)
+    int64_t cols;            // y-windows
+    int32_t w;
+    int32_t tile;            // y-windows per tile, multiple of 64
+    int32_t npairs;          // tile pairs per block of 64 strips
+    int32_t threshold;
+    uint8_t* wlcs;           // may be null
+    int64_t ld;
+    uint32_t* bitmap32;      // uint64 words addressed as little-endian u32 halves; may be null
+    int64_t ld_words32;      // row stride in u32 units (2 * ld_words)
+    uint16_t* indel;         // may be null
+    int64_t ld_indel;
+};
+
+// The pointer-free part, passed by value to the kernels (the pointers travel
+// as separate __restrict__ parameters so that uniform loads become scalar).
+struct Geom {
+    int64_t rows, cols, ld, ld_words32, ld_indel;
+    int32_t w, tile, npairs, threshold;
+    int32_t wmode;  // plot stores: 2 = 16-byte rows, 1 = 4-byte rows, 0 = bytes
+};
+
+inline Geom geom_of(const PlotArgs& a) {
+    Geom g;
+    g.rows = a.rows;
+    g.cols = a.cols;
+    g.ld = a.ld;
+    g.ld_words32 = a.ld_words32;
+    g.ld_indel = a.ld_indel;
+    g.w = a.w;
+    g.tile = a.tile;
+    g.npairs = a.npairs;
+    g.threshold = a.threshold;
+    const uintptr_t base = (uintptr_t)a.wlcs;
+    g.wmode = (a.ld % 16 == 0 && base % 16 == 0) ? 2 : (a.ld % 4 == 0 && base % 4 == 0) ? 1 : 0;
+    return g;
+}
+
+// Window capacity class of a window length: 16, 32, 64, 128 or 256.
+inline int w_class(int w) { return w <= 16 ? 16 : w <= 32 ? 32 : w <= 64 ? 64 : w <= 128 ? 128 : 256; }
+
+hipError_t launch_encode(const uint8_t* raw, int64_t len, const uint8_t* map256, int x_side,
+                         uint16_t* out, int64_t out_len, hipStream_t stream);
+hipError_t launch_seaweed(const PlotArgs& a, hipStream_t stream);
+hipError_t launch_dp(const PlotArgs& a, hipStream_t stream);
+
+}  // namespace wlcs

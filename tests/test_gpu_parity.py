@@ -1,0 +1,245 @@
+"""GPU parity: the HIP seaweed path (and the GPU DP baseline) against the CPU
+oracle, element by element, bit-exact (integer output, no tolerance).
+
+Every call goes through the C ABI of libwlcs.so via the thin binding; the
+oracle is the plain per-window dynamic program.  Sizes span several tiles,
+ragged tails, every window class (16/32/64/128/256 capacity, exact and
+partial), the label relabelling every 512 windows, all three output-store
+paths (16-byte rows, 4-byte rows, bytes), the epilogues and the degenerate
+cases.  Full-size configurations are checked on sampled rows the oracle
+computes in seconds plus invariants over the whole matrix.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_0909_2000_amd as wl
+    wl._load()  # raises if libwlcs.so is missing: no fallback
+    return wl
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cpu(t):
+    return t.cpu().numpy()
+
+
+def _bitmap_u64(t):
+    return _cpu(t).view(np.uint64)
+
+
+CASES = []
+for w in (1, 2, 3, 5, 8, 15, 16, 17, 31, 32, 33, 48, 63, 64, 65, 100, 127, 128):
+    CASES.append((w, w + 1, w + 1))      # a single window pair
+    CASES.append((w, w + 70, w + 200))   # ragged, several 64-window blocks
+    CASES.append((w, w + 131, w + 97))
+for w in (129, 200, 255):
+    CASES.append((w, w + 5, w + 90))
+
+
+@pytest.mark.parametrize("w,m,n", CASES)
+def test_small_plots_vs_oracle(ctx, oracle_mod, w, m, n):
+    _say(f"case w={w} m={m} n={n}")
+    g = workloads.rng(1000 + 7 * w + m + n)
+    alpha = workloads.DNA if w % 2 else workloads.PROTEIN
+    x, y = workloads.iid(g, m, alpha), workloads.iid(g, n, alpha)
+    want = oracle_mod.wlcs(x, y, w)
+    got = ctx.plot(x, y, w, alphabet=alpha)["wlcs"]
+    np.testing.assert_array_equal(_cpu(got), want)
+    got_dp = ctx.plot_dp(x, y, w, alphabet=alpha)["wlcs"]
+    np.testing.assert_array_equal(_cpu(got_dp), want)
+
+
+@pytest.mark.parametrize("tile", [64, 128, 576, 1024, 2048])
+def test_tiles_and_relabelling(ctx, oracle_mod, tile):
+    # long rows cross many tiles and (for tiles >= 512) the label rebase
+    _say(f"tiles tile={tile}")
+    g = workloads.rng(2000 + tile)
+    for w in (16, 37, 64, 128):
+        x, y = workloads.iid(g, 70 + w, workloads.DNA), workloads.iid(g, 3100 + w, workloads.DNA)
+        want = oracle_mod.wlcs(x, y, w)
+        ctx.set_tile(1, 255, tile)
+        try:
+            got = _cpu(ctx.plot(x, y, w)["wlcs"])
+        finally:
+            ctx.set_tile(1, 255, 0)
+        np.testing.assert_array_equal(got, want)
+
+
+def test_config1_full(ctx, oracle_mod):
+    p = workloads.config(1)
+    _say("config 1 full")
+    want = oracle_mod.wlcs(p.x, p.y, p.w)
+    got = _cpu(ctx.plot(p.x, p.y, p.w)["wlcs"])
+    assert got.shape == (984, 984)
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(_cpu(ctx.plot_dp(p.x, p.y, p.w)["wlcs"]), want)
+
+
+@pytest.mark.parametrize("pad", [0, 16, 4, 1, 7])
+def test_row_strides(lib, ctx, oracle_mod, pad):
+    # ld = cols + pad exercises the 16-byte, 4-byte and byte store paths
+    import torch
+    g = workloads.rng(3000 + pad)
+    w = 24
+    x, y = workloads.iid(g, 150, workloads.DNA), workloads.iid(g, 400 + 4 * pad, workloads.DNA)
+    want = oracle_mod.wlcs(x, y, w)
+    rows, cols = want.shape
+    ld = cols + pad
+    buf = torch.full((rows, ld), 0xEE, dtype=torch.uint8, device="cuda")
+    ctx.plot(x, y, w, out=buf[:, :cols])
+    got = _cpu(buf)
+    np.testing.assert_array_equal(got[:, :cols], want)
+    assert np.all(got[:, cols:] == 0xEE)  # nothing written past the row
+
+
+@pytest.mark.parametrize("w,thr", [(16, 12), (64, 48), (33, 0), (20, 21)])
+def test_epilogues(ctx, oracle_mod, w, thr):
+    g = workloads.rng(4000 + w)
+    x, y = workloads.iid(g, 200 + w, workloads.DNA), workloads.iid(g, 333 + w, workloads.DNA)
+    want = oracle_mod.wlcs(x, y, w)
+    for fn in (ctx.plot, ctx.plot_dp):
+        res = fn(x, y, w, threshold=thr, indel=True)
+        np.testing.assert_array_equal(_cpu(res["wlcs"]), want)
+        np.testing.assert_array_equal(_bitmap_u64(res["bitmap"]), oracle_mod.dot_bitmap(want, thr))
+        np.testing.assert_array_equal(_cpu(res["indel"]).view(np.uint16), oracle_mod.indel(want, w))
+        # epilogues alone, without the plot
+        res2 = fn(x, y, w, threshold=thr, indel=True, want_plot=False)
+        np.testing.assert_array_equal(_bitmap_u64(res2["bitmap"]), oracle_mod.dot_bitmap(want, thr))
+        np.testing.assert_array_equal(_cpu(res2["indel"]).view(np.uint16), oracle_mod.indel(want, w))
+
+
+def test_bitmap_padding_words(ctx, oracle_mod):
+    # cols not a multiple of 64: padding bits of the last word must be 0
+    import torch
+    g = workloads.rng(4500)
+    for cols in (1, 20, 33, 64, 65, 100):
+        w = 8
+        x, y = workloads.iid(g, 40, workloads.DNA), workloads.iid(g, cols + w, workloads.DNA)
+        want = oracle_mod.wlcs(x, y, w)
+        words = (cols + 63) // 64
+        bm = torch.full((want.shape[0], words), -1, dtype=torch.int64, device="cuda")
+        ctx.plot(x, y, w, threshold=3, bitmap_out=bm, want_plot=False)
+        np.testing.assert_array_equal(_bitmap_u64(bm), oracle_mod.dot_bitmap(want, 3))
+
+
+def test_full_range_flag(ctx, oracle_mod):
+    g = workloads.rng(5000)
+    for w in (1, 9, 64):
+        x, y = workloads.iid(g, w + 50, workloads.DNA), workloads.iid(g, w + 77, workloads.DNA)
+        want = oracle_mod.wlcs(x, y, w, full_range=True)
+        np.testing.assert_array_equal(_cpu(ctx.plot(x, y, w, full_range=True)["wlcs"]), want)
+        np.testing.assert_array_equal(_cpu(ctx.plot_dp(x, y, w, full_range=True)["wlcs"]), want)
+
+
+def test_degenerate(lib, ctx, oracle_mod):
+    # empty plots succeed and return empty tensors
+    for (m, n, w) in ((5, 10, 5), (10, 5, 5), (0, 0, 1), (3, 3, 4)):
+        res = ctx.plot(b"A" * m, b"C" * n, w)
+        assert tuple(res["wlcs"].shape) == (max(m - w, 0), max(n - w, 0))
+    # one-letter alphabet: every cell matches
+    x, y = b"A" * 80, b"A" * 90
+    np.testing.assert_array_equal(_cpu(ctx.plot(x, y, 12, alphabet=b"A")["wlcs"]),
+                                  np.full((68, 78), 12, dtype=np.uint8))
+    # disjoint letters of one alphabet: nothing matches
+    np.testing.assert_array_equal(_cpu(ctx.plot(b"AC" * 40, b"GT" * 45, 10)["wlcs"]), 0)
+    # x = y: w on the diagonal
+    g = workloads.rng(5100)
+    x = workloads.iid(g, 300, workloads.PROTEIN)
+    d = np.diag(_cpu(ctx.plot(x, x, 77, alphabet=workloads.PROTEIN)["wlcs"]))
+    assert np.all(d == 77)
+    # the full 64-letter alphabet
+    alpha = bytes(range(40, 104))
+    x, y = workloads.iid(g, 200, alpha), workloads.iid(g, 300, alpha)
+    np.testing.assert_array_equal(_cpu(ctx.plot(x, y, 20, alphabet=alpha)["wlcs"]),
+                                  oracle_mod.wlcs(x, y, 20))
+
+
+def test_errors(lib, ctx):
+    with pytest.raises(lib.WlcsError) as e:
+        ctx.plot(b"ACGT" * 10, b"ACGN" * 10, 4)
+    assert e.value.status == -3
+    with pytest.raises(lib.WlcsError) as e:
+        ctx.plot(b"ACGT" * 10, b"ACGT" * 10, 0)
+    assert e.value.status == -2
+    with pytest.raises(lib.WlcsError) as e:
+        ctx.plot(b"ACGT" * 10, b"ACGT" * 10, 4, alphabet=b"ACGA")
+    assert e.value.status == -3
+
+
+def _invariants_gpu(t, w, chunk=4096):
+    import torch
+    rows = t.shape[0]
+    for r0 in range(0, rows, chunk):
+        d = t[r0:min(r0 + chunk + 1, rows)].to(torch.int16)
+        assert int(d.max()) <= w and int(d.min()) >= 0
+        if d.shape[0] > 1:
+            assert int((d[1:] - d[:-1]).abs().max()) <= 1
+        assert int((d[:, 1:] - d[:, :-1]).abs().max()) <= 1
+        if d.shape[0] > 1:
+            assert int((d[1:, 1:] - d[:-1, :-1]).abs().max()) <= 1
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_full_size_sampled(ctx, oracle_mod, k):
+    """Configurations 2 and 3 at full size, in the launch the benchmark times:
+    sampled whole rows and entries against the oracle, invariants everywhere."""
+    import torch
+    p = workloads.config(k)
+    _say(f"config {k} full size m={p.m} n={p.n} w={p.w}")
+    res = ctx.plot(p.x, p.y, p.w, alphabet=p.alphabet, threshold=p.threshold)
+    torch.cuda.synchronize()
+    W = res["wlcs"]
+    rows, cols = W.shape
+    assert (rows, cols) == (p.m - p.w, p.n - p.w)
+    g = workloads.rng(6000 + k)
+    sample_rows = np.unique(np.concatenate([[0, rows - 1, rows // 2],
+                                            g.integers(0, rows, 3),
+                                            [xs for xs, _ in p.planted[:2]]]))
+    want = oracle_mod.wlcs_rows(p.x, p.y, p.w, sample_rows)
+    got = _cpu(W[torch.as_tensor(sample_rows, device="cuda")])
+    np.testing.assert_array_equal(got, want)
+    ii, jj = g.integers(0, rows, 2000), g.integers(0, cols, 2000)
+    got_at = _cpu(W[torch.as_tensor(ii, device="cuda"), torch.as_tensor(jj, device="cuda")])
+    np.testing.assert_array_equal(got_at, oracle_mod.wlcs_at(p.x, p.y, p.w, ii, jj))
+    _invariants_gpu(W, p.w)
+    if p.threshold is not None:
+        bm = _bitmap_u64(res["bitmap"][torch.as_tensor(sample_rows, device="cuda")])
+        np.testing.assert_array_equal(bm, oracle_mod.dot_bitmap(want, p.threshold))
+    # planted homologies light up, random background stays low
+    xs, ys = p.planted[0]
+    assert int(W[xs + 5, ys + 5]) > int(W[xs + 5, (ys + cols // 2) % cols])
+
+
+def test_symmetry_and_repeat(ctx):
+    import torch
+    g = workloads.rng(7000)
+    x, y = workloads.iid(g, 900, workloads.DNA), workloads.iid(g, 700, workloads.DNA)
+    a = ctx.plot(x, y, 40)["wlcs"]
+    b = ctx.plot(y, x, 40)["wlcs"]
+    assert torch.equal(a, b.t())
+    # repeated launches with different tilings are bit-identical
+    for tile in (64, 256, 1024):
+        ctx.set_tile(1, 255, tile)
+        try:
+            assert torch.equal(ctx.plot(x, y, 40)["wlcs"], a)
+        finally:
+            ctx.set_tile(1, 255, 0)
