@@ -1,0 +1,100 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point
+the header declares, and rejects bad arguments on the host before touching a
+device (a NULL context is only reported after every argument passed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wlcs.h")
+
+EINVAL, ERANGE, EALPHABET = -1, -2, -3
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wlcs_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_0909_2000_amd as wl
+    if not os.path.exists(wl.library_path()):
+        pytest.fail("libwlcs.so is not built (run __graft_entry__.build())")
+    return wl._load()
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for f in ("wlcs_ctx_create", "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_plot"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    import paper_0909_2000_amd as wl
+    for name in declared_functions():
+        assert hasattr(lib, name), f"{name} declared in wlcs.h but not exported"
+    assert set(wl.exported_symbols()) <= set(declared_functions())
+
+
+def test_status_strings(lib):
+    for st in (0, -1, -2, -3, -4, -5):
+        assert lib.wlcs_status_str(st)
+    assert lib.wlcs_status_str(-99) == b"unknown status"
+
+
+def _plot(lib, x=b"ACGTACGT", y=b"ACGTACGTAC", w=3, alpha=b"ACGT", sigma=None, out=1, ld=100,
+          bitmap=None, ld_words=0, thr=0, indel=None, ld_indel=0, flags=0, fn="wlcs_plot"):
+    sigma = len(alpha) if sigma is None else sigma
+    return getattr(lib, fn)(None, x, len(x) if x is not None else 5, y, len(y) if y is not None else 5,
+                            w, alpha, sigma,
+                            ctypes.c_void_p(out) if out else None, ld,
+                            ctypes.c_void_p(bitmap) if bitmap else None, ld_words, thr,
+                            ctypes.c_void_p(indel) if indel else None, ld_indel, flags, None)
+
+
+@pytest.mark.parametrize("fn", ["wlcs_plot", "wlcs_plot_dp"])
+def test_argument_checks_before_any_device_work(lib, fn):
+    # ranges
+    assert _plot(lib, w=0, fn=fn) == ERANGE
+    assert _plot(lib, w=256, fn=fn) == ERANGE
+    # alphabet problems
+    assert _plot(lib, alpha=b"ACGA", fn=fn) == EALPHABET          # repeated letter
+    assert _plot(lib, alpha=b"", sigma=0, fn=fn) == EALPHABET
+    assert _plot(lib, alpha=bytes(range(65)), fn=fn) == EALPHABET  # more than 64 letters
+    assert _plot(lib, x=b"ACGTNCGT", fn=fn) == EALPHABET           # letter outside
+    assert _plot(lib, y=b"ACGTACGTAc", fn=fn) == EALPHABET         # case-sensitive
+    # missing inputs / outputs and short strides
+    assert _plot(lib, x=None, fn=fn) == EINVAL
+    assert _plot(lib, out=0, fn=fn) == EINVAL                      # nothing to write
+    assert _plot(lib, ld=6, fn=fn) == EINVAL                       # cols = 7
+    assert _plot(lib, out=0, bitmap=1, ld_words=0, fn=fn) == EINVAL
+    assert _plot(lib, out=0, bitmap=1, ld_words=1, thr=256, fn=fn) == EINVAL
+    assert _plot(lib, out=0, indel=1, ld_indel=3, fn=fn) == EINVAL
+    assert _plot(lib, flags=2, fn=fn) == EINVAL
+    # every argument fine: only the NULL context is left to complain about
+    assert _plot(lib, fn=fn) == EINVAL
+    assert _plot(lib, out=0, bitmap=1, ld_words=1, thr=5, indel=1, ld_indel=7, fn=fn) == EINVAL
+
+
+def test_pair_and_ctx_argument_checks(lib):
+    h = ctypes.c_void_p()
+    assert lib.wlcs_pair_create(None, b"ACGT", 4, b"ACGT", 4, b"ACGT", 4, None, ctypes.byref(h)) == EINVAL
+    assert lib.wlcs_pair_create(None, b"ACGN", 4, b"ACGT", 4, b"ACGT", 4, None, ctypes.byref(h)) == EALPHABET
+    assert lib.wlcs_pair_create(None, b"ACGT", 4, b"ACGT", 4, b"ACGT", 4, None, None) == EINVAL
+    assert lib.wlcs_pair_plot(None, None, 3, None, 0, None, 0, 0, None, 0, 0, None) == EINVAL
+    assert lib.wlcs_pair_destroy(None) == 0
+    assert lib.wlcs_ctx_destroy(None) == 0
+    assert lib.wlcs_ctx_set_tile(None, 1, 16, 64) == EINVAL
+    assert lib.wlcs_ctx_create(0, None) == EINVAL
+
+
+def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
+    import paper_0909_2000_amd as wl
+    monkeypatch.setattr(wl, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(wl, "_lib", None)
+    with pytest.raises(wl.WlcsUnavailable):
+        wl._load()
