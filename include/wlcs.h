@@ -138,6 +138,46 @@ int wlcs_pair_plot_dp(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, uint8_t *
                       uint64_t *bitmap, int64_t ld_words, int32_t threshold, uint16_t *indel,
                       int64_t ld_indel, uint32_t flags, void *stream);
 
+/* ---- batched plots ------------------------------------------------------
+ * Many plots of uneven m, n and w in one persistent, work-stealing launch: the
+ * plots' units (64 x-windows against two y-tiles) go into one device-wide
+ * queue that resident wavefronts drain (windows w <= 128; longer windows run
+ * as separate launches on the same stream).  Each plot's outputs are exactly
+ * those of wlcs_pair_plot with the same arguments. */
+typedef struct {
+    const wlcs_pair *pair; /* resident strings (wlcs_pair_create on the same device) */
+    int32_t w;
+    uint32_t flags;        /* 0 or WLCS_FULL_RANGE */
+    uint8_t *wlcs;         /* outputs as in wlcs_plot; any may be NULL, not all */
+    int64_t ld;
+    uint64_t *bitmap;
+    int64_t ld_words;
+    int32_t threshold;
+    uint16_t *indel;
+    int64_t ld_indel;
+} wlcs_job;
+
+/* Enqueue all njobs plots on `stream`.  Jobs are checked on the host first; a
+ * bad job fails the whole call before anything is enqueued.  The job array and
+ * the table built from it are consumed before the call returns; pairs and
+ * outputs must stay valid until the stream has run the batch. */
+int wlcs_batch(wlcs_ctx *ctx, const wlcs_job *jobs, int32_t njobs, void *stream);
+
+/* The same batch captured once into a HIP graph (job table and work counter
+ * owned by the graph), to be replayed with wlcs_graph_launch as many times as
+ * wanted; each replay recomputes every plot of the batch. */
+typedef struct wlcs_graph wlcs_graph;
+int wlcs_batch_graph(wlcs_ctx *ctx, const wlcs_job *jobs, int32_t njobs, wlcs_graph **out);
+int wlcs_graph_launch(wlcs_graph *graph, void *stream);
+int wlcs_graph_destroy(wlcs_graph *graph); /* waits for the graph's device memory to be idle */
+
+/* Batch tuning: y-windows per tile for batched plots of windows w_lo..w_hi
+ * (multiple of 64, 64..32768; 0 restores the built-in choice, which aims at
+ * equal work per unit: about 131072 / w windows), and the persistent grid
+ * (workgroups per compute unit, 1..16; 0 restores the default 8). */
+int wlcs_ctx_set_batch_tile(wlcs_ctx *ctx, int32_t w_lo, int32_t w_hi, int32_t tile_windows);
+int wlcs_ctx_set_batch_grid(wlcs_ctx *ctx, int32_t waves_per_cu);
+
 #ifdef __cplusplus
 }
 #endif

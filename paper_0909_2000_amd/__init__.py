@@ -16,7 +16,7 @@ import os
 import numpy as np
 import torch  # loaded before libwlcs.so so that both share one HIP runtime
 
-__all__ = ["Context", "Pair", "WlcsError", "WlcsUnavailable", "plot", "plot_dp", "n_windows",
+__all__ = ["Context", "Pair", "BatchGraph", "Job", "WlcsError", "WlcsUnavailable", "plot", "plot_dp", "n_windows",
            "library_path", "exported_symbols", "DNA", "PROTEIN"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -43,6 +43,15 @@ class WlcsError(RuntimeError):
         if hip_error:
             msg += f", hip error {hip_error}"
         super().__init__(msg)
+
+
+class Job(ctypes.Structure):
+    """wlcs_job of include/wlcs.h."""
+    _fields_ = [("pair", ctypes.c_void_p), ("w", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("wlcs", ctypes.c_void_p), ("ld", ctypes.c_int64),
+                ("bitmap", ctypes.c_void_p), ("ld_words", ctypes.c_int64),
+                ("threshold", ctypes.c_int32), ("indel", ctypes.c_void_p),
+                ("ld_indel", ctypes.c_int64)]
 
 
 _lib = None
@@ -79,9 +88,16 @@ def _load():
     pair_args = [vp, vp, i32, vp, i64, vp, i64, i32, vp, i64, u32, vp]
     lib.wlcs_pair_plot.argtypes = pair_args
     lib.wlcs_pair_plot_dp.argtypes = pair_args
+    lib.wlcs_batch.argtypes = [vp, ctypes.POINTER(Job), i32, vp]
+    lib.wlcs_batch_graph.argtypes = [vp, ctypes.POINTER(Job), i32, ctypes.POINTER(vp)]
+    lib.wlcs_graph_launch.argtypes = [vp, vp]
+    lib.wlcs_graph_destroy.argtypes = [vp]
+    lib.wlcs_ctx_set_batch_tile.argtypes = [vp, i32, i32, i32]
+    lib.wlcs_ctx_set_batch_grid.argtypes = [vp, i32]
     for f in ("wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_ctx_set_tile",
               "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot",
-              "wlcs_pair_plot_dp"):
+              "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
+              "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -91,7 +107,8 @@ def exported_symbols() -> list:
     """Names of the C ABI entry points the binding uses."""
     return ["wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_status_str",
             "wlcs_ctx_set_tile", "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy",
-            "wlcs_pair_plot", "wlcs_pair_plot_dp"]
+            "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
+            "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid"]
 
 
 def n_windows(length: int, w: int, full_range: bool = False) -> int:
@@ -199,6 +216,50 @@ class Context:
             raise WlcsError(st, fn, lib.wlcs_ctx_last_hip_error(self._h))
         return self._result(out, bitmap_out, indel_out)
 
+    def set_batch_tile(self, w_lo: int, w_hi: int, tile: int):
+        st = _load().wlcs_ctx_set_batch_tile(self._h, w_lo, w_hi, tile)
+        if st != 0:
+            raise WlcsError(st, "wlcs_ctx_set_batch_tile")
+
+    def set_batch_grid(self, waves_per_cu: int):
+        st = _load().wlcs_ctx_set_batch_grid(self._h, waves_per_cu)
+        if st != 0:
+            raise WlcsError(st, "wlcs_ctx_set_batch_grid")
+
+    def _jobs(self, specs):
+        """specs: dicts with pair, w and optional threshold, indel, full_range,
+        want_plot, out, bitmap_out, indel_out.  Returns (Job array, results)."""
+        arr = (Job * max(len(specs), 1))()
+        results = []
+        for k, sp in enumerate(specs):
+            pair, w = sp["pair"], int(sp["w"])
+            full = bool(sp.get("full_range", False))
+            rows, cols = n_windows(pair.m, w, full), n_windows(pair.n, w, full)
+            thr = sp.get("threshold")
+            out, bm, ind = self._outputs(rows, cols, thr, sp.get("indel", False), sp.get("out"),
+                                         sp.get("bitmap_out"), sp.get("indel_out"),
+                                         sp.get("want_plot", True))
+            o = self._out_args(out, bm, ind, thr)
+            arr[k] = Job(pair._h.value, w, WLCS_FULL_RANGE if full else 0, o[0].value if o[0] else None,
+                         o[1], o[2].value if o[2] else None, o[3], o[4],
+                         o[5].value if o[5] else None, o[6])
+            results.append(self._result(out, bm, ind))
+        return arr, results
+
+    def batch(self, specs, stream=None) -> list:
+        """All plots of specs in one persistent launch (wlcs_batch)."""
+        lib = _load()
+        arr, results = self._jobs(specs)
+        stream = self._stream(stream)
+        st = lib.wlcs_batch(self._h, arr, len(specs), ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise WlcsError(st, "wlcs_batch", lib.wlcs_ctx_last_hip_error(self._h))
+        return results
+
+    def batch_graph(self, specs) -> "BatchGraph":
+        """The batch captured into a replayable HIP graph (wlcs_batch_graph)."""
+        return BatchGraph(self, specs)
+
     def pair(self, x, y, alphabet=DNA, stream=None) -> "Pair":
         """Upload and encode x and y once; plot them any number of times."""
         return Pair(self, x, y, alphabet, stream)
@@ -271,6 +332,39 @@ class Pair:
                 indel_out=None, want_plot=True, stream=None) -> dict:
         return self._run("wlcs_pair_plot_dp", w, threshold, indel, full_range, out, bitmap_out,
                          indel_out, want_plot, stream)
+
+
+class BatchGraph:
+    """A captured batch; launch() replays every plot of it into its outputs."""
+
+    def __init__(self, ctx: Context, specs):
+        lib = _load()
+        self.ctx = ctx
+        self.specs = specs  # keeps the pairs alive
+        arr, self.results = ctx._jobs(specs)
+        h = ctypes.c_void_p()
+        st = lib.wlcs_batch_graph(ctx.handle, arr, len(specs), ctypes.byref(h))
+        if st != 0:
+            raise WlcsError(st, "wlcs_batch_graph", lib.wlcs_ctx_last_hip_error(ctx.handle))
+        self._h = h
+
+    def launch(self, stream=None):
+        stream = self.ctx._stream(stream)
+        st = _load().wlcs_graph_launch(self._h, ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise WlcsError(st, "wlcs_graph_launch")
+        return self.results
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _load().wlcs_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _default_ctx = {}

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <new>
+#include <vector>
 
 #include "../../include/wlcs.h"
 #include "kernels.hpp"
@@ -39,6 +40,9 @@ struct wlcs_ctx {
     int next_slot = 0;
     TileRule rules[16];
     int nrules = 0;
+    TileRule batch_rules[16];
+    int nbatch_rules = 0;
+    int batch_waves_per_cu = 0;  // 0: kBatchWavesPerCu
 };
 
 namespace {
@@ -116,6 +120,32 @@ int validate(const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, int32_t w
         if (map[x[i]] == 0xFF) return WLCS_EALPHABET;
     for (int64_t i = 0; i < n; ++i)
         if (map[y[i]] == 0xFF) return WLCS_EALPHABET;
+    return WLCS_OK;
+}
+
+// Copy `bytes` host bytes to device memory dst on `stream` through one of the
+// context's pinned slots (the host buffer may be reused on return).
+int stage_copy(wlcs_ctx* ctx, const void* src, size_t bytes, void* dst, hipStream_t stream) {
+    if (bytes == 0) return WLCS_OK;
+    Slot& sl = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
+    hipError_t e;
+    if (sl.pending) {
+        if ((e = hipEventSynchronize(sl.done)) != hipSuccess) return fail(ctx, e);
+        sl.pending = false;
+    }
+    if (sl.cap < bytes) {
+        if (sl.buf) (void)hipHostFree(sl.buf);
+        sl.buf = nullptr;
+        sl.cap = 0;
+        const size_t cap = std::max<size_t>(bytes, 1 << 16);
+        if ((e = hipHostMalloc((void**)&sl.buf, cap, hipHostMallocDefault)) != hipSuccess) return fail(ctx, e);
+        sl.cap = cap;
+    }
+    memcpy(sl.buf, src, bytes);
+    if ((e = hipMemcpyAsync(dst, sl.buf, bytes, hipMemcpyHostToDevice, stream)) != hipSuccess) return fail(ctx, e);
+    if ((e = hipEventRecord(sl.done, stream)) != hipSuccess) return fail(ctx, e);
+    sl.pending = true;
     return WLCS_OK;
 }
 
@@ -296,6 +326,109 @@ int pair_plot_common(Path path, wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w,
 
 }  // namespace
 
+struct wlcs_graph {
+    int device = 0;
+    wlcs::JobDesc* table = nullptr;
+    unsigned long long* counter = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int32_t batch_tile(const wlcs_ctx* ctx, int64_t cols, int32_t w) {
+    for (int r = ctx->nbatch_rules - 1; r >= 0; --r)
+        if (w >= ctx->batch_rules[r].lo && w <= ctx->batch_rules[r].hi) return ctx->batch_rules[r].tile;
+    // about equal combing work per unit for every window, and at least two
+    // tiles per row so both halves of each register carry work
+    int64_t t = (131072 / w + 63) / 64 * 64;
+    const int64_t half = ((cols + 1) / 2 + 63) / 64 * 64;
+    t = std::min<int64_t>(t, half);
+    t = std::max<int64_t>(64, std::min<int64_t>(t, kMaxTile));
+    return (int32_t)t;
+}
+
+struct BatchPlan {
+    std::vector<wlcs::JobDesc> table;  // jobs with w <= kBatchMaxW, by decreasing unit cost
+    std::vector<wlcs::PlotArgs> singles;  // longer windows: single-plot launches
+    int64_t total_units = 0;
+};
+
+int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& plan) {
+    if (!ctx || njobs < 0 || (njobs > 0 && !jobs)) return WLCS_EINVAL;
+    struct Item {
+        wlcs::JobDesc d;
+        double cost;
+    };
+    std::vector<Item> items;
+    for (int32_t k = 0; k < njobs; ++k) {
+        const wlcs_job& j = jobs[k];
+        if (j.flags & ~WLCS_FULL_RANGE) return WLCS_EINVAL;
+        if (!j.pair || j.pair->device != ctx->device) return WLCS_EINVAL;
+        if (j.w < 1 || j.w > WLCS_MAX_W) return WLCS_ERANGE;
+        const bool full = (j.flags & WLCS_FULL_RANGE) != 0;
+        const int64_t rows = n_windows(j.pair->m, j.w, full), cols = n_windows(j.pair->n, j.w, full);
+        int st = check_outputs(rows, cols, j.wlcs, j.ld, j.bitmap, j.ld_words, j.threshold, j.indel, j.ld_indel);
+        if (st != WLCS_OK) return st;
+        if (rows == 0 || cols == 0) continue;
+        wlcs::PlotArgs a =
+            make_args(rows, cols, j.w, j.wlcs, j.ld, j.bitmap, j.ld_words, j.threshold, j.indel, j.ld_indel);
+        a.xf = j.pair->xf;
+        a.yg = j.pair->yg;
+        if (j.w > wlcs::kBatchMaxW) {
+            a.tile = choose_tile(ctx, rows, cols, j.w);
+            a.npairs = (int32_t)(((cols + a.tile - 1) / a.tile + 1) / 2);
+            plan.singles.push_back(a);
+            continue;
+        }
+        a.tile = batch_tile(ctx, cols, j.w);
+        a.npairs = (int32_t)(((cols + a.tile - 1) / a.tile + 1) / 2);
+        int64_t xf_len, yg_len;
+        needed_lengths(Path::Seaweed, rows, cols, j.w, a.tile, xf_len, yg_len);
+        if (xf_len > j.pair->xf_cap || yg_len > j.pair->yg_cap) return WLCS_EINVAL;
+        Item it;
+        it.d.xf = a.xf;
+        it.d.yg32 = (const uint32_t*)a.yg;
+        it.d.out = a.wlcs;
+        it.d.bm32 = a.bitmap32;
+        it.d.indel = a.indel;
+        it.d.g = wlcs::geom_of(a);
+        it.d.unit0 = (rows + 63) / 64 * a.npairs;  // unit count for now
+        it.d.variant = wlcs::batch_variant(j.w);
+        it.d.pad = 0;
+        it.cost = 2.0 * (double)(a.tile + j.w - 1) * (double)j.w;
+        items.push_back(it);
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& p, const Item& q) { return p.cost > q.cost; });
+    int64_t u0 = 0;
+    for (Item& it : items) {
+        const int64_t units = it.d.unit0;
+        it.d.unit0 = u0;
+        u0 += units;
+        plan.table.push_back(it.d);
+    }
+    plan.total_units = u0;
+    return WLCS_OK;
+}
+
+int batch_grid(const wlcs_ctx* ctx, int64_t total_units) {
+    const int64_t per_cu = ctx->batch_waves_per_cu > 0 ? ctx->batch_waves_per_cu : wlcs::kBatchWavesPerCu;
+    return (int)std::min<int64_t>(total_units, (int64_t)ctx->cus * per_cu);
+}
+
+// Enqueue a planned batch whose job table already sits at table_dev.
+hipError_t enqueue_batch(const wlcs_ctx* ctx, const BatchPlan& plan, const wlcs::JobDesc* table_dev,
+                         unsigned long long* counter, hipStream_t stream) {
+    hipError_t e = hipSuccess;
+    if (!plan.table.empty())
+        e = wlcs::launch_batch(table_dev, (int32_t)plan.table.size(), plan.total_units, counter,
+                               batch_grid(ctx, plan.total_units), stream);
+    for (size_t k = 0; e == hipSuccess && k < plan.singles.size(); ++k) e = wlcs::launch_seaweed(plan.singles[k], stream);
+    return e;
+}
+
+}  // namespace
+
 extern "C" {
 
 int wlcs_ctx_create(int device, wlcs_ctx** out) {
@@ -449,6 +582,107 @@ int wlcs_pair_plot_dp(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, uint8_t* 
                       uint32_t flags, void* stream) {
     return pair_plot_common(Path::Dp, ctx, pair, w, wlcs, ld, bitmap, ld_words, threshold, indel, ld_indel,
                             flags, stream);
+}
+
+int wlcs_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, void* stream_) {
+    BatchPlan plan;
+    int st = plan_batch(ctx, jobs, njobs, plan);
+    if (st != WLCS_OK) return st;
+    if (plan.table.empty() && plan.singles.empty()) return WLCS_OK;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
+    hipStream_t stream = (hipStream_t)stream_;
+    const size_t tbytes = plan.table.size() * sizeof(wlcs::JobDesc);
+    const size_t cnt_off = (tbytes + 255) / 256 * 256;
+    uint8_t* dev = nullptr;  // job table, then the 8-byte work counter at cnt_off
+    hipError_t e = hipSuccess;
+    if (!plan.table.empty()) {
+        if ((e = hipMallocAsync((void**)&dev, cnt_off + 256, stream)) != hipSuccess) return fail(ctx, e);
+        st = stage_copy(ctx, plan.table.data(), tbytes, dev, stream);
+        if (st != WLCS_OK) {
+            (void)hipFreeAsync(dev, stream);
+            return st;
+        }
+    }
+    e = enqueue_batch(ctx, plan, (const wlcs::JobDesc*)dev, dev ? (unsigned long long*)(dev + cnt_off) : nullptr,
+                      stream);
+    if (dev) (void)hipFreeAsync(dev, stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    return WLCS_OK;
+}
+
+int wlcs_batch_graph(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, wlcs_graph** out) {
+    if (!out) return WLCS_EINVAL;
+    *out = nullptr;
+    BatchPlan plan;
+    int st = plan_batch(ctx, jobs, njobs, plan);
+    if (st != WLCS_OK) return st;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
+    wlcs_graph* g = new (std::nothrow) wlcs_graph();
+    if (!g) return WLCS_ENOMEM;
+    g->device = ctx->device;
+    const size_t tbytes = plan.table.size() * sizeof(wlcs::JobDesc);
+    hipStream_t cap = nullptr;
+    hipError_t e = hipMalloc((void**)&g->table, std::max<size_t>(tbytes, 64));
+    if (e == hipSuccess) e = hipMalloc((void**)&g->counter, 256);
+    if (e == hipSuccess && tbytes) e = hipMemcpy(g->table, plan.table.data(), tbytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t el = enqueue_batch(ctx, plan, g->table, g->counter, cap);
+        e = hipStreamEndCapture(cap, &g->graph);
+        if (el != hipSuccess) e = el;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        wlcs_graph_destroy(g);
+        return fail(ctx, e);
+    }
+    *out = g;
+    return WLCS_OK;
+}
+
+int wlcs_graph_launch(wlcs_graph* graph, void* stream) {
+    if (!graph || !graph->exec) return WLCS_EINVAL;
+    DeviceGuard guard(graph->device);
+    if (!guard.ok) return WLCS_EHIP;
+    return hipGraphLaunch(graph->exec, (hipStream_t)stream) == hipSuccess ? WLCS_OK : WLCS_EHIP;
+}
+
+int wlcs_graph_destroy(wlcs_graph* graph) {
+    if (!graph) return WLCS_OK;
+    DeviceGuard guard(graph->device);
+    int st = WLCS_OK;
+    if (graph->exec && hipGraphExecDestroy(graph->exec) != hipSuccess) st = WLCS_EHIP;
+    if (graph->graph && hipGraphDestroy(graph->graph) != hipSuccess) st = WLCS_EHIP;
+    if (graph->table && hipFree(graph->table) != hipSuccess) st = WLCS_EHIP;
+    if (graph->counter && hipFree(graph->counter) != hipSuccess) st = WLCS_EHIP;
+    delete graph;
+    return st;
+}
+
+int wlcs_ctx_set_batch_tile(wlcs_ctx* ctx, int32_t w_lo, int32_t w_hi, int32_t tile_windows) {
+    if (!ctx || w_lo < 1 || w_hi < w_lo || w_hi > WLCS_MAX_W) return WLCS_EINVAL;
+    if (tile_windows == 0) {
+        int k = 0;
+        for (int r = 0; r < ctx->nbatch_rules; ++r)
+            if (!(ctx->batch_rules[r].lo >= w_lo && ctx->batch_rules[r].hi <= w_hi))
+                ctx->batch_rules[k++] = ctx->batch_rules[r];
+        ctx->nbatch_rules = k;
+        return WLCS_OK;
+    }
+    if (tile_windows < 64 || tile_windows > kMaxTile || tile_windows % 64) return WLCS_EINVAL;
+    if (ctx->nbatch_rules == 16) return WLCS_ENOMEM;
+    ctx->batch_rules[ctx->nbatch_rules++] = TileRule{w_lo, w_hi, tile_windows};
+    return WLCS_OK;
+}
+
+int wlcs_ctx_set_batch_grid(wlcs_ctx* ctx, int32_t waves_per_cu) {
+    if (!ctx || waves_per_cu < 0 || waves_per_cu > 16) return WLCS_EINVAL;
+    ctx->batch_waves_per_cu = waves_per_cu;
+    return WLCS_OK;
 }
 
 }  // extern "C"

@@ -63,6 +63,19 @@ inline Geom geom_of(const PlotArgs& a) {
     return g;
 }
 
+// One entry of the batched kernel's job table.
+struct JobDesc {
+    const uint16_t* xf;
+    const uint32_t* yg32;
+    uint8_t* out;
+    uint32_t* bm32;
+    uint16_t* indel;
+    Geom g;
+    int64_t unit0;    // index of the job's first unit in the global unit list
+    int32_t variant;  // per-unit code path (batch_variant)
+    int32_t pad;
+};
+
 // Window capacity class of a window length: 16, 32, 64, 128 or 256.
 inline int w_class(int w) { return w <= 16 ? 16 : w <= 32 ? 32 : w <= 64 ? 64 : w <= 128 ? 128 : 256; }
 
@@ -70,5 +83,10 @@ hipError_t launch_encode(const uint8_t* raw, int64_t len, const uint8_t* map256,
                          uint16_t* out, int64_t out_len, hipStream_t stream);
 hipError_t launch_seaweed(const PlotArgs& a, hipStream_t stream);
 hipError_t launch_dp(const PlotArgs& a, hipStream_t stream);
+int batch_variant(int w);
+constexpr int kBatchMaxW = 128;            // longer windows leave the batched kernel
+constexpr int kBatchWavesPerCu = 8;        // resident waves per CU of batch_kernel
+hipError_t launch_batch(const JobDesc* jobs_dev, int32_t njobs, int64_t total_units,
+                        unsigned long long* counter, int32_t grid, hipStream_t stream);
 
 }  // namespace wlcs

@@ -1,0 +1,171 @@
+"""GPU: the batched persistent launch (wlcs_batch) and its captured graph.
+
+Each plot of a batch must equal the oracle (whole matrices at small sizes,
+sampled rows at the batch configuration's full size) and the same plot run
+alone (bit-exact), whatever the queue order, tile choice or grid size.  Graph
+replays are checked one by one, with eager work in between.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wl():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_0909_2000_amd as wl
+    wl._load()
+    return wl
+
+
+@pytest.fixture(scope="module")
+def ctx(wl):
+    return wl.Context(0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _mixed_specs(ctx, seed, count, lo, hi, ws, extras=True):
+    g = workloads.rng(seed)
+    specs, inputs = [], []
+    for k in range(count):
+        w = int(ws[k % len(ws)])
+        m, n = int(g.integers(lo, hi)) + w, int(g.integers(lo, hi)) + w
+        alpha = workloads.PROTEIN if k % 3 == 0 else workloads.DNA
+        x, y = workloads.iid(g, m, alpha), workloads.iid(g, n, alpha)
+        spec = {"pair": ctx.pair(x, y, alphabet=alpha), "w": w}
+        if extras and k % 2 == 0:
+            spec["threshold"] = (3 * w + 3) // 4
+        if extras and k % 4 == 1:
+            spec["indel"] = True
+        if extras and k % 5 == 2:
+            spec["full_range"] = True
+        specs.append(spec)
+        inputs.append((x, y, w))
+    return specs, inputs
+
+
+def _check_vs_oracle(oracle_mod, res, spec, x, y, w):
+    full = spec.get("full_range", False)
+    want = oracle_mod.wlcs(x, y, w, full_range=full)
+    np.testing.assert_array_equal(_np(res["wlcs"]), want)
+    if "threshold" in spec:
+        np.testing.assert_array_equal(_np(res["bitmap"]).view(np.uint64),
+                                      oracle_mod.dot_bitmap(want, spec["threshold"]))
+    if spec.get("indel"):
+        np.testing.assert_array_equal(_np(res["indel"]).view(np.uint16), oracle_mod.indel(want, w))
+
+
+def test_small_mixed_batch_vs_oracle(ctx, oracle_mod):
+    ws = (1, 5, 16, 17, 32, 48, 64, 100, 128, 129, 200, 255)
+    specs, inputs = _mixed_specs(ctx, 11, 36, 1, 400, ws)
+    _say(f"batch of {len(specs)} small plots")
+    results = ctx.batch(specs)
+    for res, spec, (x, y, w) in zip(results, specs, inputs):
+        _check_vs_oracle(oracle_mod, res, spec, x, y, w)
+
+
+def test_batch_equals_single_plots(ctx):
+    import torch
+    specs, inputs = _mixed_specs(ctx, 12, 24, 500, 3000, (16, 32, 64, 128, 40))
+    _say("batch vs singles, 24 plots")
+    results = ctx.batch(specs)
+    for res, spec in zip(results, specs):
+        alone = spec["pair"].plot(spec["w"], threshold=spec.get("threshold"), indel=spec.get("indel", False),
+                                  full_range=spec.get("full_range", False))
+        for key in alone:
+            assert torch.equal(res[key], alone[key]), key
+
+
+@pytest.mark.parametrize("grid,tile", [(1, 0), (16, 0), (8, 64), (3, 1024)])
+def test_grid_and_tile_do_not_change_results(ctx, grid, tile):
+    import torch
+    specs, _ = _mixed_specs(ctx, 13, 12, 200, 1500, (16, 64, 128, 33), extras=False)
+    ref = ctx.batch(specs)
+    ctx.set_batch_grid(grid)
+    if tile:
+        ctx.set_batch_tile(1, 128, tile)
+    try:
+        got = ctx.batch(specs)
+    finally:
+        ctx.set_batch_grid(0)
+        ctx.set_batch_tile(1, 128, 0)
+    for a, b in zip(ref, got):
+        assert torch.equal(a["wlcs"], b["wlcs"])
+
+
+def test_batch_row_strides_and_empty_jobs(ctx, oracle_mod):
+    import torch
+    g = workloads.rng(14)
+    x, y = workloads.iid(g, 300, workloads.DNA), workloads.iid(g, 500, workloads.DNA)
+    p = ctx.pair(x, y)
+    tiny = ctx.pair(b"ACG", b"ACGT")  # empty plot for w >= 3
+    want = oracle_mod.wlcs(x, y, 20)
+    rows, cols = want.shape
+    buf = torch.full((rows, cols + 5), 0x5A, dtype=torch.uint8, device="cuda")
+    specs = [{"pair": p, "w": 20, "out": buf[:, :cols]}, {"pair": tiny, "w": 3},
+             {"pair": p, "w": 20, "threshold": 15, "want_plot": False}]
+    res = ctx.batch(specs)
+    np.testing.assert_array_equal(_np(buf[:, :cols]), want)
+    assert np.all(_np(buf[:, cols:]) == 0x5A)
+    assert res[1]["wlcs"].numel() == 0
+    np.testing.assert_array_equal(_np(res[2]["bitmap"]).view(np.uint64), oracle_mod.dot_bitmap(want, 15))
+
+
+def test_graph_replays(ctx, oracle_mod):
+    import torch
+    specs, inputs = _mixed_specs(ctx, 15, 10, 50, 600, (16, 32, 64, 128, 130), extras=True)
+    graph = ctx.batch_graph(specs)
+    eager = ctx.batch(specs)
+    torch.cuda.synchronize()
+    for replay in range(4):
+        for r in graph.results:  # wipe the outputs, then replay into them
+            for t in r.values():
+                t.fill_(0x33)
+        other = ctx.plot(inputs[0][0], inputs[0][1], 7, alphabet=workloads.PROTEIN)["wlcs"]  # unrelated eager work
+        graph.launch()
+        torch.cuda.synchronize()
+        for a, b in zip(graph.results, eager):
+            for key in a:
+                assert torch.equal(a[key], b[key]), (replay, key)
+        assert other.numel() > 0
+    for res, spec, (x, y, w) in zip(graph.results, specs, inputs):
+        _check_vs_oracle(oracle_mod, res, spec, x, y, w)
+    graph.close()
+
+
+def test_batch_configuration_full_size(ctx, oracle_mod):
+    """256 DNA pairs, m, n uniform in [1000, 20000], w from {16, 32, 64, 128},
+    in one persistent launch: every plot's sampled row and entries against the
+    oracle, a few plots against their single-plot run."""
+    import torch
+    pairs = workloads.batch_config()
+    _say(f"batch configuration: {len(pairs)} pairs")
+    specs = [{"pair": ctx.pair(p.x, p.y), "w": p.w} for p in pairs]
+    res = ctx.batch(specs)
+    torch.cuda.synchronize()
+    g = workloads.rng(16)
+    for k, (p, r) in enumerate(zip(pairs, res)):
+        W = r["wlcs"]
+        rows, cols = W.shape
+        assert (rows, cols) == (p.m - p.w, p.n - p.w)
+        row = int(g.integers(0, rows))
+        np.testing.assert_array_equal(_np(W[row:row + 1]), oracle_mod.wlcs_rows(p.x, p.y, p.w, [row]))
+        ii, jj = g.integers(0, rows, 16), g.integers(0, cols, 16)
+        got = _np(W[torch.as_tensor(ii, device="cuda"), torch.as_tensor(jj, device="cuda")])
+        np.testing.assert_array_equal(got, oracle_mod.wlcs_at(p.x, p.y, p.w, ii, jj))
+    for k in (0, 17, 101, 255):
+        assert torch.equal(res[k]["wlcs"], specs[k]["pair"].plot(specs[k]["w"])["wlcs"])
