@@ -48,6 +48,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU sample time")
     ap.add_argument("--tile", type=int, default=0, help="override the seaweed tile (windows)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-pair measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serving-jobs", type=int, default=2000)
+    ap.add_argument("--serving-load", type=float, default=0.7, help="arrival rate / measured capacity")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="serving HBM budget")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -161,6 +166,18 @@ def main():
                          f"{cols} y-windows, plain per-window DP, {cpu_s:.1f} s"}
         log(f"CPU oracle: {cpu['value']:.3e} window-cells/s on {threads} threads")
 
+    batched = None
+    if not args.no_batch:
+        batched = bench_batch(ctx, torch, workloads)
+        log(f"batched: {batched['value']:.3e} window-cells/s over {batched['pairs']} pairs "
+            f"({batched['ms']:.1f} ms; graph replay {batched['graph_ms']:.1f} ms)")
+
+    serving = None
+    if not args.no_serving:
+        serving = bench_serving(ctx, torch, workloads, args)
+        log(f"serving: p50 {serving['at_load']['p50_s'] * 1e3:.1f} ms, p99 "
+            f"{serving['at_load']['p99_s'] * 1e3:.1f} ms at {serving['rate_jobs_per_s']:.0f} jobs/s")
+
     rec = {
         "metric": METRIC, "value": value, "unit": "window-cells/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -170,6 +187,7 @@ def main():
                    "threshold": thr, "outputs": "uint8 plot + bitmap" if thr else "uint8 plot",
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "gpu_dp_baseline": dp,
+        "batched": batched, "serving": serving,
         "encode_ms": encode_ms, "parity_sampled_rows": parity,
         "kernel_ms": {"min": float(np.min(kern_ms)), "median": float(np.median(kern_ms)),
                       "max": float(np.max(kern_ms))},
@@ -177,6 +195,74 @@ def main():
     print(json.dumps(rec), flush=True)
     pair.close()
     ctx.close()
+
+
+def bench_batch(ctx, torch, workloads, reps=3):
+    """256 DNA pairs of uneven m, n and w in one persistent launch (eager and
+    graph-replayed), outputs preallocated, pairs resident."""
+    import numpy as np
+    pairs = workloads.batch_config()
+    specs = [{"pair": ctx.pair(p.x, p.y), "w": p.w} for p in pairs]
+    res = ctx.batch(specs)  # allocates the outputs once (and warms up)
+    for sp, r in zip(specs, res):
+        sp["out"] = r["wlcs"]
+    graph = ctx.batch_graph(specs)
+    graph.launch()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms))
+
+    eager_ms = timed(lambda: ctx.batch(specs))
+    graph_ms = timed(lambda: graph.launch())
+    nominal = sum(float(p.m) * p.n * p.w for p in pairs)
+    graph.close()
+    out = {"pairs": len(pairs), "window_cells": nominal, "ms": eager_ms, "graph_ms": graph_ms,
+           "value": nominal / (eager_ms / 1e3), "graph_value": nominal / (graph_ms / 1e3),
+           "unit": "window-cells/s", "workload": "256 iid DNA pairs, m,n ~ U[1000,20000], w ~ {16,32,64,128}"}
+    del specs, res
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_serving(ctx, torch, workloads, args):
+    """Poisson stream of DNA/protein jobs (bitmap + indel outputs): capacity
+    with every job queued at once, then latency at a fraction of it."""
+    from paper_0909_2000_amd import serve
+    jobs = workloads.serving_jobs(rate=1.0, njobs=args.serving_jobs)
+    budget = int(args.budget_gib * (1 << 30))
+
+    def run(rate_scale, all_at_once=False):
+        reqs = serve.requests_from_workload(jobs, rate_scale=rate_scale)
+        if all_at_once:
+            for r in reqs:
+                r.arrival = 0.0
+        ex = serve.GpuExecutor(0, streams=3, ctx=ctx)
+        srv = serve.Server(ex, budget_bytes=budget, max_jobs=256, max_batch=64, keep_results=False)
+        rep = srv.run(reqs)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return rep
+
+    sat = run(1.0, all_at_once=True)
+    capacity = sat["jobs_per_s"]
+    rate = args.serving_load * capacity
+    # arrivals were drawn at 1 job/s: compress them to `rate`
+    at = run(rate)
+    return {"jobs": len(jobs), "capacity_jobs_per_s": capacity, "saturated": sat,
+            "load": args.serving_load, "rate_jobs_per_s": rate, "at_load": at,
+            "budget_gib": args.budget_gib,
+            "workload": "Poisson arrivals; DNA/protein 1:1; m,n log-uniform [500,50000]; "
+                        "w ~ {16,32,64,128}; outputs bitmap (T=ceil(3w/4)) + uint16 indel"}
 
 
 if __name__ == "__main__":

@@ -115,8 +115,8 @@ int wlcs_plot_dp(wlcs_ctx *ctx, const uint8_t *x, int64_t m, const uint8_t *y, i
 /* ---- device-resident pairs --------------------------------------------
  * A pair holds x and y on the device, already mapped to letter codes, so that
  * repeated plots (several windows, benchmarking, a serving loop) start from
- * inputs resident in HBM.  The pair owns its device memory (allocated with
- * hipMalloc on the context's device) until wlcs_pair_destroy. */
+ * inputs resident in HBM.  The pair owns its device memory, taken in stream
+ * order on the stream it is created on, until wlcs_pair_destroy. */
 typedef struct wlcs_pair wlcs_pair;
 
 /* Copy host strings x (m bytes) and y (n bytes) to the device and encode them
@@ -125,8 +125,11 @@ typedef struct wlcs_pair wlcs_pair;
 int wlcs_pair_create(wlcs_ctx *ctx, const uint8_t *x, int64_t m, const uint8_t *y, int64_t n,
                      const uint8_t *alphabet, int32_t sigma, void *stream, wlcs_pair **out);
 
-/* Free a pair's device memory (waits for the device to finish using it).
- * NULL is accepted. */
+/* Release a pair's device memory in stream order on its creation stream
+ * (no device-wide wait): work already enqueued on that stream still sees the
+ * codes; work on other streams that uses the pair must have completed, or be
+ * ordered before this point of the creation stream, and the creation stream
+ * must still exist.  NULL is accepted. */
 int wlcs_pair_destroy(wlcs_pair *pair);
 
 /* wlcs_plot / wlcs_plot_dp on a resident pair: same window, output, flag and

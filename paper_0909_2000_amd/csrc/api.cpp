@@ -286,6 +286,7 @@ int plot_common(Path path, wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uin
 // A device-resident, encoded pair of strings.
 struct wlcs_pair {
     int device = 0;
+    hipStream_t stream = nullptr;  // creation stream: the codes are allocated and freed in its order
     int64_t m = 0, n = 0;
     uint16_t* xf = nullptr;  // capacity xf_cap
     uint16_t* yg = nullptr;  // capacity yg_cap
@@ -537,8 +538,9 @@ int wlcs_pair_create(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* 
     // room for any window (<= 256 capacity) and any tile (<= kMaxTile)
     pr->xf_cap = m + 64 + 256 + 64;
     pr->yg_cap = n + 2 * (int64_t)kMaxTile + 128 + 256 + 64;
-    hipError_t e = hipMalloc((void**)&pr->xf, (size_t)pr->xf_cap * 2);
-    if (e == hipSuccess) e = hipMalloc((void**)&pr->yg, (size_t)pr->yg_cap * 2);
+    pr->stream = stream;
+    hipError_t e = hipMallocAsync((void**)&pr->xf, (size_t)pr->xf_cap * 2, stream);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&pr->yg, (size_t)pr->yg_cap * 2, stream);
     if (e != hipSuccess) {
         wlcs_pair_destroy(pr);
         return fail(ctx, e);
@@ -564,8 +566,9 @@ int wlcs_pair_destroy(wlcs_pair* pair) {
     if (!pair) return WLCS_OK;
     DeviceGuard guard(pair->device);
     int st = WLCS_OK;
-    if (pair->xf && hipFree(pair->xf) != hipSuccess) st = WLCS_EHIP;
-    if (pair->yg && hipFree(pair->yg) != hipSuccess) st = WLCS_EHIP;
+    // stream-ordered release on the creation stream: no device-wide wait
+    if (pair->xf && hipFreeAsync(pair->xf, pair->stream) != hipSuccess) st = WLCS_EHIP;
+    if (pair->yg && hipFreeAsync(pair->yg, pair->stream) != hipSuccess) st = WLCS_EHIP;
     delete pair;
     return st;
 }

@@ -1,0 +1,256 @@
+"""Serving loop for alignment-plot jobs: admission by HBM footprint and
+continuous batching.
+
+A job is one plot request (strings x and y, window w, alphabet, bitmap
+threshold, optional indel output).  The server keeps a FIFO of waiting jobs
+and admits the head while its device footprint (resident letter codes plus
+its outputs) fits the memory budget and a job slot is free.  Admitted jobs
+are launched together as one batch (one persistent work-stealing launch,
+``wlcs_batch``) on one of several streams, so jobs that arrive while earlier
+batches run start on a free stream and overlap them on the device; a batch's
+completion frees its footprint and slots, which admits more jobs.  Latency is
+measured from a job's arrival to the completion of its batch on the device.
+
+The scheduler only talks to an executor: ``GpuExecutor`` drives the library on
+one GPU; the tests use a fake executor with a virtual clock to check
+admission, ordering and continuous admission without a GPU.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Padding the library allocates per resident pair (letter codes, in bytes):
+# x gets 384 extra 16-bit codes and y two maximal tiles plus a window.
+PAIR_PAD_BYTES = 2 * (384 + 2 * 32768 + 448)
+
+
+@dataclass
+class Request:
+    jid: int
+    x: np.ndarray
+    y: np.ndarray
+    w: int
+    alphabet: bytes
+    threshold: int | None = None
+    indel: bool = True
+    want_plot: bool = False
+    arrival: float = 0.0       # seconds on the server's clock
+
+
+@dataclass
+class JobState:
+    req: Request
+    admitted: float = -1.0
+    launched: float = -1.0
+    done: float = -1.0
+    footprint: int = 0
+    results: dict | None = None
+    batch_id: int = -1
+
+
+def windows(length: int, w: int) -> int:
+    return max(length - w, 0)
+
+
+def footprint_bytes(req: Request) -> int:
+    """HBM a job holds while admitted: its resident codes and its outputs."""
+    rows, cols = windows(req.x.size, req.w), windows(req.y.size, req.w)
+    b = 2 * (req.x.size + req.y.size) + PAIR_PAD_BYTES
+    if req.want_plot:
+        b += rows * cols
+    if req.threshold is not None:
+        b += rows * ((cols + 63) // 64) * 8
+    if req.indel:
+        b += rows * cols * 2
+    return b
+
+
+class GpuExecutor:
+    """Runs batches on one GPU through libwlcs, one stream per concurrent batch."""
+
+    def __init__(self, device: int = 0, streams: int = 3, ctx=None):
+        import torch
+
+        import paper_0909_2000_amd as wl
+        self.torch, self.wl = torch, wl
+        self.dev = torch.device("cuda", device)
+        self.ctx = ctx or wl.Context(device)
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
+        self.busy = [None] * streams  # per stream: (event, batch_id) or None
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def free_stream(self):
+        for k, b in enumerate(self.busy):
+            if b is None:
+                return k
+        return None
+
+    def launch(self, batch_id: int, jobs: list) -> None:
+        k = self.free_stream()
+        s = self.streams[k]
+        specs = []
+        for js in jobs:
+            r = js.req
+            pair = self.ctx.pair(r.x, r.y, alphabet=r.alphabet, stream=s)
+            specs.append({"pair": pair, "w": r.w, "threshold": r.threshold, "indel": r.indel,
+                          "want_plot": r.want_plot})
+        with self.torch.cuda.stream(s):
+            results = self.ctx.batch(specs, stream=s)
+            ev = self.torch.cuda.Event()
+            ev.record(s)
+        for js, res, sp in zip(jobs, results, specs):
+            js.results = res
+            js.results["_pair"] = sp["pair"]  # keeps the resident codes alive until the job is done
+        self.busy[k] = (ev, batch_id)
+
+    def poll(self) -> list:
+        """Batch ids whose work has finished on the device."""
+        done = []
+        for k, b in enumerate(self.busy):
+            if b is not None and b[0].query():
+                done.append(b[1])
+                self.busy[k] = None
+        return done
+
+    def idle_wait(self):
+        time.sleep(20e-6)
+
+
+class Server:
+    def __init__(self, executor, budget_bytes: int, max_jobs: int = 256, max_batch: int = 64,
+                 keep_results: bool = True):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_jobs = max_jobs
+        self.max_batch = max_batch
+        self.keep = keep_results
+        self.waiting: collections.deque = collections.deque()
+        self.admitted: list = []           # admitted, not yet launched
+        self.running: dict = {}            # batch_id -> list of JobState
+        self.jobs: dict = {}
+        self.in_use = 0                    # bytes held by admitted or running jobs
+        self.active = 0                    # jobs admitted or running
+        self.peak_use = 0
+        self.next_batch = 0
+        self.rejected: list = []
+        self.admit_log: list = []          # (time, jid) in admission order
+        self.overlaps = 0                  # launches made while another batch ran
+
+    # -- client side -----------------------------------------------------
+    def submit(self, req: Request) -> int:
+        js = JobState(req, footprint=footprint_bytes(req))
+        self.jobs[req.jid] = js
+        if js.footprint > self.budget:
+            js.done = self.ex.now()
+            self.rejected.append(req.jid)  # can never fit
+        else:
+            self.waiting.append(js)
+        return req.jid
+
+    def poll(self, jid: int) -> bool:
+        return self.jobs[jid].done >= 0
+
+    def result(self, jid: int) -> dict | None:
+        return self.jobs[jid].results
+
+    # -- scheduler -------------------------------------------------------
+    def _reap(self):
+        for bid in self.ex.poll():
+            now = self.ex.now()
+            for js in self.running.pop(bid):
+                js.done = now
+                self.in_use -= js.footprint
+                self.active -= 1
+                if not self.keep:
+                    js.results = None
+
+    def _admit(self):
+        while self.waiting and self.active < self.max_jobs:
+            head = self.waiting[0]
+            if self.in_use + head.footprint > self.budget:
+                break  # FIFO: the head waits for memory, nobody overtakes it
+            self.waiting.popleft()
+            head.admitted = self.ex.now()
+            self.in_use += head.footprint
+            self.active += 1
+            self.peak_use = max(self.peak_use, self.in_use)
+            self.admitted.append(head)
+            self.admit_log.append((head.admitted, head.req.jid))
+
+    def _launch(self):
+        while self.admitted and self.ex.free_stream() is not None:
+            batch, self.admitted = self.admitted[:self.max_batch], self.admitted[self.max_batch:]
+            bid = self.next_batch
+            self.next_batch += 1
+            if self.running:
+                self.overlaps += 1
+            now = self.ex.now()
+            for js in batch:
+                js.launched = now
+                js.batch_id = bid
+            self.running[bid] = batch
+            self.ex.launch(bid, batch)
+
+    def step(self):
+        self._reap()
+        self._admit()
+        self._launch()
+
+    def busy(self) -> bool:
+        return bool(self.waiting or self.admitted or self.running)
+
+    def run(self, requests: list) -> dict:
+        """Feed requests at their arrival times (server clock) until all are done."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        k = 0
+        while k < len(reqs) or self.busy():
+            now = self.ex.now()
+            while k < len(reqs) and reqs[k].arrival <= now:
+                self.submit(reqs[k])
+                k += 1
+            self.step()
+            if hasattr(self.ex, "advance"):
+                nxt = reqs[k].arrival if k < len(reqs) else None
+                self.ex.advance(nxt)
+            elif k < len(reqs) and not self.busy():
+                time.sleep(max(0.0, min(reqs[k].arrival - self.ex.now(), 1e-3)))
+            else:
+                self.ex.idle_wait()
+        return self.report()
+
+    def report(self) -> dict:
+        lat = np.array([js.done - js.req.arrival for js in self.jobs.values()
+                        if js.done >= 0 and js.req.jid not in self.rejected])
+        first = min((js.req.arrival for js in self.jobs.values()), default=0.0)
+        last = max((js.done for js in self.jobs.values()), default=0.0)
+        cells = sum(float(js.req.x.size) * js.req.y.size * js.req.w for js in self.jobs.values()
+                    if js.req.jid not in self.rejected)
+        span = max(last - first, 1e-9)
+        return {
+            "jobs": len(self.jobs), "rejected": len(self.rejected),
+            "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
+            "mean_s": float(lat.mean()) if lat.size else None,
+            "span_s": span, "jobs_per_s": (len(self.jobs) - len(self.rejected)) / span,
+            "window_cells_per_s": cells / span, "batches": self.next_batch,
+            "overlapped_launches": self.overlaps, "peak_bytes": self.peak_use,
+            "budget_bytes": self.budget,
+        }
+
+
+def requests_from_workload(jobs, rate_scale: float = 1.0, want_plot: bool = False) -> list:
+    """Turn workloads.serving_jobs() into Requests; arrival times are divided
+    by rate_scale (so rate_scale > 1 compresses the stream)."""
+    out = []
+    for j in jobs:
+        p = j.pair
+        out.append(Request(j.jid, p.x, p.y, p.w, p.alphabet, threshold=j.threshold, indel=True,
+                           want_plot=want_plot, arrival=j.arrival / rate_scale))
+    return out

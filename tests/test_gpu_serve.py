@@ -1,0 +1,54 @@
+"""GPU: the serving loop with the real executor.  Jobs arrive faster than the
+device drains them, so batches overlap on several streams; every job's bitmap
+and indel outputs must equal the same job plotted alone (bit-exact), and the
+oracle on a sample; the memory budget must hold."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def test_serving_results_equal_alone(oracle_mod):
+    import torch
+    import paper_0909_2000_amd as wl
+    from paper_0909_2000_amd import serve
+
+    g = workloads.rng(31)
+    reqs = []
+    t = 0.0
+    for k in range(48):
+        t += float(g.exponential(1.0 / 4000.0))
+        protein = k % 2 == 1
+        alpha = workloads.PROTEIN if protein else workloads.DNA
+        w = int((16, 32, 64, 128)[k % 4])
+        m, n = int(g.integers(200, 2500)) + w, int(g.integers(200, 2500)) + w
+        x, y = workloads.iid(g, m, alpha), workloads.iid(g, n, alpha)
+        reqs.append(serve.Request(k, x, y, w, alpha, threshold=(3 * w + 3) // 4, indel=True,
+                                  want_plot=(k % 5 == 0), arrival=t))
+    budget = 12 * max(serve.footprint_bytes(r) for r in reqs)
+    ctx = wl.Context(0)
+    ex = serve.GpuExecutor(0, streams=3, ctx=ctx)
+    srv = serve.Server(ex, budget_bytes=budget, max_jobs=24, max_batch=6, keep_results=True)
+    rep = srv.run(reqs)
+    torch.cuda.synchronize()
+    print("serving report", rep, flush=True)
+    sys.stdout.flush()
+    assert rep["rejected"] == 0
+    assert srv.peak_use <= budget
+    assert rep["batches"] > 1
+    for r in reqs:
+        res = srv.result(r.jid)
+        alone = ctx.plot(r.x, r.y, r.w, alphabet=r.alphabet, threshold=r.threshold, indel=True,
+                         want_plot=r.want_plot)
+        assert torch.equal(res["bitmap"], alone["bitmap"]), r.jid
+        assert torch.equal(res["indel"], alone["indel"]), r.jid
+        if r.want_plot:
+            assert torch.equal(res["wlcs"], alone["wlcs"]), r.jid
+    for r in reqs[:6]:
+        want = oracle_mod.wlcs(r.x, r.y, r.w)
+        np.testing.assert_array_equal(srv.result(r.jid)["indel"].cpu().numpy().view(np.uint16),
+                                      oracle_mod.indel(want, r.w))

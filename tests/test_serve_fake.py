@@ -1,0 +1,149 @@
+"""Serving scheduler on the CPU, with a fake executor on a virtual clock.
+
+The fake executor runs each batch for a time proportional to its window-cells
+and computes every job's outputs with the oracle, so these tests check the
+scheduler itself: the memory budget is never exceeded, admission is FIFO,
+jobs are admitted and launched while earlier batches still run, a job's
+result in the mix equals the job computed alone, and impossible jobs are
+rejected.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from paper_0909_2000_amd import serve
+
+
+class FakeExecutor:
+    def __init__(self, oracle, streams=2, rate=2e6, overhead=1e-3):
+        self.oracle = oracle
+        self.t = 0.0
+        self.busy = [None] * streams
+        self.rate, self.overhead = rate, overhead
+        self.launch_log = []  # (time, batch_id, running batch ids at launch)
+
+    def now(self):
+        return self.t
+
+    def free_stream(self):
+        for k, b in enumerate(self.busy):
+            if b is None:
+                return k
+        return None
+
+    def launch(self, batch_id, jobs):
+        k = self.free_stream()
+        assert k is not None
+        running = [b[1] for b in self.busy if b is not None]
+        cells = sum(float(j.req.x.size) * j.req.y.size * j.req.w for j in jobs)
+        self.busy[k] = (self.t + self.overhead + cells / self.rate, batch_id)
+        self.launch_log.append((self.t, batch_id, running))
+        for j in jobs:
+            r = j.req
+            plot = self.oracle.wlcs(r.x, r.y, r.w)
+            res = {}
+            if r.want_plot:
+                res["wlcs"] = plot
+            if r.threshold is not None:
+                res["bitmap"] = self.oracle.dot_bitmap(plot, r.threshold)
+            if r.indel:
+                res["indel"] = self.oracle.indel(plot, r.w)
+            j.results = res
+
+    def poll(self):
+        done = []
+        for k, b in enumerate(self.busy):
+            if b is not None and b[0] <= self.t + 1e-12:
+                done.append(b[1])
+                self.busy[k] = None
+        return done
+
+    def advance(self, next_arrival):
+        fins = [b[0] for b in self.busy if b is not None]
+        cands = fins + ([next_arrival] if next_arrival is not None else [])
+        if cands:
+            self.t = max(self.t, min(cands))
+
+    def idle_wait(self):
+        pass
+
+
+def _requests(n, seed, rate, lo=20, hi=120):
+    g = workloads.rng(seed)
+    t = 0.0
+    out = []
+    for k in range(n):
+        t += float(g.exponential(1.0 / rate))
+        w = int(g.choice([4, 8, 16]))
+        m, n_ = int(g.integers(lo, hi)) + w, int(g.integers(lo, hi)) + w
+        x, y = workloads.iid(g, m, workloads.DNA), workloads.iid(g, n_, workloads.DNA)
+        out.append(serve.Request(k, x, y, w, workloads.DNA, threshold=(3 * w + 3) // 4, indel=True,
+                                 arrival=t))
+    return out
+
+
+def test_budget_fifo_and_overlap(oracle_mod):
+    reqs = _requests(60, 1, rate=400.0)
+    budget = 6 * max(serve.footprint_bytes(r) for r in reqs)
+    ex = FakeExecutor(oracle_mod, streams=2)
+    srv = serve.Server(ex, budget_bytes=budget, max_jobs=10, max_batch=4)
+    rep = srv.run(reqs)
+    assert rep["rejected"] == 0 and rep["jobs"] == 60
+    assert srv.peak_use <= budget
+    # FIFO: admitted in arrival order
+    order = [jid for _, jid in srv.admit_log]
+    assert order == sorted(order)
+    # continuous batching: some batch was launched while another was running
+    assert any(running for _, _, running in ex.launch_log)
+    assert srv.overlaps > 0
+    # every job finished after it arrived, latencies are reported
+    for js in srv.jobs.values():
+        assert js.done >= js.launched >= js.admitted >= js.req.arrival
+    assert rep["p99_s"] >= rep["p50_s"] > 0
+
+
+def test_results_in_mix_equal_alone(oracle_mod):
+    reqs = _requests(25, 2, rate=1000.0)
+    srv = serve.Server(FakeExecutor(oracle_mod, streams=3), budget_bytes=1 << 40, max_batch=5)
+    srv.run(reqs)
+    for r in reqs:
+        alone = oracle_mod.wlcs(r.x, r.y, r.w)
+        res = srv.result(r.jid)
+        np.testing.assert_array_equal(res["bitmap"], oracle_mod.dot_bitmap(alone, r.threshold))
+        np.testing.assert_array_equal(res["indel"], oracle_mod.indel(alone, r.w))
+
+
+def test_memory_pressure_holds_the_head(oracle_mod):
+    # a budget that fits one job at a time: batches of one, strictly in order
+    reqs = _requests(8, 3, rate=1e6)
+    budget = max(serve.footprint_bytes(r) for r in reqs)
+    ex = FakeExecutor(oracle_mod, streams=4)
+    srv = serve.Server(ex, budget_bytes=budget)
+    srv.run(reqs)
+    assert srv.peak_use <= budget
+    launches = sorted(srv.jobs.values(), key=lambda js: js.launched)
+    assert [js.req.jid for js in launches] == list(range(8))
+    # no two jobs were ever on the device together
+    spans = sorted((js.launched, js.done) for js in srv.jobs.values())
+    for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
+        assert b0 >= a1 - 1e-12
+
+
+def test_oversized_job_is_rejected(oracle_mod):
+    reqs = _requests(5, 4, rate=100.0)
+    big = serve.Request(99, workloads.iid(workloads.rng(5), 5000, workloads.DNA),
+                        workloads.iid(workloads.rng(6), 5000, workloads.DNA), 16, workloads.DNA,
+                        threshold=12, arrival=0.001)
+    budget = serve.footprint_bytes(big) - 1
+    srv = serve.Server(FakeExecutor(oracle_mod), budget_bytes=budget)
+    rep = srv.run(reqs + [big])
+    assert rep["rejected"] == 1 and 99 in srv.rejected
+    assert all(srv.poll(r.jid) for r in reqs)
+
+
+def test_footprint_formula():
+    r = serve.Request(0, np.zeros(1000, np.uint8), np.zeros(2000, np.uint8), 64, b"A", threshold=48,
+                      indel=True, want_plot=True)
+    rows, cols = 936, 1936
+    want = 2 * 3000 + serve.PAIR_PAD_BYTES + rows * cols + rows * ((cols + 63) // 64) * 8 + rows * cols * 2
+    assert serve.footprint_bytes(r) == want
