@@ -38,6 +38,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the timed kernel, from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs, each scaled by what the same counter read for
+    a plain 1 GiB device copy; None when the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"seaweed_counters_{workload.replace('-planted', '')}.json")
+    if not os.path.exists(path):
+        return None, None
+    with open(path) as f:
+        d = json.load(f)
+    h = hashlib.sha1()
+    for fn in d["digest_files"]:
+        with open(os.path.join(ROOT, fn), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != d["kernel_digest"]:
+        return None, {"stale": True, "source": os.path.relpath(path, ROOT)}
+    fetch = sum(d["fetch_kib_per_dispatch"]) / len(d["fetch_kib_per_dispatch"]) * 1024
+    write = sum(d["write_kib_per_dispatch"]) / len(d["write_kib_per_dispatch"]) * 1024
+    f_scale = d["copy_fetch_kib"] * 1024 / d["copy_bytes"]
+    w_scale = d["copy_write_kib"] * 1024 / d["copy_bytes"]
+    detail = {"read_bytes": fetch / f_scale, "write_bytes": write / w_scale,
+              "fetch_scale": f_scale, "write_scale": w_scale,
+              "source": os.path.relpath(path, ROOT)}
+    return detail["read_bytes"] + detail["write_bytes"], detail
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +79,8 @@ def main():
     ap.add_argument("--serving-jobs", type=int, default=2000)
     ap.add_argument("--serving-load", type=float, default=0.7, help="arrival rate / measured capacity")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving HBM budget")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -112,11 +140,22 @@ def main():
     value = nominal / (ms_per_step / 1e3)
     log(f"seaweed: {ms_per_step:.3f} ms/step, {value:.3e} window-cells/s")
 
+    if args.calib_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy: 1 GiB read + 1 GiB written")
+
     avg_kernel_ms = float(np.mean(kern_ms))
     cells = float(rows) * n * w  # cells the method combs: m-w strips of w x n
     achieved = cells * OPS_PER_CELL / (avg_kernel_ms / 1e3)
+    traffic, traffic_detail = measured_traffic(p.name)
+    algo_bytes = float(m + n) * 2 + float(rows) * cols + (float(rows) * ((cols + 63) // 64) * 8 if thr else 0)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_U16_OPS / 1e12,
-                "unit": "TOP/s", "frac": achieved / PEAK_U16_OPS, "traffic": None,
+                "unit": "TOP/s", "frac": achieved / PEAK_U16_OPS, "traffic": traffic,
+                "traffic_detail": traffic_detail, "algorithmic_bytes": algo_bytes,
                 "ops_per_cell": OPS_PER_CELL, "cells_per_launch": cells,
                 "avg_launch_ms": avg_kernel_ms}
 
@@ -201,11 +240,17 @@ def bench_batch(ctx, torch, workloads, reps=3):
     """256 DNA pairs of uneven m, n and w in one persistent launch (eager and
     graph-replayed), outputs preallocated, pairs resident."""
     import numpy as np
+    from paper_0909_2000_amd import autotune
     pairs = workloads.batch_config()
     specs = [{"pair": ctx.pair(p.x, p.y), "w": p.w} for p in pairs]
+    cache = autotune.load(os.path.join(ROOT, "paper_0909_2000_amd", "tuning_gfx950.json"), torch)
     res = ctx.batch(specs)  # allocates the outputs once (and warms up)
     for sp, r in zip(specs, res):
         sp["out"] = r["wlcs"]
+    default_ms = None
+    if cache:
+        default_ms = float(np.median([_timed_once(torch, lambda: ctx.batch(specs)) for _ in range(3)]))
+        autotune.apply(ctx, cache)
     graph = ctx.batch_graph(specs)
     graph.launch()
     torch.cuda.synchronize()
@@ -227,11 +272,23 @@ def bench_batch(ctx, torch, workloads, reps=3):
     nominal = sum(float(p.m) * p.n * p.w for p in pairs)
     graph.close()
     out = {"pairs": len(pairs), "window_cells": nominal, "ms": eager_ms, "graph_ms": graph_ms,
+           "tuned": bool(cache), "untuned_ms": default_ms,
+           "tuning": {k: cache[k] for k in ("batch_tiles", "batch_grid")} if cache else None,
            "value": nominal / (eager_ms / 1e3), "graph_value": nominal / (graph_ms / 1e3),
            "unit": "window-cells/s", "workload": "256 iid DNA pairs, m,n ~ U[1000,20000], w ~ {16,32,64,128}"}
     del specs, res
     torch.cuda.empty_cache()
     return out
+
+
+def _timed_once(torch, fn):
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
 
 
 def bench_serving(ctx, torch, workloads, args):
