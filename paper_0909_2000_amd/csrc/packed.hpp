@@ -104,6 +104,30 @@ __device__ __forceinline__ uint32_t dp_cell(uint32_t up, uint32_t left, uint32_t
     return v;
 }
 
+// Per half: 1 if p < w (unsigned), else 0 -- min(sat(w - p), 1).  Written as
+// two packed instructions (the compiler would otherwise split the halves).
+__device__ __forceinline__ uint32_t pk_below(uint32_t w2, uint32_t p2, uint32_t one2) {
+    uint32_t v;
+    asm("v_pk_sub_u16 %0, %1, %2 clamp\n\tv_pk_min_u16 %0, %0, %3" : "=&v"(v) : "v"(w2), "v"(p2), "v"(one2));
+    return v;
+}
+
+// Per half: val << (amount & 15), one v_pk_lshlrev_b16.
+__device__ __forceinline__ uint32_t pk_lshl(uint32_t amount, uint32_t val) {
+    uint32_t r;
+    asm("v_pk_lshlrev_b16 %0, %1, %2" : "=v"(r) : "v"(amount), "v"(val));
+    return r;
+}
+
+// A wave-uniform pointer, forced into scalar registers.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (T*)(((uint64_t)hi << 32) | lo);
+}
+
 // 16-bit element i of a wave-uniform array, through a 32-bit (scalar) load
 __device__ __forceinline__ uint32_t u16_at(const uint32_t* __restrict__ p, int64_t i) {
     return (p[i >> 1] >> ((uint32_t)(i & 1) * 16u)) & 0xFFFFu;

@@ -53,7 +53,18 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     uint32_t ring_pf = 0;
     const uint32_t w2 = pk_rep(w);
 
-    auto yload = [&](int l) -> uint32_t { return u16_at(yg32, tA + l) | (u16_at(yg32, tB + l) << 16); };
+    // y codes of the two tiles (tile starts are multiples of 64, so both
+    // bases are dword aligned); the index is wave-uniform, so the loads and
+    // the unpacking stay on the scalar unit
+    const uint32_t* __restrict__ yA = uniform_ptr(yg32 + (tA >> 1));
+    const uint32_t* __restrict__ yB = uniform_ptr(yg32 + (tB >> 1));
+    auto yload = [&](int l) -> uint32_t {
+        const int q = __builtin_amdgcn_readfirstlane(l >> 1);
+        const uint32_t sh = (uint32_t)__builtin_amdgcn_readfirstlane(l & 1) * 16u;
+        const uint32_t a = yA[q], b = yB[q];
+        return ((a >> sh) & 0xFFFFu) | (((b >> sh) & 0xFFFFu) << 16);
+    };
+    const uint32_t one2 = 0x00010001u;
     uint32_t ynext = yload(0);
 
     // Comb column l (tile-relative) through the w rows and update the sliding
@@ -78,9 +89,9 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         }
         // p = start - (l - w + 1) lies in [0, w) iff the exit's span is below w
         const uint32_t p2 = pk_sub(t, pk_rep(l - org + 2 - w));
-        const uint32_t v2 = pk_min(pk_sub_sat(w2, p2), 0x00010001u);
+        const uint32_t v2 = pk_below(w2, p2, one2);
         const uint32_t pos2 = pk_add(p2, pk_rep(l - w + 1));
-        const uint32_t bit2 = pk_shl(v2, pos2);
+        const uint32_t bit2 = pk_lshl(pos2, v2);
         const uint32_t wlo = (pos2 >> 4) & (RW - 1), whi = (pos2 >> 20) & (RW - 1);
         atomicOr(&ring[wlo * 64 + lane], bit2 & 0xFFFFu);
         atomicOr(&ring[whi * 64 + lane], bit2 & 0xFFFF0000u);
