@@ -79,6 +79,10 @@ def main():
     ap.add_argument("--serving-jobs", type=int, default=2000)
     ap.add_argument("--serving-load", type=float, default=0.7, help="arrival rate / measured capacity")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving HBM budget")
+    ap.add_argument("--row-align", type=int, default=64,
+                    help="row stride of the timed plot rounded up to this many bytes")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other single-pair configurations (1k DNA w16, 30k protein w128)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -111,7 +115,10 @@ def main():
     pair = ctx.pair(p.x, p.y, alphabet=p.alphabet)
     torch.cuda.synchronize()
     encode_ms = (time.perf_counter() - t0) * 1e3
-    out = torch.empty((rows, cols), dtype=torch.uint8, device=dev)
+    # plot rows padded to whole 64-byte sectors (a pitched layout; the plot
+    # itself is out[:, :cols])
+    ld = (cols + args.row_align - 1) // args.row_align * args.row_align
+    out = torch.empty((rows, ld), dtype=torch.uint8, device=dev)[:, :cols]
     thr = p.threshold
     bm = torch.empty((rows, (cols + 63) // 64), dtype=torch.int64, device=dev) if thr else None
 
@@ -205,6 +212,15 @@ def main():
                          f"{cols} y-windows, plain per-window DP, {cpu_s:.1f} s"}
         log(f"CPU oracle: {cpu['value']:.3e} window-cells/s on {threads} threads")
 
+    others = None
+    if not args.no_configs:
+        others = {}
+        for k in (1, 3):
+            if WORKLOADS[args.workload] == k:
+                continue  # already the headline workload
+            others[workloads.config(k).name] = bench_config(ctx, torch, workloads, oracle, k)
+            log(f"config {k}: {others[workloads.config(k).name]}")
+
     batched = None
     if not args.no_batch:
         batched = bench_batch(ctx, torch, workloads)
@@ -222,11 +238,11 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16",
         "data": "synthetic",
-        "config": {"workload": p.name, "m": m, "n": n, "w": w, "rows": rows, "cols": cols,
+        "config": {"workload": p.name, "m": m, "n": n, "w": w, "rows": rows, "cols": cols, "ld": ld,
                    "threshold": thr, "outputs": "uint8 plot + bitmap" if thr else "uint8 plot",
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "gpu_dp_baseline": dp,
-        "batched": batched, "serving": serving,
+        "other_configs": others, "batched": batched, "serving": serving,
         "encode_ms": encode_ms, "parity_sampled_rows": parity,
         "kernel_ms": {"min": float(np.min(kern_ms)), "median": float(np.median(kern_ms)),
                       "max": float(np.max(kern_ms))},
@@ -279,6 +295,38 @@ def bench_batch(ctx, torch, workloads, reps=3):
     del specs, res
     torch.cuda.empty_cache()
     return out
+
+
+def bench_config(ctx, torch, workloads, oracle, k, steps=10):
+    """Seaweed plot and GPU DP on another single-pair configuration, with
+    parity against the oracle (whole plot for the small one, sampled rows
+    otherwise)."""
+    import numpy as np
+    p = workloads.config(k)
+    rows, cols = p.m - p.w, p.n - p.w
+    pair = ctx.pair(p.x, p.y, alphabet=p.alphabet)
+    out = torch.empty((rows, cols), dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        pair.plot(p.w, out=out)
+    ms = float(np.median([_timed_once(torch, lambda: pair.plot(p.w, out=out)) for _ in range(steps)]))
+    if rows * cols <= 2_000_000:
+        want = oracle.wlcs(p.x, p.y, p.w)
+        parity = bool(np.array_equal(out.cpu().numpy(), want))
+        sample = "whole plot"
+    else:
+        ids = np.array([0, rows // 2, rows - 1])
+        want = oracle.wlcs_rows(p.x, p.y, p.w, ids)
+        parity = bool(np.array_equal(out[torch.as_tensor(ids, device="cuda")].cpu().numpy(), want))
+        sample = "rows 0, mid, last"
+    dp_ms = _timed_once(torch, lambda: pair.plot_dp(p.w, out=out))
+    nominal = float(p.m) * p.n * p.w
+    cells = float(rows) * p.n * p.w
+    res = {"m": p.m, "n": p.n, "w": p.w, "ms": ms, "value": nominal / (ms / 1e3),
+           "unit": "window-cells/s", "roofline_frac": cells * OPS_PER_CELL / (ms / 1e3) / PEAK_U16_OPS,
+           "dp_ms": dp_ms, "dp_value": nominal / (dp_ms / 1e3), "speedup_over_dp": dp_ms / ms,
+           "parity": parity, "parity_sample": sample}
+    pair.close()
+    return res
 
 
 def _timed_once(torch, fn):

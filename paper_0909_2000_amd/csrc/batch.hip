@@ -26,7 +26,7 @@ __device__ __forceinline__ void run_unit(const JobDesc& jd, int64_t local, uint3
 __global__ __launch_bounds__(64, 2) void batch_kernel(const JobDesc* __restrict__ jobs, int32_t njobs,
                                                       int64_t total_units, unsigned long long* __restrict__ counter) {
     __shared__ uint32_t ring[ring_words(128) * 64];
-    __shared__ uint32_t stage[stage_dwords()];
+    __shared__ uint32_t stage[stage_dwords(128)];
     const int lane = threadIdx.x;
     for (;;) {
         uint32_t ulo = 0, uhi = 0;

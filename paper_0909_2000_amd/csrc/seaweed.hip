@@ -58,7 +58,7 @@ __global__ __launch_bounds__(64, min_waves_per_simd(WC)) void seaweed_kernel(con
                                                      uint32_t* __restrict__ bm32,
                                                      uint16_t* __restrict__ indel, Geom g) {
     __shared__ uint32_t ring[ring_words(WC) * 64];
-    __shared__ uint32_t stage[stage_dwords()];
+    __shared__ uint32_t stage[stage_dwords(WC)];
     const int64_t unit = blockIdx.x;
     const int64_t sb = unit / g.npairs;
     const int pr = (int)(unit - sb * g.npairs);

@@ -9,12 +9,17 @@
 
 namespace wlcs {
 
-constexpr int kStagePitch = 9;  // dwords per lane row of the staging buffer (8 + 1 pad)
+// Windows staged per lane before a flush: 64 (64-byte row segments) where
+// the LDS budget allows it at the class's occupancy, else 32.
+constexpr int flush_windows(int wc) { return wc >= 64 ? 64 : 32; }
+// dwords per lane row of the staging buffer (one per 4 windows, plus a pad
+// dword that spreads the lanes over the LDS banks)
+constexpr int stage_pitch(int wc) { return flush_windows(wc) / 4 + 1; }
 // LDS ring words (16 start columns each) per lane: the ring must cover the
 // w + 1 start columns that can be pending at once, with a margin that keeps
 // the word being cleared apart from the newest marks.
 constexpr int ring_words(int wc) { return wc <= 128 ? 16 : 32; }
-constexpr int stage_dwords() { return 2 * 64 * kStagePitch; }
+constexpr int stage_dwords(int wc) { return 2 * 64 * stage_pitch(wc); }
 // Occupancy each window class is compiled for (waves per SIMD): the w labels
 // and w/2 code registers per lane plus the flush temporaries must fit.
 constexpr int min_waves_per_simd(int wc) { return wc <= 32 ? 4 : wc <= 64 ? 3 : wc <= 128 ? 2 : 1; }
@@ -25,6 +30,8 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                                           uint16_t* __restrict__ indel, const Geom& g, int64_t sb, int pr,
                                           uint32_t* __restrict__ ring, uint32_t* __restrict__ stage) {
     constexpr int RW = ring_words(WC);
+    constexpr int FL = flush_windows(WC);
+    constexpr int PITCH = stage_pitch(WC);
     const int lane = threadIdx.x & 63;
     const int64_t s0 = sb * 64;
     const int64_t tA = (int64_t)(2 * pr) * g.tile;
@@ -104,9 +111,9 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     for (int l = 0; l < w - 1; ++l) (void)column(l);
 
     const uint32_t bm_words = (uint32_t)(((g.cols + 63) >> 6) * 2);
-    for (int jb = 0; jb < nproc; jb += 32) {
+    for (int jb = 0; jb < nproc; jb += FL) {
 #pragma unroll 1
-        for (int gi = 0; gi < 8; ++gi) {
+        for (int gi = 0; gi < FL / 4; ++gi) {
             const int jj = jb + 4 * gi;
             if (jj > 0 && (jj % kRebase) == 0) {
                 const int32_t norg = jj - 1;  // (column jj + w - 1) - w
@@ -123,8 +130,8 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
             const uint32_t wa = (r0 & 0xFFu) | ((r1 & 0xFFu) << 8) | ((r2 & 0xFFu) << 16) | ((r3 & 0xFFu) << 24);
             const uint32_t wb = ((r0 >> 16) & 0xFFu) | (((r1 >> 16) & 0xFFu) << 8) |
                                 (((r2 >> 16) & 0xFFu) << 16) | (((r3 >> 16) & 0xFFu) << 24);
-            stage[lane * kStagePitch + gi] = wa;
-            stage[64 * kStagePitch + lane * kStagePitch + gi] = wb;
+            stage[lane * PITCH + gi] = wa;
+            stage[64 * PITCH + lane * PITCH + gi] = wb;
         }
         __syncthreads();
         const int64_t s = s0 + lane;  // this lane's strip
@@ -135,44 +142,54 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
             const int64_t j0 = ts + jb;
             // windows of this block inside the tile (0 for the padding block
             // that completes the last bitmap word, or past the end of y)
-            const int nvalid = (int)(te - j0 < 32 ? (te - j0 > 0 ? te - j0 : 0) : 32);
+            const int nvalid = (int)(te - j0 < FL ? (te - j0 > 0 ? te - j0 : 0) : FL);
             if (nvalid == 0 && (uint32_t)(j0 >> 5) >= bm_words) continue;  // uniform
-            uint32_t d[8];
+            uint32_t d[FL / 4];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) d[k] = stage[half * 64 * kStagePitch + lane * kStagePitch + k];
+            for (int k = 0; k < FL / 4; ++k) d[k] = stage[half * 64 * PITCH + lane * PITCH + k];
             if (out && g.wmode > 0 && nvalid > 0) {
                 if (s < g.rows) {
                     uint8_t* row = out + s * g.ld + j0;
-                    if (nvalid == 32) {
+                    if (nvalid == FL) {
                         if (g.wmode == 2) {
-                            ((uint4*)row)[0] = make_uint4(d[0], d[1], d[2], d[3]);
-                            ((uint4*)row)[1] = make_uint4(d[4], d[5], d[6], d[7]);
+#pragma unroll
+                            for (int k = 0; k < FL / 16; ++k)
+                                ((uint4*)row)[k] = make_uint4(d[4 * k], d[4 * k + 1], d[4 * k + 2], d[4 * k + 3]);
                         } else {
 #pragma unroll
-                            for (int k = 0; k < 8; ++k) ((uint32_t*)row)[k] = d[k];
+                            for (int k = 0; k < FL / 4; ++k) ((uint32_t*)row)[k] = d[k];
                         }
                     } else {
                         for (int b = 0; b < nvalid; ++b) row[b] = (uint8_t)(d[b >> 2] >> (8 * (b & 3)));
                     }
                 }
             }
-            if (bm32 && s < g.rows && (uint32_t)(j0 >> 5) < bm_words) {
-                uint32_t bits = 0;
+            if (bm32 && s < g.rows) {
 #pragma unroll
-                for (int b = 0; b < 32; ++b)
-                    bits |= (uint32_t)((int)((d[b >> 2] >> (8 * (b & 3))) & 0xFFu) >= g.threshold) << b;
-                if (nvalid < 32) bits &= nvalid ? (0xFFFFFFFFu >> (32 - nvalid)) : 0u;
-                bm32[s * g.ld_words32 + (j0 >> 5)] = bits;
+                for (int sub = 0; sub < FL / 32; ++sub) {
+                    const uint32_t wi = (uint32_t)(j0 >> 5) + sub;
+                    if (wi < bm_words) {
+                        const int nv = nvalid - 32 * sub;
+                        uint32_t bits = 0;
+#pragma unroll
+                        for (int b = 0; b < 32; ++b)
+                            bits |= (uint32_t)((int)((d[8 * sub + (b >> 2)] >> (8 * (b & 3))) & 0xFFu) >= g.threshold)
+                                    << b;
+                        if (nv < 32) bits &= nv > 0 ? (0xFFFFFFFFu >> (32 - nv)) : 0u;
+                        bm32[s * g.ld_words32 + wi] = bits;
+                    }
+                }
             }
             if (((out && g.wmode == 0) || indel) && nvalid > 0) {
-                // transposed: lanes cover 32 windows of two strips per step
-                const int q = lane & 31;
+                // transposed: the lanes cover FL windows of 64 / FL strips per step
+                constexpr int RPI = 64 / FL;
+                const int q = lane % FL;
                 const uint8_t* sbytes = (const uint8_t*)stage;
 #pragma unroll 4
-                for (int it = 0; it < 32; ++it) {
-                    const int r = 2 * it + (lane >> 5);
+                for (int it = 0; it < 64 / RPI; ++it) {
+                    const int r = RPI * it + lane / FL;
                     const int64_t sr = s0 + r;
-                    const uint32_t v = sbytes[(half * 64 * kStagePitch + r * kStagePitch) * 4 + q];
+                    const uint32_t v = sbytes[(half * 64 * PITCH + r * PITCH) * 4 + q];
                     if (sr < g.rows && q < nvalid) {
                         if (out && g.wmode == 0) out[sr * g.ld + j0 + q] = (uint8_t)v;
                         if (indel) indel[sr * g.ld_indel + j0 + q] = (uint16_t)(2 * w - 2 * (int)v);
