@@ -55,6 +55,14 @@ def _load():
         lib.oracle_wlcs_at.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, ctypes.c_int32,
                                        i64p, i64p, ctypes.c_int64, u8p]
         lib.oracle_wlcs_at.restype = ctypes.c_int
+        lib.oracle_score2.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_int32)]
+        lib.oracle_score2.restype = ctypes.c_int
+        lib.oracle_score_plot.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int8), ctypes.c_int64,
+                                          ctypes.c_int32]
+        lib.oracle_score_plot.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -158,3 +166,32 @@ def dot_bitmap(plot: np.ndarray, threshold: int) -> np.ndarray:
 def indel(plot: np.ndarray, w: int) -> np.ndarray:
     """Indel (insert/delete) distance of the window pairs: 2w - 2*WLCS."""
     return (2 * w - 2 * plot.astype(np.int32)).astype(np.uint16)
+
+
+def score(a, b) -> float:
+    """Alignment score of a and b: match 1, mismatch 0, gap -1/2 (Section 2),
+    by its own dynamic program."""
+    a, b = _bytes(a), _bytes(b)
+    v = ctypes.c_int32()
+    r = _load().oracle_score2(_p(a), a.size, _p(b), b.size, ctypes.byref(v))
+    if r != 0:
+        raise ValueError(f"oracle_score2 failed ({r})")
+    return v.value / 2.0
+
+
+def score_plot(x, y, w: int, step: int = 1, full_range: bool = False,
+               nthreads: int | None = None) -> np.ndarray:
+    """Alignment-score plot: int8 scores of the x-windows 0, step, 2*step, ...
+    against every y-window (w <= 127)."""
+    x, y = _bytes(x), _bytes(y)
+    rows_all = n_windows(x.size, w, full_range)
+    rows = (rows_all + step - 1) // step if rows_all else 0
+    cols = n_windows(y.size, w, full_range)
+    out = np.zeros((rows, cols), dtype=np.int8)
+    if rows and cols:
+        nt = nthreads or default_threads()
+        r = _load().oracle_score_plot(_p(x), x.size, _p(y), y.size, w, step, int(full_range),
+                                      _p(out, ctypes.c_int8), cols, nt)
+        if r != 0:
+            raise ValueError(f"oracle_score_plot failed ({r})")
+    return out

@@ -182,3 +182,104 @@ int oracle_wlcs_at(const uint8_t *x, int64_t m, const uint8_t *y, int64_t n, int
     free(tab);
     return ORACLE_OK;
 }
+
+/* ---- alignment-score plots ----------------------------------------------
+ * Section 2 also scores alignments with match 1, mismatch 0 and gap -1/2.  The
+ * oracle computes that score directly by the standard dynamic program, kept in
+ * half units so that everything stays integral:
+ *     T[p][0] = -p,  T[0][q] = -q,
+ *     T[p][q] = max(T[p-1][q-1] + 2 [a_p == b_q], T[p-1][q] - 1, T[p][q-1] - 1),
+ *     score(a, b) = T[|a|][|b|] / 2.
+ * (It does not use the '$' blow-up the paper reduces this score to.) */
+static int score2_table(const uint8_t *a, int la, const uint8_t *b, int lb, int *tab)
+{
+    const int cols = lb + 1;
+    for (int q = 0; q <= lb; ++q) tab[q] = -q;
+    for (int p = 1; p <= la; ++p) {
+        tab[p * cols] = -p;
+        for (int q = 1; q <= lb; ++q) {
+            int diag = tab[(p - 1) * cols + (q - 1)] + (a[p - 1] == b[q - 1] ? 2 : 0);
+            int up = tab[(p - 1) * cols + q] - 1;
+            int left = tab[p * cols + (q - 1)] - 1;
+            int v = diag;
+            if (up > v) v = up;
+            if (left > v) v = left;
+            tab[p * cols + q] = v;
+        }
+    }
+    return tab[la * cols + lb];
+}
+
+/* Twice the alignment score of a and b (lengths <= 4096). */
+int oracle_score2(const uint8_t *a, int64_t la, const uint8_t *b, int64_t lb, int32_t *out)
+{
+    if (la < 0 || lb < 0 || la > 4096 || lb > 4096 || !out || (la > 0 && !a) || (lb > 0 && !b))
+        return ORACLE_EINVAL;
+    int *tab = (int *)malloc(sizeof(int) * (size_t)(la + 1) * (size_t)(lb + 1));
+    if (!tab) return ORACLE_ENOMEM;
+    *out = score2_table(a, (int)la, b, (int)lb, tab);
+    free(tab);
+    return ORACLE_OK;
+}
+
+typedef struct {
+    const uint8_t *x, *y;
+    int32_t w, step;
+    int64_t cols;
+    int8_t *out;
+    int64_t ld;
+    int64_t r0, r1;
+    int status;
+} score_job;
+
+static void *score_worker(void *arg)
+{
+    score_job *jb = (score_job *)arg;
+    const int w = jb->w;
+    int *tab = (int *)malloc(sizeof(int) * (size_t)(w + 1) * (size_t)(w + 1));
+    if (!tab) {
+        jb->status = ORACLE_ENOMEM;
+        return NULL;
+    }
+    for (int64_t r = jb->r0; r < jb->r1; ++r) {
+        const int64_t i = r * jb->step;
+        for (int64_t j = 0; j < jb->cols; ++j)
+            jb->out[r * jb->ld + j] = (int8_t)(score2_table(jb->x + i, w, jb->y + j, w, tab) / 2);
+    }
+    free(tab);
+    return NULL;
+}
+
+/* Alignment-score plot with a vertical step: out row r holds the scores of the
+ * x-window starting at r*step against every y-window (score of two w-windows
+ * is an integer in [-w, w]; w <= 127).  Rows: the windows 0, step, 2*step, ...
+ * below m - w (m - w + 1 with full_range); columns: n - w (n - w + 1). */
+int oracle_score_plot(const uint8_t *x, int64_t m, const uint8_t *y, int64_t n, int32_t w, int32_t step,
+                      int32_t full_range, int8_t *out, int64_t ld, int32_t nthreads)
+{
+    if (m < 0 || n < 0 || w < 1 || w > 127 || step < 1) return ORACLE_EINVAL;
+    int64_t rows_all = n_windows(m, w, full_range), cols = n_windows(n, w, full_range);
+    int64_t rows = rows_all > 0 ? (rows_all + step - 1) / step : 0;
+    if (rows == 0 || cols == 0) return ORACLE_OK;
+    if (!x || !y || !out || ld < cols) return ORACLE_EINVAL;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (nthreads > rows) nthreads = (int)rows;
+    score_job jobs[256];
+    pthread_t th[256];
+    int started[256];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (score_job){x, y, w, step, cols, out, ld, rows * t / nthreads, rows * (t + 1) / nthreads,
+                              ORACLE_OK};
+        started[t] = (t > 0) && pthread_create(&th[t], NULL, score_worker, &jobs[t]) == 0;
+    }
+    score_worker(&jobs[0]);
+    int status = jobs[0].status;
+    for (int t = 1; t < nthreads; ++t) {
+        if (started[t]) pthread_join(th[t], NULL);
+        else score_worker(&jobs[t]);
+        if (jobs[t].status != ORACLE_OK) status = jobs[t].status;
+    }
+    return status;
+}
+
