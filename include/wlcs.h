@@ -52,6 +52,7 @@ extern "C" {
 #define WLCS_MAX_W 255         /* WLCS values must fit the uint8 output */
 #define WLCS_MAX_SIGMA 64      /* letters per alphabet */
 #define WLCS_MAX_LEN 100000000 /* longest string accepted (bytes) */
+#define WLCS_MAX_SCORE_W 127   /* alignment-score plots: scores in [-w, w] fit int8 */
 
 /* flags */
 #define WLCS_FULL_RANGE 1u /* every window: (m-w+1) x (n-w+1) instead of (m-w) x (n-w) */
@@ -111,6 +112,23 @@ int wlcs_plot_dp(wlcs_ctx *ctx, const uint8_t *x, int64_t m, const uint8_t *y, i
                  int32_t w, const uint8_t *alphabet, int32_t sigma, uint8_t *wlcs, int64_t ld,
                  uint64_t *bitmap, int64_t ld_words, int32_t threshold, uint16_t *indel,
                  int64_t ld_indel, uint32_t flags, void *stream);
+
+/* Alignment-score plot (Section 2's scoring: match 1, mismatch 0, gap -1/2)
+ * with a vertical step, as in the paper's experiments (Section 4).  Row r is
+ * the x-window starting at x[r * step] (r < ceil((m - w) / step)), column j the
+ * y-window starting at y[j] (j < n - w; WLCS_FULL_RANGE: m - w + 1 and
+ * n - w + 1 windows).  score[r*ld + j] is the best alignment score of the two
+ * windows, an integer in [-w, w] stored as int8.  The library computes it by
+ * the paper's reduction: with a separator letter inserted before every letter
+ * of both strings, the score of two w-windows equals the LLCS of their
+ * 2w-letter images minus w; the plot is the seaweed plot of the blown-up
+ * strings at window 2w, taken at every second window (the (2w, 2)-restricted
+ * plot of Definition 3.2).  The separator takes one letter code, so sigma must
+ * be at most 63.  bitmap (optional) marks score >= threshold (-128..127).
+ * 1 <= w <= WLCS_MAX_SCORE_W, step >= 1. */
+int wlcs_score_plot(wlcs_ctx *ctx, const uint8_t *x, int64_t m, const uint8_t *y, int64_t n, int32_t w,
+                    int32_t step, const uint8_t *alphabet, int32_t sigma, int8_t *score, int64_t ld,
+                    uint64_t *bitmap, int64_t ld_words, int32_t threshold, uint32_t flags, void *stream);
 
 /* ---- device-resident pairs --------------------------------------------
  * A pair holds x and y on the device, already mapped to letter codes, so that

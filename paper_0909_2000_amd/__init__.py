@@ -88,6 +88,8 @@ def _load():
     pair_args = [vp, vp, i32, vp, i64, vp, i64, i32, vp, i64, u32, vp]
     lib.wlcs_pair_plot.argtypes = pair_args
     lib.wlcs_pair_plot_dp.argtypes = pair_args
+    lib.wlcs_score_plot.argtypes = [vp, u8p, i64, u8p, i64, i32, i32, u8p, i32, vp, i64, vp, i64, i32,
+                                    u32, vp]
     lib.wlcs_batch.argtypes = [vp, ctypes.POINTER(Job), i32, vp]
     lib.wlcs_batch_graph.argtypes = [vp, ctypes.POINTER(Job), i32, ctypes.POINTER(vp)]
     lib.wlcs_graph_launch.argtypes = [vp, vp]
@@ -97,7 +99,8 @@ def _load():
     for f in ("wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_ctx_set_tile",
               "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot",
               "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
-              "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid"):
+              "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
+              "wlcs_score_plot"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -108,7 +111,8 @@ def exported_symbols() -> list:
     return ["wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_status_str",
             "wlcs_ctx_set_tile", "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy",
             "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
-            "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid"]
+            "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
+            "wlcs_score_plot"]
 
 
 def n_windows(length: int, w: int, full_range: bool = False) -> int:
@@ -259,6 +263,41 @@ class Context:
     def batch_graph(self, specs) -> "BatchGraph":
         """The batch captured into a replayable HIP graph (wlcs_batch_graph)."""
         return BatchGraph(self, specs)
+
+    def score_plot(self, x, y, w: int, step: int = 1, alphabet=DNA, threshold: int | None = None,
+                   full_range: bool = False, out=None, bitmap_out=None, want_plot: bool = True,
+                   stream=None) -> dict:
+        """Alignment-score plot (match 1, mismatch 0, gap -1/2) of the x-windows
+        0, step, 2*step, ... against every y-window: 'score' (int8 in [-w, w])
+        and 'bitmap' (score >= threshold) when asked for."""
+        lib = _load()
+        xa, ya, alpha = _as_bytes(x), _as_bytes(y), _as_bytes(alphabet)
+        rows_all = n_windows(xa.size, w, full_range)
+        rows = (rows_all + step - 1) // step if rows_all and step >= 1 else 0
+        cols = n_windows(ya.size, w, full_range)
+        dev = torch.device("cuda", self.device)
+        if out is None and want_plot:
+            out = torch.empty((rows, cols), dtype=torch.int8, device=dev)
+        if threshold is not None and bitmap_out is None:
+            bitmap_out = torch.empty((rows, (cols + 63) // 64), dtype=torch.int64, device=dev)
+        for t in (out, bitmap_out):
+            if t is not None and (t.device != dev or t.dim() != 2 or t.stride(1) != 1):
+                raise ValueError("outputs must be 2-D row-major tensors on the context's device")
+        stream = self._stream(stream)
+        st = lib.wlcs_score_plot(
+            self._h, _ptr(xa), xa.size, _ptr(ya), ya.size, int(w), int(step), _ptr(alpha), alpha.size,
+            ctypes.c_void_p(out.data_ptr()) if out is not None else None,
+            out.stride(0) if out is not None else 0,
+            ctypes.c_void_p(bitmap_out.data_ptr()) if bitmap_out is not None else None,
+            bitmap_out.stride(0) if bitmap_out is not None else 0,
+            int(threshold) if threshold is not None else 0,
+            WLCS_FULL_RANGE if full_range else 0, ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise WlcsError(st, "wlcs_score_plot", lib.wlcs_ctx_last_hip_error(self._h))
+        res = {"score": out}
+        if bitmap_out is not None:
+            res["bitmap"] = bitmap_out
+        return res
 
     def pair(self, x, y, alphabet=DNA, stream=None) -> "Pair":
         """Upload and encode x and y once; plot them any number of times."""

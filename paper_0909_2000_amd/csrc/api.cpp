@@ -152,7 +152,7 @@ int stage_copy(wlcs_ctx* ctx, const void* src, size_t bytes, void* dst, hipStrea
 // Copy x and y into a pinned slot, then to device memory, and encode them into
 // the padded code arrays the kernels read.
 int upload(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, const uint8_t map[256],
-           int64_t xf_len, int64_t yg_len, hipStream_t stream, Prepared& p) {
+           int64_t xf_len, int64_t yg_len, hipStream_t stream, Prepared& p, int sep = -1) {
     const size_t need = (size_t)(m + n);
     if (need == 0) return WLCS_OK;
     Slot& sl = ctx->slots[ctx->next_slot];
@@ -182,9 +182,9 @@ int upload(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t
         return fail(ctx, e);
     if ((e = hipEventRecord(sl.done, stream)) != hipSuccess) return fail(ctx, e);
     sl.pending = true;
-    if (xf_len > 0 && (e = wlcs::launch_encode(p.raw, m, map, 1, p.xf, xf_len, stream)) != hipSuccess)
+    if (xf_len > 0 && (e = wlcs::launch_encode(p.raw, m, map, 1, p.xf, xf_len, stream, sep)) != hipSuccess)
         return fail(ctx, e);
-    if (yg_len > 0 && (e = wlcs::launch_encode(p.raw + m, n, map, 0, p.yg, yg_len, stream)) != hipSuccess)
+    if (yg_len > 0 && (e = wlcs::launch_encode(p.raw + m, n, map, 0, p.yg, yg_len, stream, sep)) != hipSuccess)
         return fail(ctx, e);
     return WLCS_OK;
 }
@@ -517,6 +517,55 @@ int wlcs_plot_dp(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, i
                  void* stream) {
     return plot_common(Path::Dp, ctx, x, m, y, n, w, alphabet, sigma, wlcs, ld, bitmap, ld_words, threshold,
                        indel, ld_indel, flags, stream);
+}
+
+int wlcs_score_plot(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, int32_t w, int32_t step,
+                    const uint8_t* alphabet, int32_t sigma, int8_t* score, int64_t ld, uint64_t* bitmap,
+                    int64_t ld_words, int32_t threshold, uint32_t flags, void* stream_) {
+    if (flags & ~WLCS_FULL_RANGE) return WLCS_EINVAL;
+    if (w < 1 || w > WLCS_MAX_SCORE_W || step < 1) return WLCS_ERANGE;
+    if (sigma >= WLCS_MAX_SIGMA) return WLCS_EALPHABET;  // one code is kept for the separator
+    uint8_t map[256];
+    int st = validate(x, m, y, n, w, alphabet, sigma, map);
+    if (st != WLCS_OK) return st;
+    const bool full = (flags & WLCS_FULL_RANGE) != 0;
+    const int64_t rows_all = n_windows(m, w, full), cols = n_windows(n, w, full);
+    const int64_t rows = rows_all > 0 ? (rows_all + step - 1) / step : 0;
+    if (rows > 0 && cols > 0) {
+        if (!score && !bitmap) return WLCS_EINVAL;
+        if (score && ld < cols) return WLCS_EINVAL;
+        if (bitmap && (ld_words < (cols + 63) / 64 || threshold < -128 || threshold > 127)) return WLCS_EINVAL;
+    }
+    if (!ctx) return WLCS_EINVAL;
+    if (rows == 0 || cols == 0) return WLCS_OK;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
+    hipStream_t stream = (hipStream_t)stream_;
+    // the LCS plot of the blown-up strings x', y' (window 2w), at the strips of
+    // x' that start x-windows 0, step, 2 step, ... and the even windows of y'
+    const int32_t w2 = 2 * w;
+    wlcs::PlotArgs a = make_args(rows, 2 * cols, w2, (uint8_t*)score, ld, bitmap, ld_words,
+                                 std::min(std::max(threshold + w, 0), 256), nullptr, 0);
+    a.ws = 2;
+    a.xstride = 2 * (int64_t)step;
+    a.bias = w;
+    a.tile = choose_tile(ctx, rows, a.cols, w2);
+    a.npairs = (int32_t)(((a.cols + a.tile - 1) / a.tile + 1) / 2);
+    int64_t xf_len, yg_len;
+    needed_lengths(Path::Seaweed, rows, a.cols, w2, a.tile, xf_len, yg_len);
+    xf_len = (rows + 63) / 64 * 64 * a.xstride + wlcs::w_class(w2) + 64;
+    Prepared p;
+    st = upload(ctx, x, m, y, n, map, xf_len, yg_len, stream, p, sigma);
+    if (st != WLCS_OK) {
+        release(p, stream);
+        return st;
+    }
+    a.xf = p.xf;
+    a.yg = p.yg;
+    hipError_t e = wlcs::launch_seaweed(a, stream);
+    release(p, stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    return WLCS_OK;
 }
 
 int wlcs_pair_create(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n,

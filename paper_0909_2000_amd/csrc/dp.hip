@@ -115,11 +115,17 @@ struct Map256 {
     uint8_t m[256];
 };
 
-__global__ void encode_kernel(const uint8_t* __restrict__ raw, int64_t len, Map256 map, int x_side,
+// Letters -> codes.  With a separator code (sep >= 0) the string is first
+// blown up as in Section 2's reduction of the alignment score: the separator
+// letter goes before every letter, so code i of the output belongs to
+// separator (i even) or letter i/2 (i odd).
+__global__ void encode_kernel(const uint8_t* __restrict__ raw, int64_t len, Map256 map, int x_side, int sep,
                               uint16_t* __restrict__ out, int64_t out_len) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < out_len;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t c = i < len ? map.m[raw[i]] : 0u;
+        uint32_t c;
+        if (sep < 0) c = i < len ? map.m[raw[i]] : 0u;
+        else c = i < 2 * len ? ((i & 1) ? map.m[raw[i >> 1]] : (uint32_t)sep) : 0u;
         out[i] = x_side ? f_code(c) : g_code(c);
     }
 }
@@ -162,14 +168,14 @@ hipError_t launch_dp(const PlotArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_encode(const uint8_t* raw, int64_t len, const uint8_t* map256, int x_side, uint16_t* out,
-                         int64_t out_len, hipStream_t stream) {
+                         int64_t out_len, hipStream_t stream, int sep) {
     if (out_len <= 0) return hipSuccess;
     Map256 m;
     for (int i = 0; i < 256; ++i) m.m[i] = map256[i];
     int64_t blocks = (out_len + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(encode_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, raw, len, m, x_side, out,
-                       out_len);
+    hipLaunchKernelGGL(encode_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, raw, len, m, x_side, sep,
+                       out, out_len);
     return hipGetLastError();
 }
 

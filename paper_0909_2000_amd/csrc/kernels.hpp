@@ -23,6 +23,9 @@ constexpr int kRebase = 512;
 
 // One plot's worth of kernel arguments (host side).
 struct PlotArgs {
+    int64_t xstride = 1;     // x codes between consecutive strips
+    int32_t ws = 1;          // store every ws-th combed window (1 or 2)
+    int32_t bias = 0;        // subtracted from every stored value
     const uint16_t* xf;      // f-codes of x, padded (see host runtime)
     const uint16_t* yg;      // g-codes of y, padded
     int64_t rows;            // x-windows (strips)
@@ -43,8 +46,11 @@ struct PlotArgs {
 // as separate __restrict__ parameters so that uniform loads become scalar).
 struct Geom {
     int64_t rows, cols, ld, ld_words32, ld_indel;
+    int64_t ocols;     // output columns (cols / ws: only every ws-th combed window is stored)
+    int64_t xstride;   // x codes between consecutive strips (1: every x-window)
     int32_t w, tile, npairs, threshold;
-    int32_t wmode;  // plot stores: 2 = 16-byte rows, 1 = 4-byte rows, 0 = bytes
+    int32_t wmode;     // plot stores: 2 = 16-byte rows, 1 = 4-byte rows, 0 = bytes
+    int32_t bias;      // subtracted from every stored value (0..127)
 };
 
 inline Geom geom_of(const PlotArgs& a) {
@@ -58,6 +64,9 @@ inline Geom geom_of(const PlotArgs& a) {
     g.tile = a.tile;
     g.npairs = a.npairs;
     g.threshold = a.threshold;
+    g.ocols = a.ws == 2 ? a.cols / 2 : a.cols;
+    g.xstride = a.xstride;
+    g.bias = a.bias;
     const uintptr_t base = (uintptr_t)a.wlcs;
     g.wmode = (a.ld % 16 == 0 && base % 16 == 0) ? 2 : (a.ld % 4 == 0 && base % 4 == 0) ? 1 : 0;
     return g;
@@ -80,7 +89,7 @@ struct JobDesc {
 inline int w_class(int w) { return w <= 16 ? 16 : w <= 32 ? 32 : w <= 64 ? 64 : w <= 128 ? 128 : 256; }
 
 hipError_t launch_encode(const uint8_t* raw, int64_t len, const uint8_t* map256, int x_side,
-                         uint16_t* out, int64_t out_len, hipStream_t stream);
+                         uint16_t* out, int64_t out_len, hipStream_t stream, int sep = -1);
 hipError_t launch_seaweed(const PlotArgs& a, hipStream_t stream);
 hipError_t launch_dp(const PlotArgs& a, hipStream_t stream);
 int batch_variant(int w);

@@ -51,18 +51,29 @@
 namespace wlcs {
 namespace {
 
-template <int WC, bool EXACT>
+template <int WC, bool EXACT, int WS>
 __global__ __launch_bounds__(64, min_waves_per_simd(WC)) void seaweed_kernel(const uint16_t* __restrict__ xf,
-                                                     const uint32_t* __restrict__ yg32,
-                                                     uint8_t* __restrict__ out,
-                                                     uint32_t* __restrict__ bm32,
-                                                     uint16_t* __restrict__ indel, Geom g) {
+                                                                              const uint32_t* __restrict__ yg32,
+                                                                              uint8_t* __restrict__ out,
+                                                                              uint32_t* __restrict__ bm32,
+                                                                              uint16_t* __restrict__ indel, Geom g) {
     __shared__ uint32_t ring[ring_words(WC) * 64];
-    __shared__ uint32_t stage[stage_dwords(WC)];
+    __shared__ uint32_t stage[stage_dwords(WC, WS)];
     const int64_t unit = blockIdx.x;
     const int64_t sb = unit / g.npairs;
     const int pr = (int)(unit - sb * g.npairs);
-    comb_unit<WC, EXACT>(xf, yg32, out, bm32, indel, g, sb, pr, ring, stage);
+    comb_unit<WC, EXACT, WS>(xf, yg32, out, bm32, indel, g, sb, pr, ring, stage);
+}
+
+template <int WC, int WS>
+void launch_ws(const PlotArgs& a, const Geom& g, uint32_t units, hipStream_t stream) {
+    const uint32_t* yg32 = (const uint32_t*)a.yg;
+    if (a.w == WC)
+        hipLaunchKernelGGL((seaweed_kernel<WC, true, WS>), dim3(units), dim3(64), 0, stream, a.xf, yg32, a.wlcs,
+                           a.bitmap32, a.indel, g);
+    else
+        hipLaunchKernelGGL((seaweed_kernel<WC, false, WS>), dim3(units), dim3(64), 0, stream, a.xf, yg32, a.wlcs,
+                           a.bitmap32, a.indel, g);
 }
 
 template <int WC>
@@ -72,13 +83,10 @@ hipError_t launch_wc(const PlotArgs& a, hipStream_t stream) {
     if (units <= 0) return hipSuccess;
     if (units > 0x7FFFFFFFll) return hipErrorInvalidValue;
     const Geom g = geom_of(a);
-    const uint32_t* yg32 = (const uint32_t*)a.yg;
-    if (a.w == WC)
-        hipLaunchKernelGGL((seaweed_kernel<WC, true>), dim3((uint32_t)units), dim3(64), 0, stream, a.xf, yg32,
-                           a.wlcs, a.bitmap32, a.indel, g);
+    if (a.ws == 2)
+        launch_ws<WC, 2>(a, g, (uint32_t)units, stream);
     else
-        hipLaunchKernelGGL((seaweed_kernel<WC, false>), dim3((uint32_t)units), dim3(64), 0, stream, a.xf, yg32,
-                           a.wlcs, a.bitmap32, a.indel, g);
+        launch_ws<WC, 1>(a, g, (uint32_t)units, stream);
     return hipGetLastError();
 }
 

@@ -10,28 +10,37 @@
 namespace wlcs {
 
 // Windows staged per lane before a flush: 64 (64-byte row segments) where
-// the LDS budget allows it at the class's occupancy, else 32.
-constexpr int flush_windows(int wc) { return wc >= 64 ? 64 : 32; }
+// the LDS budget allows it at the class's occupancy, else 32; 64 whenever only
+// every second window is stored (ws = 2), so a block still fills 32 outputs.
+constexpr int flush_windows(int wc, int ws = 1) { return (wc >= 64 || ws == 2) ? 64 : 32; }
 // dwords per lane row of the staging buffer (one per 4 windows, plus a pad
 // dword that spreads the lanes over the LDS banks)
-constexpr int stage_pitch(int wc) { return flush_windows(wc) / 4 + 1; }
+constexpr int stage_pitch(int wc, int ws = 1) { return flush_windows(wc, ws) / 4 + 1; }
+
+// Per byte: x - b (mod 256) for b <= 127 in every byte, without borrows
+// between the bytes.
+__device__ __forceinline__ uint32_t sub_bytes(uint32_t x, uint32_t b4) {
+    const uint32_t H = 0x80808080u;
+    return ((x | H) - b4) ^ ((x ^ ~b4) & H);
+}
 // LDS ring words (16 start columns each) per lane: the ring must cover the
 // w + 1 start columns that can be pending at once, with a margin that keeps
 // the word being cleared apart from the newest marks.
 constexpr int ring_words(int wc) { return wc <= 128 ? 16 : 32; }
-constexpr int stage_dwords(int wc) { return 2 * 64 * stage_pitch(wc); }
+constexpr int stage_dwords(int wc, int ws = 1) { return 2 * 64 * stage_pitch(wc, ws); }
 // Occupancy each window class is compiled for (waves per SIMD): the w labels
 // and w/2 code registers per lane plus the flush temporaries must fit.
 constexpr int min_waves_per_simd(int wc) { return wc <= 32 ? 4 : wc <= 64 ? 3 : wc <= 128 ? 2 : 1; }
 
-template <int WC, bool EXACT>
+template <int WC, bool EXACT, int WS = 1>
 __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32,
                                           uint8_t* __restrict__ out, uint32_t* __restrict__ bm32,
                                           uint16_t* __restrict__ indel, const Geom& g, int64_t sb, int pr,
                                           uint32_t* __restrict__ ring, uint32_t* __restrict__ stage) {
     constexpr int RW = ring_words(WC);
-    constexpr int FL = flush_windows(WC);
-    constexpr int PITCH = stage_pitch(WC);
+    constexpr int FL = flush_windows(WC, WS);
+    constexpr int PITCH = stage_pitch(WC, WS);
+    constexpr int FO = FL / WS;  // outputs per flushed block
     const int lane = threadIdx.x & 63;
     const int64_t s0 = sb * 64;
     const int64_t tA = (int64_t)(2 * pr) * g.tile;
@@ -41,7 +50,7 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     // x letters of this lane's strip, two rows per register
     uint32_t xc[WC / 2];
     {
-        const uint16_t* xp = xf + s0 + lane;
+        const uint16_t* xp = xf + (s0 + lane) * g.xstride;
 #pragma unroll
         for (int j = 0; j < WC / 2; ++j) xc[j] = (uint32_t)xp[2 * j] | ((uint32_t)xp[2 * j + 1] << 16);
     }
@@ -110,7 +119,7 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     // warm-up columns: no window is complete yet
     for (int l = 0; l < w - 1; ++l) (void)column(l);
 
-    const uint32_t bm_words = (uint32_t)(((g.cols + 63) >> 6) * 2);
+    const uint32_t bm_words = (uint32_t)(((g.ocols + 63) >> 6) * 2);
     for (int jb = 0; jb < nproc; jb += FL) {
 #pragma unroll 1
         for (int gi = 0; gi < FL / 4; ++gi) {
@@ -139,35 +148,29 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         for (int half = 0; half < 2; ++half) {
             const int64_t ts = half ? tB : tA;
             const int64_t te = ts + g.tile < g.cols ? ts + g.tile : g.cols;
-            const int64_t j0 = ts + jb;
+            const int64_t j0 = ts + jb;   // first (combed) window of the block
+            const int64_t o0 = j0 / WS;   // its output column
             // windows of this block inside the tile (0 for the padding block
-            // that completes the last bitmap word, or past the end of y)
-            const int nvalid = (int)(te - j0 < FL ? (te - j0 > 0 ? te - j0 : 0) : FL);
-            if (nvalid == 0 && (uint32_t)(j0 >> 5) >= bm_words) continue;  // uniform
-            uint32_t d[FL / 4];
+            // that completes the last bitmap word, or past the end of y);
+            // with WS = 2 only the even ones are outputs
+            const int nk = (int)(te - j0 < FL ? (te - j0 > 0 ? te - j0 : 0) : FL);
+            const int nvalid = (nk + WS - 1) / WS;
+            if (nvalid == 0 && (uint32_t)(o0 >> 5) >= bm_words) continue;  // uniform
+            uint32_t d[FO / 4];
 #pragma unroll
-            for (int k = 0; k < FL / 4; ++k) d[k] = stage[half * 64 * PITCH + lane * PITCH + k];
-            if (out && g.wmode > 0 && nvalid > 0) {
-                if (s < g.rows) {
-                    uint8_t* row = out + s * g.ld + j0;
-                    if (nvalid == FL) {
-                        if (g.wmode == 2) {
-#pragma unroll
-                            for (int k = 0; k < FL / 16; ++k)
-                                ((uint4*)row)[k] = make_uint4(d[4 * k], d[4 * k + 1], d[4 * k + 2], d[4 * k + 3]);
-                        } else {
-#pragma unroll
-                            for (int k = 0; k < FL / 4; ++k) ((uint32_t*)row)[k] = d[k];
-                        }
-                    } else {
-                        for (int b = 0; b < nvalid; ++b) row[b] = (uint8_t)(d[b >> 2] >> (8 * (b & 3)));
-                    }
+            for (int k = 0; k < FO / 4; ++k) {
+                if (WS == 1) {
+                    d[k] = stage[half * 64 * PITCH + lane * PITCH + k];
+                } else {  // keep bytes 0 and 2 of two staged dwords
+                    const uint32_t a = stage[half * 64 * PITCH + lane * PITCH + 2 * k];
+                    const uint32_t b = stage[half * 64 * PITCH + lane * PITCH + 2 * k + 1];
+                    d[k] = (a & 0xFFu) | ((a >> 8) & 0xFF00u) | ((b & 0xFFu) << 16) | ((b << 8) & 0xFF000000u);
                 }
             }
             if (bm32 && s < g.rows) {
 #pragma unroll
-                for (int sub = 0; sub < FL / 32; ++sub) {
-                    const uint32_t wi = (uint32_t)(j0 >> 5) + sub;
+                for (int sub = 0; sub < FO / 32; ++sub) {
+                    const uint32_t wi = (uint32_t)(o0 >> 5) + sub;
                     if (wi < bm_words) {
                         const int nv = nvalid - 32 * sub;
                         uint32_t bits = 0;
@@ -180,19 +183,40 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                     }
                 }
             }
+            if (g.bias) {
+#pragma unroll
+                for (int k = 0; k < FO / 4; ++k) d[k] = sub_bytes(d[k], (uint32_t)g.bias * 0x01010101u);
+            }
+            if (out && g.wmode > 0 && nvalid > 0) {
+                if (s < g.rows) {
+                    uint8_t* row = out + s * g.ld + o0;
+                    if (nvalid == FO) {
+                        if (g.wmode == 2) {
+#pragma unroll
+                            for (int k = 0; k < FO / 16; ++k)
+                                ((uint4*)row)[k] = make_uint4(d[4 * k], d[4 * k + 1], d[4 * k + 2], d[4 * k + 3]);
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < FO / 4; ++k) ((uint32_t*)row)[k] = d[k];
+                        }
+                    } else {
+                        for (int b = 0; b < nvalid; ++b) row[b] = (uint8_t)(d[b >> 2] >> (8 * (b & 3)));
+                    }
+                }
+            }
             if (((out && g.wmode == 0) || indel) && nvalid > 0) {
-                // transposed: the lanes cover FL windows of 64 / FL strips per step
-                constexpr int RPI = 64 / FL;
-                const int q = lane % FL;
+                // transposed: the lanes cover FO outputs of 64 / FO strips per step
+                constexpr int RPI = 64 / FO;
+                const int q = lane % FO;
                 const uint8_t* sbytes = (const uint8_t*)stage;
 #pragma unroll 4
                 for (int it = 0; it < 64 / RPI; ++it) {
-                    const int r = RPI * it + lane / FL;
+                    const int r = RPI * it + lane / FO;
                     const int64_t sr = s0 + r;
-                    const uint32_t v = sbytes[(half * 64 * PITCH + r * PITCH) * 4 + q];
+                    const uint32_t v = sbytes[(half * 64 * PITCH + r * PITCH) * 4 + q * WS];
                     if (sr < g.rows && q < nvalid) {
-                        if (out && g.wmode == 0) out[sr * g.ld + j0 + q] = (uint8_t)v;
-                        if (indel) indel[sr * g.ld_indel + j0 + q] = (uint16_t)(2 * w - 2 * (int)v);
+                        if (out && g.wmode == 0) out[sr * g.ld + o0 + q] = (uint8_t)(v - (uint32_t)g.bias);
+                        if (indel) indel[sr * g.ld_indel + o0 + q] = (uint16_t)(2 * w - 2 * (int)v);
                     }
                 }
             }
