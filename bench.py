@@ -83,6 +83,8 @@ def main():
                     help="row stride of the timed plot rounded up to this many bytes")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other single-pair configurations (1k DNA w16, 30k protein w128)")
+    ap.add_argument("--no-paper-shapes", action="store_true",
+                    help="skip the alignment-score plots shaped like the paper's experiments")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -221,6 +223,13 @@ def main():
             others[workloads.config(k).name] = bench_config(ctx, torch, workloads, oracle, k)
             log(f"config {k}: {others[workloads.config(k).name]}")
 
+    paper_shapes = None
+    if not args.no_paper_shapes:
+        paper_shapes = bench_paper_shapes(ctx, torch, workloads, oracle)
+        for k, v in paper_shapes.items():
+            log(f"{k}: {v['ms']:.1f} ms (paper: Sea-8 {v['paper_sea8_s']} s on 1 core, MPI "
+                f"{v['paper_mpi_s']} s on {v['paper_mpi_cores']} cores)")
+
     batched = None
     if not args.no_batch:
         batched = bench_batch(ctx, torch, workloads)
@@ -242,7 +251,8 @@ def main():
                    "threshold": thr, "outputs": "uint8 plot + bitmap" if thr else "uint8 plot",
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "gpu_dp_baseline": dp,
-        "other_configs": others, "batched": batched, "serving": serving,
+        "other_configs": others, "paper_shaped_score_plots": paper_shapes,
+        "batched": batched, "serving": serving,
         "encode_ms": encode_ms, "parity_sampled_rows": parity,
         "kernel_ms": {"min": float(np.min(kern_ms)), "median": float(np.median(kern_ms)),
                       "max": float(np.max(kern_ms))},
@@ -327,6 +337,45 @@ def bench_config(ctx, torch, workloads, oracle, k, steps=10):
            "parity": parity, "parity_sample": sample}
     pair.close()
     return res
+
+
+# The paper's experiments (Section 4, Table 1): alignment-score plots with
+# w = 100 (window 200 after the blow-up) and a vertical step of 5 on four
+# biological pairs.  The sequences are not available; iid DNA of the same
+# lengths stands in (the seaweed method's time does not depend on content).
+# (m, n, Sea-16 1 core s, Sea-8 1 core s, fastest MPI run s, its cores)
+PAPER_SHAPES = {
+    "berti-2712x2305": (2712, 2305, 10.8, 3.8, 1.3, 4),
+    "jimmy-15kx97k": (15000, 97000, 1026.0, 368.0, 11.0, 64),
+    "henry-80kx80k": (80000, 80000, 4514.0, 1614.0, 23.0, 64),
+}
+
+
+def bench_paper_shapes(ctx, torch, workloads, oracle):
+    """Alignment-score plots at the paper's experimental shapes, timed with
+    HIP events (strings uploaded, blown up and encoded inside each call)."""
+    import numpy as np
+    out = {}
+    for name, (m, n, sea16, sea8, mpi, mpi_cores) in PAPER_SHAPES.items():
+        g = workloads.rng(500 + m % 97)
+        x, y = workloads.iid(g, m, workloads.DNA), workloads.iid(g, n, workloads.DNA)
+        w, step = 100, 5
+        res = ctx.score_plot(x, y, w, step=step)  # allocates and warms up
+        S = res["score"]
+        ms = float(np.median([_timed_once(torch, lambda: ctx.score_plot(x, y, w, step=step, out=S))
+                              for _ in range(3)]))
+        r = S.shape[0] // 2
+        want = oracle.score_plot(x[r * step:r * step + w], y, w, full_range=True)[0, :S.shape[1]]
+        cells = float(S.shape[0]) * (2 * n) * (2 * w)
+        out[name] = {"m": m, "n": n, "w": w, "step": step, "rows": S.shape[0], "cols": S.shape[1],
+                     "ms": ms, "blown_up_cells_per_s": cells / (ms / 1e3),
+                     "parity_row": bool(np.array_equal(S[r].cpu().numpy(), want)),
+                     "paper_sea16_s": sea16, "paper_sea8_s": sea8, "paper_mpi_s": mpi,
+                     "paper_mpi_cores": mpi_cores,
+                     "data": "iid uniform DNA of the paper's lengths (datasets not available)"}
+        del res, S
+    torch.cuda.empty_cache()
+    return out
 
 
 def _timed_once(torch, fn):
