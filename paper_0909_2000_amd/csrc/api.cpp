@@ -71,25 +71,40 @@ int64_t n_windows(int64_t len, int32_t w, bool full) {
     return k > 0 ? k : 0;
 }
 
-int waves_per_cu(int wc) { return wc <= 64 ? 16 : wc == 128 ? 8 : 4; }
+// Resident waves per SIMD of the single-plot kernel of a window class (the
+// register budget; LDS allows 4 more at 8.7 KB per wave for the 32-window
+// flush and 3 at 12.8 KB for the 64-window one).
+int waves_per_simd(int wc, int ws) {
+    const int regs = wc <= 32 ? 4 : wc == 64 ? 3 : wc == 128 ? 2 : 1;
+    const int lds = (wc >= 64 || ws == 2) ? 3 : 4;
+    return std::min(regs, lds);
+}
 
-// Tile length for the seaweed kernel: among multiples of 64, take the one that
-// minimises (rounds of resident waves) x (columns each wave combs), the larger
-// tile on ties.  A context rule set by wlcs_ctx_set_tile overrides it.
-int32_t choose_tile(const wlcs_ctx* ctx, int64_t rows, int64_t cols, int32_t w) {
+// Tile length for the seaweed kernel.  A unit (64 strips, two tiles) combs
+// min(T, rest) + w - 1 columns; units are handed out to the SIMDs as they free
+// up.  The estimate is the combing work per SIMD plus a tail of one unit that
+// shrinks with the number of waves sharing a SIMD; the tile with the lowest
+// estimate wins (the longer one on ties).  A context rule set by
+// wlcs_ctx_set_tile overrides it.
+int32_t choose_tile(const wlcs_ctx* ctx, int64_t rows, int64_t cols, int32_t w, int ws = 1) {
     for (int r = ctx->nrules - 1; r >= 0; --r)
         if (w >= ctx->rules[r].lo && w <= ctx->rules[r].hi) return ctx->rules[r].tile;
+    static const int32_t cand[] = {64, 128, 192, 256, 384, 512, 768, 1024, 1280, 1536, 2048, 2560, 3072, 4096, 6144, 8192, 12288, 16384};
     const int64_t nblocks = (rows + 63) / 64;
-    const int64_t slots = (int64_t)ctx->cus * waves_per_cu(wlcs::w_class(w));
+    const double simds = 4.0 * ctx->cus;
+    const double tail = 2.0 / waves_per_simd(wlcs::w_class(w), ws);
     const int64_t cap = std::max<int64_t>(64, (cols + 63) / 64 * 64);
     int32_t best = 64;
     double best_cost = 1e300;
-    for (int32_t t = 64; t <= 16384; t *= 2) {
+    for (int32_t t : cand) {
         if (t > cap && t > 64) break;
         const int64_t ntiles = (cols + t - 1) / t;
-        const int64_t units = nblocks * ((ntiles + 1) / 2);
-        const int64_t rounds = (units + slots - 1) / slots;
-        const double cost = (double)rounds * (double)(t + w - 1);
+        const int64_t npairs = (ntiles + 1) / 2;
+        const int64_t rest = cols - (2 * npairs - 2) * (int64_t)t;  // windows left for the last pair
+        const int64_t last = std::min<int64_t>(t, (rest + 63) / 64 * 64);
+        const double full = (double)(t + w - 1), part = (double)(last + w - 1);
+        const double work = (double)nblocks * ((double)(npairs - 1) * full + part);
+        const double cost = work / simds + tail * full;
         if (cost <= best_cost) {
             best_cost = cost;
             best = t;
@@ -549,7 +564,7 @@ int wlcs_score_plot(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y
     a.ws = 2;
     a.xstride = 2 * (int64_t)step;
     a.bias = w;
-    a.tile = choose_tile(ctx, rows, a.cols, w2);
+    a.tile = choose_tile(ctx, rows, a.cols, w2, 2);
     a.npairs = (int32_t)(((a.cols + a.tile - 1) / a.tile + 1) / 2);
     int64_t xf_len, yg_len;
     needed_lengths(Path::Seaweed, rows, a.cols, w2, a.tile, xf_len, yg_len);

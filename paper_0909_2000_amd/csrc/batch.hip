@@ -18,8 +18,10 @@ namespace {
 
 template <int WC, bool EXACT>
 __device__ __forceinline__ void run_unit(const JobDesc& jd, int64_t local, uint32_t* ring, uint32_t* stage) {
-    const int64_t sb = local / jd.g.npairs;
-    const int pr = (int)(local - sb * jd.g.npairs);
+    // pair-major within a job, as in the single-plot kernel
+    const int64_t nblocks = (jd.g.rows + 63) / 64;
+    const int pr = (int)(local / nblocks);
+    const int64_t sb = local - (int64_t)pr * nblocks;
     comb_unit<WC, EXACT>(jd.xf, jd.yg32, jd.out, jd.bm32, jd.indel, jd.g, sb, pr, ring, stage);
 }
 

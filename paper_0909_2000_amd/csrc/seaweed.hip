@@ -59,9 +59,13 @@ __global__ __launch_bounds__(64, min_waves_per_simd(WC)) void seaweed_kernel(con
                                                                               uint16_t* __restrict__ indel, Geom g) {
     __shared__ uint32_t ring[ring_words(WC) * 64];
     __shared__ uint32_t stage[stage_dwords(WC, WS)];
+    // pair-major order: the last tile pair of every strip block (usually
+    // shorter: the plot's width is rarely a multiple of two tiles) comes last
+    // and fills the tail of the launch
+    const int64_t nblocks = (g.rows + 63) / 64;
     const int64_t unit = blockIdx.x;
-    const int64_t sb = unit / g.npairs;
-    const int pr = (int)(unit - sb * g.npairs);
+    const int pr = (int)(unit / nblocks);
+    const int64_t sb = unit - (int64_t)pr * nblocks;
     comb_unit<WC, EXACT, WS>(xf, yg32, out, bm32, indel, g, sb, pr, ring, stage);
 }
 
