@@ -100,8 +100,7 @@ int32_t choose_tile(const wlcs_ctx* ctx, int64_t rows, int64_t cols, int32_t w, 
         if (t > cap && t > 64) break;
         const int64_t ntiles = (cols + t - 1) / t;
         const int64_t npairs = (ntiles + 1) / 2;
-        const int64_t rest = cols - (2 * npairs - 2) * (int64_t)t;  // windows left for the last pair
-        const int64_t last = std::min<int64_t>(t, (rest + 63) / 64 * 64);
+        const int64_t last = wlcs::pair_tile(cols, t, npairs - 1);  // the last pair's (split) tiles
         const double full = (double)(t + w - 1), part = (double)(last + w - 1);
         const double work = (double)nblocks * ((double)(npairs - 1) * full + part);
         const double cost = work / simds + tail * full;

@@ -53,6 +53,17 @@ struct Geom {
     int32_t bias;      // subtracted from every stored value (0..127)
 };
 
+// Windows per tile in tile pair pr of a row of cols windows: the full tile,
+// except in the last pair, whose remaining windows are split evenly (in whole
+// blocks of 64) between its two tiles, so that both halves of every register
+// carry work there too.  Tile A of the pair starts at 2 * pr * tile, tile B
+// right after it.
+__host__ __device__ inline int64_t pair_tile(int64_t cols, int64_t tile, int64_t pr) {
+    const int64_t rest = cols - 2 * pr * tile;
+    const int64_t half = ((rest + 1) / 2 + 63) / 64 * 64;
+    return half < tile ? half : tile;
+}
+
 inline Geom geom_of(const PlotArgs& a) {
     Geom g;
     g.rows = a.rows;

@@ -50,7 +50,8 @@ __device__ __forceinline__ uint32_t pk_add_bcast(uint32_t x, uint32_t y) {
 //     s     = s ^ t ^ down          (the seaweed leaving to the right)
 // Written as one volatile block so that the five instructions stay together
 // and the compiler cannot hoist the letter sums of a whole column into
-// registers ahead of time.  Pure ALU, no memory access.
+// registers ahead of time.  The y codes of a column are the same in every
+// lane, so they come from a scalar register.  Pure ALU, no memory access.
 template <int HI>
 __device__ __forceinline__ uint32_t seaweed_cell(uint32_t& s, uint32_t t, uint32_t x, uint32_t y) {
     uint32_t down;
@@ -62,7 +63,7 @@ __device__ __forceinline__ uint32_t seaweed_cell(uint32_t& s, uint32_t t, uint32
             "v_xor_b32 %0, %0, %2\n\t"
             "v_xor_b32 %0, %0, %1"
             : "+v"(s), "=&v"(down)
-            : "v"(t), "v"(x), "v"(y));
+            : "v"(t), "v"(x), "s"(y));
     else
         asm volatile(
             "v_pk_add_u16 %1, %3, %4 op_sel_hi:[0,1]\n\t"
@@ -71,7 +72,21 @@ __device__ __forceinline__ uint32_t seaweed_cell(uint32_t& s, uint32_t t, uint32
             "v_xor_b32 %0, %0, %2\n\t"
             "v_xor_b32 %0, %0, %1"
             : "+v"(s), "=&v"(down)
-            : "v"(t), "v"(x), "v"(y));
+            : "v"(t), "v"(x), "s"(y));
+    return down;
+}
+// The cell of the top row: t is the label of the seaweed entering the column
+// from the top, the same in every lane, so it too comes from a scalar register.
+__device__ __forceinline__ uint32_t seaweed_cell_top(uint32_t& s, uint32_t t, uint32_t x, uint32_t y) {
+    uint32_t down;
+    asm volatile(
+        "v_pk_add_u16 %1, %3, %4 op_sel_hi:[0,1]\n\t"
+        "v_pk_min_u16 %1, %2, %1\n\t"
+        "v_pk_max_u16 %1, %0, %1\n\t"
+        "v_xor_b32 %0, %2, %0\n\t"
+        "v_xor_b32 %0, %0, %1"
+        : "+v"(s), "=&v"(down)
+        : "s"(t), "v"(x), "s"(y));
     return down;
 }
 
@@ -118,6 +133,21 @@ __device__ __forceinline__ uint32_t pk_lshl(uint32_t amount, uint32_t val) {
     asm("v_pk_lshlrev_b16 %0, %1, %2" : "=v"(r) : "v"(amount), "v"(val));
     return r;
 }
+
+// (x >> OFF) & ((1 << WIDTH) - 1) as one v_bfe_u32 (the compiler would
+// otherwise split it into a shift and a mask).
+template <int OFF, int WIDTH>
+__device__ __forceinline__ uint32_t bfe(uint32_t x) {
+    uint32_t r;
+    asm("v_bfe_u32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "i"(OFF), "i"(WIDTH));
+    return r;
+}
+
+// Read-only device memory seen through the constant address space: loads
+// with a wave-uniform address become scalar loads (s_load), whose results
+// stay in scalar registers.  Only for data that no kernel of the launch writes.
+typedef const __attribute__((address_space(4))) uint32_t* const_u32p;
+__device__ __forceinline__ const_u32p as_const(const uint32_t* p) { return (const_u32p)p; }
 
 // A wave-uniform pointer, forced into scalar registers.
 template <typename T>

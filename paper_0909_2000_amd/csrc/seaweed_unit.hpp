@@ -43,8 +43,9 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     constexpr int FO = FL / WS;  // outputs per flushed block
     const int lane = threadIdx.x & 63;
     const int64_t s0 = sb * 64;
+    const int64_t tlen = pair_tile(g.cols, g.tile, pr);  // windows per tile of this pair
     const int64_t tA = (int64_t)(2 * pr) * g.tile;
-    const int64_t tB = tA + g.tile;
+    const int64_t tB = tA + tlen;
     const int w = EXACT ? WC : g.w;
 
     // x letters of this lane's strip, two rows per register
@@ -62,23 +63,25 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
 
     const int64_t restA = g.cols - tA;  // > 0: every launched unit has a non-empty tile A
     const int64_t nA = (restA + 63) / 64 * 64;
-    const int nproc = (int)(nA < g.tile ? nA : g.tile);
+    const int nproc = (int)(nA < tlen ? nA : tlen);
 
     int32_t org = -w;   // the seaweed starting at tile column l carries label l - org + 1
-    uint32_t cur2 = 0;  // seaweeds counted for the current window, both tiles
+    uint32_t rem2 = pk_rep(w);  // w minus the seaweeds counted for the current window, both tiles
     uint32_t ring_pf = 0;
     const uint32_t w2 = pk_rep(w);
+    constexpr int RB = RW == 16 ? 4 : 5;  // log2 of the ring words per lane
+    uint32_t* const ring_lane = ring + lane;
 
     // y codes of the two tiles (tile starts are multiples of 64, so both
-    // bases are dword aligned); the index is wave-uniform, so the loads and
-    // the unpacking stay on the scalar unit
-    const uint32_t* __restrict__ yA = uniform_ptr(yg32 + (tA >> 1));
-    const uint32_t* __restrict__ yB = uniform_ptr(yg32 + (tB >> 1));
+    // bases are dword aligned); the codes are read-only and the index is
+    // wave-uniform, so the loads and the unpacking stay on the scalar unit
+    const const_u32p yA = as_const(yg32 + (tA >> 1));
+    const const_u32p yB = as_const(yg32 + (tB >> 1));
     auto yload = [&](int l) -> uint32_t {
         const int q = __builtin_amdgcn_readfirstlane(l >> 1);
         const uint32_t sh = (uint32_t)__builtin_amdgcn_readfirstlane(l & 1) * 16u;
         const uint32_t a = yA[q], b = yB[q];
-        return ((a >> sh) & 0xFFFFu) | (((b >> sh) & 0xFFFFu) << 16);
+        return __builtin_amdgcn_readfirstlane(((a >> sh) & 0xFFFFu) | (((b >> sh) & 0xFFFFu) << 16));
     };
     const uint32_t one2 = 0x00010001u;
     uint32_t ynext = yload(0);
@@ -88,9 +91,9 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     auto column = [&](int l) -> uint32_t {
         const uint32_t Y = ynext;
         ynext = yload(l + 1);
-        uint32_t t = pk_rep(l - org + 1);
+        uint32_t t = seaweed_cell_top(h[0], pk_rep(l - org + 1), xc[0], Y);
 #pragma unroll
-        for (int k = 0; k < WC; ++k) {
+        for (int k = 1; k < WC; ++k) {
             if (EXACT || k < w) {
                 t = (k & 1) ? seaweed_cell<1>(h[k], t, xc[k >> 1], Y) : seaweed_cell<0>(h[k], t, xc[k >> 1], Y);
             }
@@ -101,19 +104,20 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         const int pc = l - w;
         if (pc >= 0) {
             f2 = (ring_pf >> (pc & 15)) & 0x00010001u;
-            if ((pc & 15) == 15) ring[((pc >> 4) & (RW - 1)) * 64 + lane] = 0;
+            if ((pc & 15) == 15) ring_lane[((pc >> 4) & (RW - 1)) * 64] = 0;
         }
         // p = start - (l - w + 1) lies in [0, w) iff the exit's span is below w
         const uint32_t p2 = pk_sub(t, pk_rep(l - org + 2 - w));
         const uint32_t v2 = pk_below(w2, p2, one2);
         const uint32_t pos2 = pk_add(p2, pk_rep(l - w + 1));
         const uint32_t bit2 = pk_lshl(pos2, v2);
-        const uint32_t wlo = (pos2 >> 4) & (RW - 1), whi = (pos2 >> 20) & (RW - 1);
-        atomicOr(&ring[wlo * 64 + lane], bit2 & 0xFFFFu);
-        atomicOr(&ring[whi * 64 + lane], bit2 & 0xFFFF0000u);
-        cur2 = pk_sub(pk_add(cur2, v2), f2);
-        if (pc + 1 >= 0) ring_pf = ring[(((pc + 1) >> 4) & (RW - 1)) * 64 + lane];
-        return pk_sub(w2, cur2);
+        // ring word of each mark: bits 4.. of its start column
+        const uint32_t wlo = bfe<4, RB>(pos2), whi = bfe<20, RB>(pos2);
+        atomicOr(&ring_lane[wlo * 64], bit2 & 0xFFFFu);
+        atomicOr(&ring_lane[whi * 64], bit2 & 0xFFFF0000u);
+        rem2 = pk_add(pk_sub(rem2, v2), f2);
+        if (pc + 1 >= 0) ring_pf = ring_lane[(((pc + 1) >> 4) & (RW - 1)) * 64];
+        return rem2;
     };
 
     // warm-up columns: no window is complete yet
@@ -136,9 +140,13 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
             const uint32_t r1 = column(l + 1);
             const uint32_t r2 = column(l + 2);
             const uint32_t r3 = column(l + 3);
-            const uint32_t wa = (r0 & 0xFFu) | ((r1 & 0xFFu) << 8) | ((r2 & 0xFFu) << 16) | ((r3 & 0xFFu) << 24);
-            const uint32_t wb = ((r0 >> 16) & 0xFFu) | (((r1 >> 16) & 0xFFu) << 8) |
-                                (((r2 >> 16) & 0xFFu) << 16) | (((r3 >> 16) & 0xFFu) << 24);
+            // bytes 0 (tile A) and 2 (tile B) of the four results, gathered
+            // into one dword per tile: r0.b0 r0.b2 r1.b0 r1.b2, then the same
+            // for r2, r3, then the even and the odd bytes of the two
+            const uint32_t t01 = __builtin_amdgcn_perm(r1, r0, 0x06040200u);
+            const uint32_t t23 = __builtin_amdgcn_perm(r3, r2, 0x06040200u);
+            const uint32_t wa = __builtin_amdgcn_perm(t23, t01, 0x06040200u);
+            const uint32_t wb = __builtin_amdgcn_perm(t23, t01, 0x07050301u);
             stage[lane * PITCH + gi] = wa;
             stage[64 * PITCH + lane * PITCH + gi] = wb;
         }
@@ -147,7 +155,7 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
 #pragma unroll 1
         for (int half = 0; half < 2; ++half) {
             const int64_t ts = half ? tB : tA;
-            const int64_t te = ts + g.tile < g.cols ? ts + g.tile : g.cols;
+            const int64_t te = ts + tlen < g.cols ? ts + tlen : g.cols;
             const int64_t j0 = ts + jb;   // first (combed) window of the block
             const int64_t o0 = j0 / WS;   // its output column
             // windows of this block inside the tile (0 for the padding block
