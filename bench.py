@@ -38,10 +38,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, cells: float = 0.0):
     """HBM bytes per launch of the timed kernel, from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs, each scaled by what the same counter read for
-    a plain 1 GiB device copy; None when the kernel sources changed since."""
+    a plain 1 GiB device copy; None when the kernel sources changed since.
+    The detail also carries the VALU instruction counters of the same kernel:
+    wave instructions x 64 lanes per cell (5 packed instructions per two cells
+    is 2.5), and the share of SIMD cycles that issued a VALU instruction (a
+    wave64 instruction holds a 16-lane SIMD for 4 cycles; GRBM_GUI_ACTIVE is
+    the busy cycles summed over the 8 XCDs, each with 32 CUs x 4 SIMDs)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"seaweed_counters_{workload.replace('-planted', '')}.json")
     if not os.path.exists(path):
@@ -61,6 +66,14 @@ def measured_traffic(workload: str):
     detail = {"read_bytes": fetch / f_scale, "write_bytes": write / w_scale,
               "fetch_scale": f_scale, "write_scale": w_scale,
               "source": os.path.relpath(path, ROOT)}
+    vc = d.get("valu_counters_per_dispatch")
+    if vc and cells:
+        mean = lambda k: sum(vc[k]) / len(vc[k])
+        insts, gui = mean("SQ_INSTS_VALU"), mean("GRBM_GUI_ACTIVE")
+        detail["valu"] = {"lane_instructions_per_cell": insts * 64 / cells,
+                          "issue_share": insts * 4 / (gui * 32 * 4),
+                          "salu_per_valu": mean("SQ_INSTS_SALU") / insts,
+                          "lds_per_valu": mean("SQ_INSTS_LDS") / insts}
     return detail["read_bytes"] + detail["write_bytes"], detail
 
 
@@ -160,7 +173,7 @@ def main():
     avg_kernel_ms = float(np.mean(kern_ms))
     cells = float(rows) * n * w  # cells the method combs: m-w strips of w x n
     achieved = cells * OPS_PER_CELL / (avg_kernel_ms / 1e3)
-    traffic, traffic_detail = measured_traffic(p.name)
+    traffic, traffic_detail = measured_traffic(p.name, cells)
     algo_bytes = float(m + n) * 2 + float(rows) * cols + (float(rows) * ((cols + 63) // 64) * 8 if thr else 0)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_U16_OPS / 1e12,
                 "unit": "TOP/s", "frac": achieved / PEAK_U16_OPS, "traffic": traffic,
