@@ -48,6 +48,7 @@ extern "C" {
 #define WLCS_EALPHABET (-3) /* bad alphabet, or a string byte outside it */
 #define WLCS_EHIP (-4)      /* HIP runtime or launch failure (wlcs_ctx_last_hip_error) */
 #define WLCS_ENOMEM (-5)    /* host or device allocation failed */
+#define WLCS_EIO (-6)       /* a file could not be written (wlcs_tune's cache) */
 
 #define WLCS_MAX_W 255         /* WLCS values must fit the uint8 output */
 #define WLCS_MAX_SIGMA 64      /* letters per alphabet */
@@ -198,6 +199,43 @@ int wlcs_graph_destroy(wlcs_graph *graph); /* waits for the graph's device memor
  * (workgroups per compute unit, 1..16; 0 restores the default 8). */
 int wlcs_ctx_set_batch_tile(wlcs_ctx *ctx, int32_t w_lo, int32_t w_hi, int32_t tile_windows);
 int wlcs_ctx_set_batch_grid(wlcs_ctx *ctx, int32_t waves_per_cu);
+
+/* What applies now: the tile set for batched plots of window w (0 if the
+ * built-in choice applies), and the persistent grid (0: the default). */
+int wlcs_ctx_get_batch_tile(const wlcs_ctx *ctx, int32_t w, int32_t *tile_windows);
+int wlcs_ctx_get_batch_grid(const wlcs_ctx *ctx, int32_t *waves_per_cu);
+
+/* Autotuner of the batched launch: the y-windows per tile of each window class
+ * (1-16, 17-32, 33-64, 65-128) and the persistent grid, picked by timing real
+ * batched launches of a seeded synthetic batch (128 uniform random DNA pairs,
+ * m, n in 1,000..16,000, 32 per class) on the context's device, and applied
+ * to ctx with wlcs_ctx_set_batch_tile / wlcs_ctx_set_batch_grid.  The search
+ * starts from the built-in choices and changes one knob at a time (each
+ * class's tile in turn: 256..4096; then the grid: 4..16 workgroups per CU),
+ * keeping a candidate only if the whole batch runs faster with it, so the
+ * result never times slower than the built-in choices.  A knob left at its
+ * built-in choice is stored as 0.
+ *
+ *   cache_path  JSON file of results keyed by device ("gfx950-256cu": the
+ *               architecture and compute-unit count).  If it holds an entry
+ *               for this device, the entry is applied and nothing is timed;
+ *               otherwise the tuner runs and the entry is added to the file
+ *               (created if missing; other devices' entries are kept; written
+ *               to a temporary file, then renamed).  NULL: tune, apply, write
+ *               nothing.
+ *   flags       0, or WLCS_TUNE_FORCE to tune even when the cache has an entry
+ *               (the entry is then replaced).
+ *
+ * Synchronous: returns when the tuning launches have completed (a few seconds
+ * of device time; up to about 15 GB of device memory is taken and released).
+ * Errors: WLCS_EINVAL for a bad flag or a cache file that is not a JSON object,
+ * or whose entry for this device does not have the shape above (the file is
+ * then left as it is and nothing is applied); WLCS_EIO if the cache cannot be
+ * written (the tuned values are applied all the same); WLCS_EHIP / WLCS_ENOMEM
+ * from the device.  Window tiling does not change any result, only speed
+ * (Theorem 3.1 holds for every tile). */
+#define WLCS_TUNE_FORCE 1u
+int wlcs_tune(wlcs_ctx *ctx, const char *cache_path, uint32_t flags);
 
 #ifdef __cplusplus
 }

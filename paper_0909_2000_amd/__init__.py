@@ -28,7 +28,8 @@ PROTEIN = b"ACDEFGHIKLMNPQRSTVWY"
 WLCS_FULL_RANGE = 1
 _STATUS = {0: "ok", -1: "invalid argument", -2: "window or length out of range",
            -3: "bad alphabet or letter outside the alphabet", -4: "HIP runtime error",
-           -5: "out of memory"}
+           -5: "out of memory", -6: "file could not be written"}
+WLCS_TUNE_FORCE = 1
 
 
 class WlcsUnavailable(RuntimeError):
@@ -96,11 +97,14 @@ def _load():
     lib.wlcs_graph_destroy.argtypes = [vp]
     lib.wlcs_ctx_set_batch_tile.argtypes = [vp, i32, i32, i32]
     lib.wlcs_ctx_set_batch_grid.argtypes = [vp, i32]
+    lib.wlcs_ctx_get_batch_tile.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    lib.wlcs_ctx_get_batch_grid.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.wlcs_tune.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint32]
     for f in ("wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_ctx_set_tile",
               "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot",
               "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
               "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
-              "wlcs_score_plot"):
+              "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -112,7 +116,7 @@ def exported_symbols() -> list:
             "wlcs_ctx_set_tile", "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy",
             "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
             "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
-            "wlcs_score_plot"]
+            "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune"]
 
 
 def n_windows(length: int, w: int, full_range: bool = False) -> int:
@@ -229,6 +233,31 @@ class Context:
         st = _load().wlcs_ctx_set_batch_grid(self._h, waves_per_cu)
         if st != 0:
             raise WlcsError(st, "wlcs_ctx_set_batch_grid")
+
+    def batch_tile(self, w: int) -> int:
+        """Tile set for batched plots of window w (0: the built-in choice)."""
+        v = ctypes.c_int32(0)
+        st = _load().wlcs_ctx_get_batch_tile(self._h, w, ctypes.byref(v))
+        if st != 0:
+            raise WlcsError(st, "wlcs_ctx_get_batch_tile")
+        return v.value
+
+    def batch_grid(self) -> int:
+        """Persistent grid of the batched launch (0: the default)."""
+        v = ctypes.c_int32(0)
+        st = _load().wlcs_ctx_get_batch_grid(self._h, ctypes.byref(v))
+        if st != 0:
+            raise WlcsError(st, "wlcs_ctx_get_batch_grid")
+        return v.value
+
+    def tune(self, cache_path: str | None = None, force: bool = False):
+        """wlcs_tune: apply this device's entry of the JSON cache, or time the
+        candidates on the device, apply the best and add them to the cache."""
+        lib = _load()
+        path = os.fsencode(cache_path) if cache_path is not None else None
+        st = lib.wlcs_tune(self._h, path, WLCS_TUNE_FORCE if force else 0)
+        if st != 0:
+            raise WlcsError(st, "wlcs_tune", lib.wlcs_ctx_last_hip_error(self._h))
 
     def _jobs(self, specs):
         """specs: dicts with pair, w and optional threshold, indel, full_range,

@@ -1,4 +1,4 @@
-"""Tuner for the tiling knobs of the seaweed kernels.
+"""Tuning of the seaweed kernels' tiling knobs.
 
 Two knobs decide how the batched launch cuts its work:
 
@@ -11,10 +11,13 @@ Two knobs decide how the batched launch cuts its work:
   workgroup" follows from it: every workgroup keeps taking units until the
   queue is empty).
 
-The tuner times real batched launches on the device for each candidate and
-keeps the fastest; the single-plot tile is tuned the same way for a given
-plot shape.  Results go to a JSON cache keyed by device name and compute-unit
-count, and ``apply`` sets them on a context.
+The tuner itself is native: ``Context.tune`` calls ``wlcs_tune``, which times
+real batched launches of a seeded synthetic batch for every candidate on the
+device, applies the fastest and keeps them in a JSON cache keyed by device
+name and compute-unit count (this module's command line rewrites the
+package's cache).  ``tune_batch`` and ``tune_plot`` below do the same search
+on a caller's own batch or plot shape, through the same context setters, and
+``load`` / ``apply`` read the cache format from Python.
 
     python -m paper_0909_2000_amd.autotune --out paper_0909_2000_amd/tuning_gfx950.json
 """
@@ -122,36 +125,17 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   "tuning_gfx950.json"))
-    ap.add_argument("--pairs", type=int, default=128, help="pairs of the batch workload used")
     args = ap.parse_args()
     import torch
 
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     sys.path.insert(0, root)
     import paper_0909_2000_amd as wl
-    import workloads
-
-    def log(*a):
-        print(*a, file=sys.stderr, flush=True)
 
     ctx = wl.Context(0)
-    pairs = workloads.batch_config(seed=40, npairs=args.pairs)  # a tuning set, not the benchmark's
-    specs = [{"pair": ctx.pair(p.x, p.y), "w": p.w} for p in pairs]
-    res = ctx.batch(specs)
-    for s, r in zip(specs, res):
-        s["out"] = r["wlcs"]
-    log(f"tuning on {len(specs)} pairs ({_device_key(torch)})")
-    default_ms = _time(torch, lambda: ctx.batch(specs))
-    entry = tune_batch(ctx, specs, log=log)
-    entry["batch_ms"]["default"] = default_ms
-    data = {}
-    if os.path.exists(args.out):
-        with open(args.out) as f:
-            data = json.load(f)
-    data[_device_key(torch)] = entry
-    with open(args.out, "w") as f:
-        json.dump(data, f, indent=1, sort_keys=True)
-    log(f"default {default_ms:.2f} ms -> tuned {entry['batch_ms']['tuned']:.2f} ms; wrote {args.out}")
+    ctx.tune(args.out, force=True)
+    entry = load(args.out, torch)
+    print(f"tuned on {_device_key(torch)}: {json.dumps(entry)}", file=sys.stderr, flush=True)
     print(json.dumps(entry))
 
 

@@ -15,37 +15,25 @@
 #include "../../include/wlcs.h"
 #include "kernels.hpp"
 
-namespace {
+#include "runtime.hpp"
 
-constexpr int kSlots = 4;  // pinned staging buffers per context
-
-struct Slot {
-    uint8_t* buf = nullptr;
-    size_t cap = 0;
-    hipEvent_t done = nullptr;
-    bool pending = false;
-};
-
-struct TileRule {
-    int32_t lo, hi, tile;
-};
-
-}  // namespace
-
-struct wlcs_ctx {
-    int device = 0;
-    int cus = 256;
-    int last_hip = 0;
-    Slot slots[kSlots];
-    int next_slot = 0;
-    TileRule rules[16];
-    int nrules = 0;
-    TileRule batch_rules[16];
-    int nbatch_rules = 0;
-    int batch_waves_per_cu = 0;  // 0: kBatchWavesPerCu
-};
+using wlcs_rt::kSlots;
+using wlcs_rt::Slot;
+using wlcs_rt::TileRule;
 
 namespace {
+
+// Append a tiling rule (later rules win).  A rule for exactly the same range
+// replaces the earlier one, so setting a range again never fills the table.
+int add_rule(TileRule* rules, int& nrules, TileRule r) {
+    int k = 0;
+    for (int i = 0; i < nrules; ++i)
+        if (!(rules[i].lo == r.lo && rules[i].hi == r.hi)) rules[k++] = rules[i];
+    nrules = k;
+    if (nrules == 16) return WLCS_ENOMEM;
+    rules[nrules++] = r;
+    return WLCS_OK;
+}
 
 // Switch to the context's device for the duration of a call.
 struct DeviceGuard {
@@ -498,6 +486,7 @@ const char* wlcs_status_str(int status) {
         case WLCS_EALPHABET: return "bad alphabet or letter outside the alphabet";
         case WLCS_EHIP: return "HIP runtime error";
         case WLCS_ENOMEM: return "out of memory";
+        case WLCS_EIO: return "file could not be written";
         default: return "unknown status";
     }
 }
@@ -512,9 +501,7 @@ int wlcs_ctx_set_tile(wlcs_ctx* ctx, int32_t w_lo, int32_t w_hi, int32_t tile_wi
         return WLCS_OK;
     }
     if (tile_windows < 64 || tile_windows > 32768 || tile_windows % 64) return WLCS_EINVAL;
-    if (ctx->nrules == 16) return WLCS_ENOMEM;
-    ctx->rules[ctx->nrules++] = TileRule{w_lo, w_hi, tile_windows};
-    return WLCS_OK;
+    return add_rule(ctx->rules, ctx->nrules, TileRule{w_lo, w_hi, tile_windows});
 }
 
 int wlcs_plot(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, int32_t w,
@@ -740,9 +727,7 @@ int wlcs_ctx_set_batch_tile(wlcs_ctx* ctx, int32_t w_lo, int32_t w_hi, int32_t t
         return WLCS_OK;
     }
     if (tile_windows < 64 || tile_windows > kMaxTile || tile_windows % 64) return WLCS_EINVAL;
-    if (ctx->nbatch_rules == 16) return WLCS_ENOMEM;
-    ctx->batch_rules[ctx->nbatch_rules++] = TileRule{w_lo, w_hi, tile_windows};
-    return WLCS_OK;
+    return add_rule(ctx->batch_rules, ctx->nbatch_rules, TileRule{w_lo, w_hi, tile_windows});
 }
 
 int wlcs_ctx_set_batch_grid(wlcs_ctx* ctx, int32_t waves_per_cu) {
