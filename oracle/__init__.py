@@ -48,6 +48,10 @@ def _load():
         lib.oracle_wlcs.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, ctypes.c_int32,
                                     ctypes.c_int32, u8p, ctypes.c_int64, ctypes.c_int32]
         lib.oracle_wlcs.restype = ctypes.c_int
+        lib.oracle_wlcs_strided.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, ctypes.c_int32,
+                                            ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, u8p,
+                                            ctypes.c_int64, ctypes.c_int32]
+        lib.oracle_wlcs_strided.restype = ctypes.c_int
         lib.oracle_wlcs_rows.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, ctypes.c_int32,
                                          ctypes.c_int32, i64p, ctypes.c_int64, u8p,
                                          ctypes.c_int64, ctypes.c_int32]
@@ -115,6 +119,41 @@ def wlcs(x, y, w: int, full_range: bool = False, nthreads: int | None = None) ->
                                 cols, nt)
         if r != 0:
             raise ValueError(f"oracle_wlcs failed ({r})")
+    return out
+
+
+def wlcs_strided(x, y, w: int, hx: int = 1, hy: int = 1, full_range: bool = False,
+                 nthreads: int | None = None) -> np.ndarray:
+    """The plot with step sizes (Section 3): entry (r, c) is WLCS of the
+    x-window starting at r*hx and the y-window starting at c*hy."""
+    x, y = _bytes(x), _bytes(y)
+    if hx < 1 or hy < 1:
+        raise ValueError("steps must be >= 1")
+    rows, cols = n_windows(x.size, w, full_range), n_windows(y.size, w, full_range)
+    orows, ocols = -(-rows // hx), -(-cols // hy)
+    out = np.zeros((orows, ocols), dtype=np.uint8)
+    if orows and ocols:
+        nt = nthreads or default_threads()
+        r = _load().oracle_wlcs_strided(_p(x), x.size, _p(y), y.size, w, hx, hy, int(full_range),
+                                        _p(out), ocols, nt)
+        if r != 0:
+            raise ValueError(f"oracle_wlcs_strided failed ({r})")
+    return out
+
+
+DOT = np.dtype([("i", "<u4"), ("j", "<u4"), ("wlcs", "<u2"), ("indel", "<u2")])
+
+
+def dot_list(plot: np.ndarray, w: int, threshold: int, hx: int = 1, hy: int = 1) -> np.ndarray:
+    """The sparse dot plot (Section 1: a dot for each window pair whose
+    similarity clears a threshold): one record per entry with WLCS >= threshold,
+    holding the window starts i = r*hx, j = c*hy, the WLCS and the indel
+    distance 2w - 2*WLCS, in row-major order of (i, j)."""
+    r, c = np.nonzero(plot >= threshold)
+    out = np.zeros(r.size, dtype=DOT)
+    out["i"], out["j"] = r * hx, c * hy
+    out["wlcs"] = plot[r, c]
+    out["indel"] = 2 * w - 2 * plot[r, c].astype(np.int32)
     return out
 
 

@@ -27,6 +27,10 @@
  *             = max(L[p-1][q], L[p][q-1])        otherwise
  *     LLCS(a, b) = L[|a|][|b|]
  *
+ * With step sizes hx, hy (Section 3: only windows starting at multiples of a
+ * step are compared), oracle_wlcs_strided evaluates the same definition at the
+ * x-windows r*hx and the y-windows c*hy only.
+ *
  * Characters are compared as raw bytes.  Parallelism is over independent rows
  * of the plot only (plain POSIX threads, static partition); each entry is
  * evaluated by the recurrence above in its textbook order.
@@ -87,6 +91,7 @@ typedef struct {
     int32_t w;
     int64_t rows, cols;
     const int64_t *row_ids;   /* NULL: rows 0..rows-1; else the listed x-windows */
+    int64_t hx, hy;           /* steps: output (r, c) is x-window r*hx (or row_ids[r]), y-window c*hy */
     uint8_t *out;
     int64_t ld;
     int64_t r0, r1;           /* this worker's range of output rows */
@@ -99,16 +104,17 @@ static void *rows_worker(void *arg)
     int *tab = (int *)malloc(sizeof(int) * (size_t)(w + 1) * (size_t)(w + 1));
     if (!tab) return (void *)1;
     for (int64_t r = jb->r0; r < jb->r1; ++r) {
-        int64_t i = jb->row_ids ? jb->row_ids[r] : r;
-        for (int64_t j = 0; j < jb->cols; ++j)
-            jb->out[r * jb->ld + j] = (uint8_t)llcs_table(jb->x + i, w, jb->y + j, w, tab);
+        int64_t i = jb->row_ids ? jb->row_ids[r] : r * jb->hx;
+        for (int64_t c = 0; c < jb->cols; ++c)
+            jb->out[r * jb->ld + c] = (uint8_t)llcs_table(jb->x + i, w, jb->y + c * jb->hy, w, tab);
     }
     free(tab);
     return NULL;
 }
 
 static int run_rows(const uint8_t *x, const uint8_t *y, int32_t w, int64_t rows, int64_t cols,
-                    const int64_t *row_ids, uint8_t *out, int64_t ld, int nthreads)
+                    const int64_t *row_ids, int64_t hx, int64_t hy, uint8_t *out, int64_t ld,
+                    int nthreads)
 {
     if (rows == 0 || cols == 0) return ORACLE_OK;
     if (nthreads < 1) nthreads = 1;
@@ -119,7 +125,7 @@ static int run_rows(const uint8_t *x, const uint8_t *y, int32_t w, int64_t rows,
     int started[256];
     int status = ORACLE_OK;
     for (int t = 0; t < nthreads; ++t) {
-        jobs[t] = (rows_job){x, y, w, rows, cols, row_ids, out, ld,
+        jobs[t] = (rows_job){x, y, w, rows, cols, row_ids, hx, hy, out, ld,
                              rows * t / nthreads, rows * (t + 1) / nthreads};
         started[t] = (t > 0) && pthread_create(&th[t], NULL, rows_worker, &jobs[t]) == 0;
         if (t > 0 && !started[t]) status = ORACLE_ENOMEM;
@@ -145,7 +151,23 @@ int oracle_wlcs(const uint8_t *x, int64_t m, const uint8_t *y, int64_t n, int32_
     int64_t rows = n_windows(m, w, full_range), cols = n_windows(n, w, full_range);
     if (rows == 0 || cols == 0) return ORACLE_OK;
     if (!x || !y || !out || ld < cols) return ORACLE_EINVAL;
-    return run_rows(x, y, w, rows, cols, NULL, out, ld, nthreads);
+    return run_rows(x, y, w, rows, cols, NULL, 1, 1, out, ld, nthreads);
+}
+
+/* The plot with step sizes (Section 3: only windows starting at multiples of
+ * a step are compared): out[r*ld + c] = WLCS of x-window r*hx and y-window
+ * c*hy (0-based starts), for the ceil(rows/hx) x ceil(cols/hy) such pairs,
+ * rows and cols counted as in oracle_wlcs. */
+int oracle_wlcs_strided(const uint8_t *x, int64_t m, const uint8_t *y, int64_t n, int32_t w,
+                        int64_t hx, int64_t hy, int32_t full_range, uint8_t *out, int64_t ld,
+                        int32_t nthreads)
+{
+    if (m < 0 || n < 0 || w < 1 || w > 255 || hx < 1 || hy < 1) return ORACLE_EINVAL;
+    int64_t rows = n_windows(m, w, full_range), cols = n_windows(n, w, full_range);
+    int64_t orows = (rows + hx - 1) / hx, ocols = (cols + hy - 1) / hy;
+    if (orows == 0 || ocols == 0) return ORACLE_OK;
+    if (!x || !y || !out || ld < ocols) return ORACLE_EINVAL;
+    return run_rows(x, y, w, orows, ocols, NULL, hx, hy, out, ld, nthreads);
 }
 
 /* Selected rows of the plot: out row r holds x-window row_ids[r] against every
@@ -160,7 +182,7 @@ int oracle_wlcs_rows(const uint8_t *x, int64_t m, const uint8_t *y, int64_t n, i
     if (!x || !y || !out || !row_ids || ld < cols) return ORACLE_EINVAL;
     for (int64_t r = 0; r < nrows; ++r)
         if (row_ids[r] < 0 || row_ids[r] >= rows) return ORACLE_EINVAL;
-    return run_rows(x, y, w, nrows, cols, row_ids, out, ld, nthreads);
+    return run_rows(x, y, w, nrows, cols, row_ids, 1, 1, out, ld, nthreads);
 }
 
 /* Individual entries: out[k] = WLCS at (ii[k], jj[k]) (0-based window starts). */
