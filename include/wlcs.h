@@ -160,6 +160,51 @@ int wlcs_pair_plot_dp(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, uint8_t *
                       uint64_t *bitmap, int64_t ld_words, int32_t threshold, uint16_t *indel,
                       int64_t ld_indel, uint32_t flags, void *stream);
 
+/* ---- strided and sparse plots ---------------------------------------------
+ * Section 3's step size: only windows starting at multiples of a step are
+ * compared.  Output row r is the x-window starting at r*hx, column c the
+ * y-window starting at c*hy (0-based), so rows = ceil((m-w)/hx) and
+ * cols = ceil((n-w)/hy) (over m-w+1 and n-w+1 windows with WLCS_FULL_RANGE).
+ * The x-step divides the seaweed work by hx (only every hx-th strip is
+ * combed); the y-step thins the output (every column of a strip is combed
+ * anyway, and the sliding count visits every window).
+ *
+ * Section 1's dot plot as a list: every (r, c) with WLCS >= threshold, as the
+ * record below (window starts, WLCS, indel distance 2w - 2*WLCS), in no
+ * particular order (the set is the same on every run; the order is not).
+ *
+ *   hx, hy            steps, >= 1 (hx = hy = 1: the plain plot).
+ *   wlcs, ld          uint8 plot over the strided grid, ld >= cols.  May be NULL.
+ *   bitmap, ld_words  as in wlcs_plot, over the strided grid; only with hy = 1
+ *                     (WLCS_EINVAL otherwise: the dot list serves thresholds
+ *                     with a y-step).  May be NULL.
+ *   threshold         for the bitmap and the dot list, 0..255.
+ *   indel, ld_indel   uint16 over the strided grid.  May be NULL.
+ *   dot_count         device uint64: if non-NULL the dots are listed and
+ *                     *dot_count is set (on the stream, also for an empty
+ *                     plot) to their number, which may exceed dot_cap.
+ *   dots, dot_cap     device array of dot_cap records; the first
+ *                     min(*dot_count, dot_cap) dots are written there.  dots
+ *                     may be NULL to count only; non-NULL needs dot_count.
+ * At least one of wlcs, bitmap, indel, dot_count must be given.  Window starts
+ * must fit 32 bits when dots are listed (WLCS_ERANGE otherwise). */
+typedef struct {
+    uint32_t i, j;  /* window starts in x and y (0-based) */
+    uint16_t wlcs;  /* WLCS(i, j) >= threshold */
+    uint16_t indel; /* 2w - 2*WLCS(i, j) */
+} wlcs_dot;
+
+int wlcs_pair_plot_strided(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, int32_t hx, int32_t hy,
+                           uint8_t *wlcs, int64_t ld, uint64_t *bitmap, int64_t ld_words,
+                           int32_t threshold, uint16_t *indel, int64_t ld_indel, wlcs_dot *dots,
+                           int64_t dot_cap, uint64_t *dot_count, uint32_t flags, void *stream);
+/* The same outputs by the plain per-window dynamic program (the paper's
+ * baseline with a step size: its work falls by hx * hy). */
+int wlcs_pair_plot_dp_strided(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, int32_t hx, int32_t hy,
+                              uint8_t *wlcs, int64_t ld, uint64_t *bitmap, int64_t ld_words,
+                              int32_t threshold, uint16_t *indel, int64_t ld_indel, wlcs_dot *dots,
+                              int64_t dot_cap, uint64_t *dot_count, uint32_t flags, void *stream);
+
 /* ---- batched plots ------------------------------------------------------
  * Many plots of uneven m, n and w in one persistent, work-stealing launch: the
  * plots' units (64 x-windows against two y-tiles) go into one device-wide

@@ -17,7 +17,7 @@ import numpy as np
 import torch  # loaded before libwlcs.so so that both share one HIP runtime
 
 __all__ = ["Context", "Pair", "BatchGraph", "Job", "WlcsError", "WlcsUnavailable", "plot", "plot_dp", "n_windows",
-           "library_path", "exported_symbols", "DNA", "PROTEIN"]
+           "library_path", "exported_symbols", "DNA", "PROTEIN", "DOT", "dot_records"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwlcs.so")
@@ -100,11 +100,15 @@ def _load():
     lib.wlcs_ctx_get_batch_tile.argtypes = [vp, i32, ctypes.POINTER(i32)]
     lib.wlcs_ctx_get_batch_grid.argtypes = [vp, ctypes.POINTER(i32)]
     lib.wlcs_tune.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint32]
+    strided_args = [vp, vp, i32, i32, i32, vp, i64, vp, i64, i32, vp, i64, vp, i64, vp, ctypes.c_uint32, vp]
+    lib.wlcs_pair_plot_strided.argtypes = strided_args
+    lib.wlcs_pair_plot_dp_strided.argtypes = strided_args
     for f in ("wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_ctx_set_tile",
               "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot",
               "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
               "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
-              "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune"):
+              "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
+              "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -116,7 +120,24 @@ def exported_symbols() -> list:
             "wlcs_ctx_set_tile", "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy",
             "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
             "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
-            "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune"]
+            "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
+            "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided"]
+
+
+# the wlcs_dot record
+DOT = np.dtype([("i", "<u4"), ("j", "<u4"), ("wlcs", "<u2"), ("indel", "<u2")])
+
+
+def dot_records(res: dict) -> np.ndarray:
+    """The listed dots of a plot_strided result as a numpy record array
+    (fields i, j, wlcs, indel; waits for the device), sorted by (i, j), and
+    the total count (which may exceed the list's capacity)."""
+    torch.cuda.synchronize(res["dot_count"].device)
+    count = int(res["dot_count"].item())
+    dots = res["dots"]
+    k = min(count, int(dots.shape[0])) if dots is not None else 0
+    recs = dots[:k].cpu().numpy().view(DOT).reshape(-1) if k else np.zeros(0, dtype=DOT)
+    return np.sort(recs, order=("i", "j")), count
 
 
 def n_windows(length: int, w: int, full_range: bool = False) -> int:
@@ -400,6 +421,62 @@ class Pair:
                 indel_out=None, want_plot=True, stream=None) -> dict:
         return self._run("wlcs_pair_plot_dp", w, threshold, indel, full_range, out, bitmap_out,
                          indel_out, want_plot, stream)
+
+    def _run_strided(self, fn, w, hx, hy, threshold, indel, want_plot, bitmap, dot_cap, full_range,
+                     out, bitmap_out, indel_out, dots_out, count_out, stream):
+        lib = _load()
+        c = self.ctx
+        rows = -(-n_windows(self.m, w, full_range) // hx) if hx >= 1 else 0
+        cols = -(-n_windows(self.n, w, full_range) // hy) if hy >= 1 else 0
+        if bitmap is None:
+            bitmap = threshold is not None and hy == 1 and dot_cap is None and dots_out is None
+        out, bitmap_out, indel_out = c._outputs(rows, cols, threshold if bitmap else None, indel, out,
+                                                bitmap_out, indel_out, want_plot)
+        dev = torch.device("cuda", c.device)
+        count = None
+        if dot_cap is not None or dots_out is not None:
+            if threshold is None:
+                raise ValueError("a dot list needs a threshold")
+            if dots_out is None and dot_cap:
+                dots_out = torch.empty((int(dot_cap), 3), dtype=torch.int32, device=dev)
+            count = count_out if count_out is not None else torch.empty(1, dtype=torch.int64, device=dev)
+            if count.device != dev or count.dtype != torch.int64 or count.numel() < 1:
+                raise ValueError("count_out must be an int64 tensor on the context's device")
+        cap = int(dots_out.shape[0]) if dots_out is not None else 0
+        if dots_out is not None and (dots_out.device != dev or dots_out.dtype != torch.int32
+                                     or tuple(dots_out.shape[1:]) != (3,) or not dots_out.is_contiguous()):
+            raise ValueError("dots_out must be a contiguous (cap, 3) int32 tensor on the context's device")
+        stream = c._stream(stream)
+        a = c._out_args(out, bitmap_out, indel_out, threshold)
+        st = getattr(lib, fn)(c.handle, self._h, int(w), int(hx), int(hy), *a,
+                              ctypes.c_void_p(dots_out.data_ptr()) if dots_out is not None else None, cap,
+                              ctypes.c_void_p(count.data_ptr()) if count is not None else None,
+                              WLCS_FULL_RANGE if full_range else 0, ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise WlcsError(st, fn, lib.wlcs_ctx_last_hip_error(c.handle))
+        res = c._result(out, bitmap_out, indel_out)
+        if count is not None:
+            res["dots"], res["dot_count"] = dots_out, count
+        return res
+
+    def plot_strided(self, w, hx=1, hy=1, threshold=None, indel=False, want_plot=True, bitmap=None,
+                     dot_cap=None, full_range=False, out=None, bitmap_out=None, indel_out=None,
+                     dots_out=None, count_out=None, stream=None) -> dict:
+        """wlcs_pair_plot_strided: the plot at x-windows r*hx and y-windows
+        c*hy.  With dot_cap (or dots_out) the dots (WLCS >= threshold) are
+        listed too: result "dots" holds wlcs_dot records as a (cap, 3) int32
+        tensor and "dot_count" their number (one int64); read them with
+        dot_records().  bitmap defaults to True when a threshold is given,
+        hy == 1 and no dot list is asked for."""
+        return self._run_strided("wlcs_pair_plot_strided", w, hx, hy, threshold, indel, want_plot, bitmap,
+                                 dot_cap, full_range, out, bitmap_out, indel_out, dots_out, count_out, stream)
+
+    def plot_dp_strided(self, w, hx=1, hy=1, threshold=None, indel=False, want_plot=True, bitmap=None,
+                        dot_cap=None, full_range=False, out=None, bitmap_out=None, indel_out=None,
+                        dots_out=None, count_out=None, stream=None) -> dict:
+        """The same by the plain per-window dynamic program."""
+        return self._run_strided("wlcs_pair_plot_dp_strided", w, hx, hy, threshold, indel, want_plot, bitmap,
+                                 dot_cap, full_range, out, bitmap_out, indel_out, dots_out, count_out, stream)
 
 
 class BatchGraph:

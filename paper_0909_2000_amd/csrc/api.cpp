@@ -327,6 +327,58 @@ int pair_plot_common(Path path, wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w,
     return WLCS_OK;
 }
 
+// Strided and sparse plots on a resident pair (both paths).
+int strided_common(Path path, wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, int32_t hx, int32_t hy, uint8_t* out,
+                   int64_t ld, uint64_t* bitmap, int64_t ld_words, int32_t threshold, uint16_t* indel,
+                   int64_t ld_indel, wlcs_dot* dots, int64_t dot_cap, uint64_t* dot_count, uint32_t flags,
+                   void* stream_) {
+    if (flags & ~WLCS_FULL_RANGE) return WLCS_EINVAL;
+    if (!pair) return WLCS_EINVAL;
+    if (w < 1 || w > WLCS_MAX_W || hx < 1 || hy < 1) return WLCS_ERANGE;
+    const bool full = (flags & WLCS_FULL_RANGE) != 0;
+    const int64_t rows_all = n_windows(pair->m, w, full), cols_all = n_windows(pair->n, w, full);
+    const int64_t rows = (rows_all + hx - 1) / hx, cols = (cols_all + hy - 1) / hy;
+    if (bitmap && hy > 1) return WLCS_EINVAL;  // the dot list serves thresholds on a y-step
+    if (!out && !bitmap && !indel && !dot_count) return WLCS_EINVAL;
+    if (rows > 0 && cols > 0 && (out || bitmap || indel)) {
+        const int st = check_outputs(rows, cols, out, ld, bitmap, ld_words, threshold, indel, ld_indel);
+        if (st != WLCS_OK) return st;
+    }
+    if (dot_count && (threshold < 0 || threshold > 255 || dot_cap < 0)) return WLCS_EINVAL;
+    if (!dot_count && dots) return WLCS_EINVAL;  // a list needs its counter
+    if (dots && rows_all > 0 && cols_all > 0 &&
+        ((rows - 1) * (int64_t)hx > 0xFFFFFFFFll || (cols - 1) * (int64_t)hy > 0xFFFFFFFFll))
+        return WLCS_ERANGE;  // window starts must fit the record's 32-bit fields
+    if (!ctx || ctx->device != pair->device) return WLCS_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
+    hipStream_t stream = (hipStream_t)stream_;
+    if (dot_count) {  // the count is written even when the plot is empty
+        const hipError_t e = wlcs::launch_zero_u64((unsigned long long*)dot_count, stream);
+        if (e != hipSuccess) return fail(ctx, e);
+    }
+    if (rows == 0 || cols == 0) return WLCS_OK;
+    wlcs::PlotArgs a = make_args(rows, path == Path::Seaweed ? cols_all : cols, w, out, ld, bitmap, ld_words,
+                                 threshold, indel, ld_indel);
+    a.xstride = hx;
+    a.hy = hy;
+    a.dots = (wlcs::DotRec*)dots;
+    a.dot_cap = dots ? dot_cap : 0;
+    a.dot_count = (unsigned long long*)dot_count;
+    // strips past the last window read a copy of the last one, so the x codes
+    // read stay below m + the window class; y as for an unstrided plot
+    a.tile = path == Path::Seaweed ? choose_tile(ctx, rows, a.cols, w) : 64;
+    a.npairs = (int32_t)(((a.cols + a.tile - 1) / a.tile + 1) / 2);
+    int64_t xf_len, yg_len;
+    needed_lengths(path, 1, path == Path::Seaweed ? a.cols : cols_all, w, a.tile, xf_len, yg_len);
+    if (pair->m + wlcs::w_class(w) > pair->xf_cap || yg_len > pair->yg_cap) return WLCS_EINVAL;
+    a.xf = pair->xf;
+    a.yg = pair->yg;
+    const hipError_t e = path == Path::Seaweed ? wlcs::launch_seaweed(a, stream) : wlcs::launch_dp(a, stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    return WLCS_OK;
+}
+
 }  // namespace
 
 struct wlcs_graph {
@@ -628,6 +680,22 @@ int wlcs_pair_plot(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, uint8_t* wlc
                    void* stream) {
     return pair_plot_common(Path::Seaweed, ctx, pair, w, wlcs, ld, bitmap, ld_words, threshold, indel, ld_indel,
                             flags, stream);
+}
+
+int wlcs_pair_plot_strided(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, int32_t hx, int32_t hy, uint8_t* wlcs,
+                           int64_t ld, uint64_t* bitmap, int64_t ld_words, int32_t threshold, uint16_t* indel,
+                           int64_t ld_indel, wlcs_dot* dots, int64_t dot_cap, uint64_t* dot_count, uint32_t flags,
+                           void* stream) {
+    return strided_common(Path::Seaweed, ctx, pair, w, hx, hy, wlcs, ld, bitmap, ld_words, threshold, indel,
+                          ld_indel, dots, dot_cap, dot_count, flags, stream);
+}
+
+int wlcs_pair_plot_dp_strided(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, int32_t hx, int32_t hy,
+                              uint8_t* wlcs, int64_t ld, uint64_t* bitmap, int64_t ld_words, int32_t threshold,
+                              uint16_t* indel, int64_t ld_indel, wlcs_dot* dots, int64_t dot_cap,
+                              uint64_t* dot_count, uint32_t flags, void* stream) {
+    return strided_common(Path::Dp, ctx, pair, w, hx, hy, wlcs, ld, bitmap, ld_words, threshold, indel, ld_indel,
+                          dots, dot_cap, dot_count, flags, stream);
 }
 
 int wlcs_pair_plot_dp(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, uint8_t* wlcs, int64_t ld,

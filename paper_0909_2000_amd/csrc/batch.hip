@@ -22,7 +22,7 @@ __device__ __forceinline__ void run_unit(const JobDesc& jd, int64_t local, uint3
     const int64_t nblocks = (jd.g.rows + 63) / 64;
     const int pr = (int)(local / nblocks);
     const int64_t sb = local - (int64_t)pr * nblocks;
-    comb_unit<WC, EXACT>(jd.xf, jd.yg32, jd.out, jd.bm32, jd.indel, jd.g, sb, pr, ring, stage);
+    comb_unit<WC, EXACT>(jd.xf, jd.yg32, jd.out, jd.bm32, jd.indel, nullptr, nullptr, jd.g, sb, pr, ring, stage);
 }
 
 __global__ __launch_bounds__(64, 2) void batch_kernel(const JobDesc* __restrict__ jobs, int32_t njobs,

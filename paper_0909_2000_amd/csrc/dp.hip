@@ -22,7 +22,7 @@ constexpr int kDpChunk = 64;  // y-windows per half per unit
 template <int WC, bool EXACT>
 __global__ __launch_bounds__(64) void dp_kernel(const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32,
                                                 uint8_t* __restrict__ wout, int64_t ldo, int64_t rows, int64_t cols,
-                                                int32_t wrt, int32_t nchunks) {
+                                                int32_t wrt, int32_t nchunks, int64_t xstride, int64_t hy) {
     const int lane = threadIdx.x;
     const int64_t unit = blockIdx.x;
     const int64_t sb = unit / nchunks;
@@ -32,20 +32,24 @@ __global__ __launch_bounds__(64) void dp_kernel(const uint16_t* __restrict__ xf,
     const int w = EXACT ? WC : wrt;
     const uint32_t one2 = 0x00010001u;
 
+    // output (s, j) compares the x-window at s * xstride with the y-window
+    // at j * hy; lanes and windows past the end compute copies of the last
+    // ones, which are never stored
     uint32_t xc[WC / 2];
     {
-        const uint16_t* xp = xf + sb * 64 + lane;
+        const uint16_t* xp = xf + (s < rows ? s : rows - 1) * xstride;
 #pragma unroll
         for (int j = 0; j < WC / 2; ++j) xc[j] = (uint32_t)xp[2 * j] | ((uint32_t)xp[2 * j + 1] << 16);
     }
     for (int jj = 0; jj < kDpChunk; ++jj) {
         const int64_t jA = jA0 + jj, jB = jB0 + jj;
         if (jA >= cols) break;
+        const int64_t yA = jA * hy, yB = (jB < cols ? jB : cols - 1) * hy;
         uint32_t col[WC];  // col[p] = L[p+1][q-1], both windows
 #pragma unroll
         for (int p = 0; p < WC; ++p) col[p] = 0;
         for (int q = 0; q < w; ++q) {
-            const uint32_t Y = u16_at(yg32, jA + q) | (u16_at(yg32, jB + q) << 16);
+            const uint32_t Y = u16_at(yg32, yA + q) | (u16_at(yg32, yB + q) << 16);
             uint32_t up = 0, diag = 0;  // L[p][q], L[p][q-1]
 #pragma unroll
             for (int p = 0; p < WC; ++p) {
@@ -70,12 +74,16 @@ __global__ __launch_bounds__(64) void dp_kernel(const uint16_t* __restrict__ xf,
     }
 }
 
-// bitmap and indel from a finished plot; one wave per 64 windows of a row
+// bitmap, indel and dot list from a finished plot; one wave per 64 windows of
+// a row.  Dots (entries >= threshold) are appended with one vector atomic per
+// wave that has any; entry (r, j) is the window pair (r * xstride, j * hy).
 __global__ __launch_bounds__(256) void epilogue_kernel(const uint8_t* __restrict__ plot, int64_t ld,
                                                        int64_t rows, int64_t cols, int32_t w,
                                                        uint32_t* __restrict__ bitmap32, int64_t ldw32,
                                                        int32_t threshold, uint16_t* __restrict__ indel,
-                                                       int64_t ld_indel) {
+                                                       int64_t ld_indel, DotRec* __restrict__ dots, int64_t dot_cap,
+                                                       unsigned long long* __restrict__ dot_count, int64_t xstride,
+                                                       int64_t hy) {
     const int64_t words = (cols + 63) / 64;
     const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (gw >= rows * words) return;  // whole wave exits together
@@ -85,11 +93,24 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const uint8_t* __restrict
     const bool in = j < cols;
     const int v = in ? plot[r * ld + j] : 0;
     if (indel && in) indel[r * ld_indel + j] = (uint16_t)(2 * w - 2 * v);
-    if (bitmap32) {
+    if (bitmap32 || dot_count) {
         const uint64_t bal = __ballot(in && v >= threshold);
-        if (lane == 0) {
+        if (bitmap32 && lane == 0) {
             bitmap32[r * ldw32 + 2 * q] = (uint32_t)bal;
             bitmap32[r * ldw32 + 2 * q + 1] = (uint32_t)(bal >> 32);
+        }
+        if (dot_count && bal) {  // uniform
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(dot_count, (unsigned long long)__popcll(bal));
+            const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, 0);
+            const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), 0);
+            const unsigned long long k = (((unsigned long long)hi << 32) | lo) + __popcll(bal & ((1ull << lane) - 1ull));
+            if (dots && in && v >= threshold && k < (unsigned long long)dot_cap) {
+                uint32_t* rec = (uint32_t*)(dots + k);
+                rec[0] = (uint32_t)(r * xstride);
+                rec[1] = (uint32_t)(j * hy);
+                rec[2] = (uint32_t)v | ((uint32_t)(2 * w - 2 * v) << 16);
+            }
         }
     }
 }
@@ -104,10 +125,10 @@ hipError_t dp_wc(const PlotArgs& a, uint8_t* wout, int64_t ldo, hipStream_t stre
     const uint32_t* yg32 = (const uint32_t*)a.yg;
     if (a.w == WC)
         hipLaunchKernelGGL((dp_kernel<WC, true>), dim3((uint32_t)units), dim3(64), 0, stream, a.xf, yg32, wout, ldo,
-                           a.rows, a.cols, a.w, (int32_t)nchunks);
+                           a.rows, a.cols, a.w, (int32_t)nchunks, a.xstride, a.hy);
     else
         hipLaunchKernelGGL((dp_kernel<WC, false>), dim3((uint32_t)units), dim3(64), 0, stream, a.xf, yg32, wout,
-                           ldo, a.rows, a.cols, a.w, (int32_t)nchunks);
+                           ldo, a.rows, a.cols, a.w, (int32_t)nchunks, a.xstride, a.hy);
     return hipGetLastError();
 }
 
@@ -137,7 +158,7 @@ hipError_t launch_dp(const PlotArgs& a, hipStream_t stream) {
     uint8_t* wout = a.wlcs;
     int64_t ldo = a.ld;
     hipError_t e = hipSuccess;
-    const bool epi = a.bitmap32 || a.indel;
+    const bool epi = a.bitmap32 || a.indel || a.dot_count;
     if (!wout) {
         e = hipMallocAsync((void**)&wout, (size_t)(a.rows * a.cols), stream);
         if (e != hipSuccess) return e;
@@ -156,7 +177,8 @@ hipError_t launch_dp(const PlotArgs& a, hipStream_t stream) {
         if (blocks > 0x7FFFFFFFll) e = hipErrorInvalidValue;
         else {
             hipLaunchKernelGGL(epilogue_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, wout, ldo, a.rows,
-                               a.cols, a.w, a.bitmap32, a.ld_words32, a.threshold, a.indel, a.ld_indel);
+                               a.cols, a.w, a.bitmap32, a.ld_words32, a.threshold, a.indel, a.ld_indel, a.dots,
+                               a.dot_cap, a.dot_count, a.xstride, a.hy);
             e = hipGetLastError();
         }
     }

@@ -22,10 +22,22 @@ constexpr uint16_t g_code(uint32_t c) { return (uint16_t)(((64u - c) & 63u) << k
 constexpr int kRebase = 512;
 
 // One plot's worth of kernel arguments (host side).
+// One dot of a sparse plot: window starts, WLCS and indel distance (the
+// wlcs_dot record of the C ABI).
+struct DotRec {
+    uint32_t i, j;
+    uint16_t wlcs, indel;
+};
+static_assert(sizeof(DotRec) == 12, "dot record layout");
+
 struct PlotArgs {
     int64_t xstride = 1;     // x codes between consecutive strips
     int32_t ws = 1;          // store every ws-th combed window (1 or 2)
     int32_t bias = 0;        // subtracted from every stored value
+    int64_t hy = 1;          // strided plots: output column c is the window c * hy
+    DotRec* dots = nullptr;  // sparse output (may be null while counting)
+    int64_t dot_cap = 0;
+    unsigned long long* dot_count = nullptr;  // non-null: list the dots
     const uint16_t* xf;      // f-codes of x, padded (see host runtime)
     const uint16_t* yg;      // g-codes of y, padded
     int64_t rows;            // x-windows (strips)
@@ -51,6 +63,8 @@ struct Geom {
     int32_t w, tile, npairs, threshold;
     int32_t wmode;     // plot stores: 2 = 16-byte rows, 1 = 4-byte rows, 0 = bytes
     int32_t bias;      // subtracted from every stored value (0..127)
+    int64_t hy;        // strided plots: output column c is the window c * hy
+    int64_t dot_cap;   // dot records the sparse output holds
 };
 
 // Windows per tile in tile pair pr of a row of cols windows: the full tile,
@@ -78,6 +92,8 @@ inline Geom geom_of(const PlotArgs& a) {
     g.ocols = a.ws == 2 ? a.cols / 2 : a.cols;
     g.xstride = a.xstride;
     g.bias = a.bias;
+    g.hy = a.hy;
+    g.dot_cap = a.dot_cap;
     const uintptr_t base = (uintptr_t)a.wlcs;
     g.wmode = (a.ld % 16 == 0 && base % 16 == 0) ? 2 : (a.ld % 4 == 0 && base % 4 == 0) ? 1 : 0;
     return g;
@@ -102,6 +118,7 @@ inline int w_class(int w) { return w <= 16 ? 16 : w <= 32 ? 32 : w <= 64 ? 64 : 
 hipError_t launch_encode(const uint8_t* raw, int64_t len, const uint8_t* map256, int x_side,
                          uint16_t* out, int64_t out_len, hipStream_t stream, int sep = -1);
 hipError_t launch_seaweed(const PlotArgs& a, hipStream_t stream);
+hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream);
 hipError_t launch_dp(const PlotArgs& a, hipStream_t stream);
 int batch_variant(int w);
 constexpr int kBatchMaxW = 128;            // longer windows leave the batched kernel

@@ -46,17 +46,25 @@
 //    32 bytes per tile (16-byte or 4-byte stores when the row stride allows,
 //    else the block is transposed through LDS into coalesced byte stores),
 //    plus the bitmap word and the uint16 indel distances when requested.
+//  * strided and sparse plots (the step size of Section 3, the dot plot of
+//    Section 1): every x-window at a multiple of hx is a strip (hx x codes
+//    between strips), every window is combed and counted, and each flushed
+//    block stores only its windows at multiples of hy, and/or appends the
+//    windows at or above the threshold to a list of dots.
 #include "seaweed_unit.hpp"
 
 namespace wlcs {
 namespace {
 
-template <int WC, bool EXACT, int WS>
+template <int WC, bool EXACT, int WS, bool SP>
 __global__ __launch_bounds__(64, min_waves_per_simd(WC)) void seaweed_kernel(const uint16_t* __restrict__ xf,
                                                                               const uint32_t* __restrict__ yg32,
                                                                               uint8_t* __restrict__ out,
                                                                               uint32_t* __restrict__ bm32,
-                                                                              uint16_t* __restrict__ indel, Geom g) {
+                                                                              uint16_t* __restrict__ indel,
+                                                                              DotRec* __restrict__ dots,
+                                                                              unsigned long long* __restrict__ dot_count,
+                                                                              Geom g) {
     __shared__ uint32_t ring[ring_words(WC) * 64];
     __shared__ uint32_t stage[stage_dwords(WC, WS)];
     // pair-major order: the last tile pair of every strip block (usually
@@ -66,18 +74,22 @@ __global__ __launch_bounds__(64, min_waves_per_simd(WC)) void seaweed_kernel(con
     const int64_t unit = blockIdx.x;
     const int pr = (int)(unit / nblocks);
     const int64_t sb = unit - (int64_t)pr * nblocks;
-    comb_unit<WC, EXACT, WS>(xf, yg32, out, bm32, indel, g, sb, pr, ring, stage);
+    comb_unit<WC, EXACT, WS, SP>(xf, yg32, out, bm32, indel, dots, dot_count, g, sb, pr, ring, stage);
 }
 
-template <int WC, int WS>
+__global__ void zero_u64(unsigned long long* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+}
+
+template <int WC, int WS, bool SP>
 void launch_ws(const PlotArgs& a, const Geom& g, uint32_t units, hipStream_t stream) {
     const uint32_t* yg32 = (const uint32_t*)a.yg;
     if (a.w == WC)
-        hipLaunchKernelGGL((seaweed_kernel<WC, true, WS>), dim3(units), dim3(64), 0, stream, a.xf, yg32, a.wlcs,
-                           a.bitmap32, a.indel, g);
+        hipLaunchKernelGGL((seaweed_kernel<WC, true, WS, SP>), dim3(units), dim3(64), 0, stream, a.xf, yg32, a.wlcs,
+                           a.bitmap32, a.indel, a.dots, a.dot_count, g);
     else
-        hipLaunchKernelGGL((seaweed_kernel<WC, false, WS>), dim3(units), dim3(64), 0, stream, a.xf, yg32, a.wlcs,
-                           a.bitmap32, a.indel, g);
+        hipLaunchKernelGGL((seaweed_kernel<WC, false, WS, SP>), dim3(units), dim3(64), 0, stream, a.xf, yg32, a.wlcs,
+                           a.bitmap32, a.indel, a.dots, a.dot_count, g);
 }
 
 template <int WC>
@@ -88,13 +100,20 @@ hipError_t launch_wc(const PlotArgs& a, hipStream_t stream) {
     if (units > 0x7FFFFFFFll) return hipErrorInvalidValue;
     const Geom g = geom_of(a);
     if (a.ws == 2)
-        launch_ws<WC, 2>(a, g, (uint32_t)units, stream);
+        launch_ws<WC, 2, false>(a, g, (uint32_t)units, stream);
+    else if (a.hy > 1 || a.dot_count)
+        launch_ws<WC, 1, true>(a, g, (uint32_t)units, stream);
     else
-        launch_ws<WC, 1>(a, g, (uint32_t)units, stream);
+        launch_ws<WC, 1, false>(a, g, (uint32_t)units, stream);
     return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream) {
+    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, stream, p);
+    return hipGetLastError();
+}
 
 hipError_t launch_seaweed(const PlotArgs& a, hipStream_t stream) {
     switch (w_class(a.w)) {

@@ -32,11 +32,68 @@ constexpr int stage_dwords(int wc, int ws = 1) { return 2 * 64 * stage_pitch(wc,
 // and w/2 code registers per lane plus the flush temporaries must fit.
 constexpr int min_waves_per_simd(int wc) { return wc <= 32 ? 4 : wc <= 64 ? 3 : wc <= 128 ? 2 : 1; }
 
-template <int WC, bool EXACT, int WS = 1>
+// Stores of a strided or sparse plot for one flushed block: window j0 + b of
+// strip s0 + r sits in byte b of row r of the staged block (stride pitch
+// dwords).  Output column c holds the window c * hy; the lanes of the wave
+// cover the block's output columns of one strip at a time, so the stores of a
+// strip are contiguous.  Dots (windows with WLCS >= threshold) are appended to
+// the list: one vector atomic per strip and block that has any, reserving a
+// run of slots the hitting lanes fill in lane order.  The counter keeps
+// counting past dot_cap; records beyond it are not written.
+__device__ __forceinline__ void strided_flush(uint8_t* __restrict__ out, uint16_t* __restrict__ indel,
+                                              DotRec* __restrict__ dots, unsigned long long* __restrict__ dot_count,
+                                              const Geom& g, int64_t s0, int64_t j0, int nk, int w,
+                                              const uint8_t* staged, int pitch) {
+    if (nk <= 0) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t hy = g.hy;
+    const int64_t c_lo = (j0 + hy - 1) / hy;
+    const int nout = (int)((j0 + nk + hy - 1) / hy - c_lo);  // <= 64
+    if (nout <= 0) return;
+    const bool act = lane < nout;
+    const int64_t c = c_lo + lane;
+    const int b = act ? (int)(c * hy - j0) : 0;
+    const bool dense = g.hy > 1;
+#pragma unroll 1
+    for (int r = 0; r < 64; ++r) {
+        const int64_t s = s0 + r;
+        if (s >= g.rows) break;  // uniform
+        const uint32_t v = staged[r * pitch * 4 + b];
+        if (act && dense) {
+            if (out) out[s * g.ld + c] = (uint8_t)v;
+            if (indel) indel[s * g.ld_indel + c] = (uint16_t)(2 * w - 2 * (int)v);
+        }
+        if (dot_count) {
+            const bool hit = act && (int)v >= g.threshold;
+            const uint64_t mask = __ballot(hit);
+            if (mask) {  // uniform
+                const int leader = __builtin_ctzll(mask);
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(dot_count, (unsigned long long)__popcll(mask));
+                const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
+                const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
+                const unsigned long long k =
+                    (((unsigned long long)hi << 32) | lo) + __popcll(mask & ((1ull << lane) - 1ull));
+                if (hit && dots && k < (unsigned long long)g.dot_cap) {
+                    uint32_t* rec = (uint32_t*)(dots + k);
+                    rec[0] = (uint32_t)(s * g.xstride);
+                    rec[1] = (uint32_t)(c * hy);
+                    rec[2] = v | ((uint32_t)(2 * w - 2 * (int)v) << 16);
+                }
+            }
+        }
+    }
+}
+
+// SP: the strided / sparse variant (store every g.hy-th window and list the
+// dots of the windows at or above the threshold; WS = 1 only).
+template <int WC, bool EXACT, int WS = 1, bool SP = false>
 __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32,
                                           uint8_t* __restrict__ out, uint32_t* __restrict__ bm32,
-                                          uint16_t* __restrict__ indel, const Geom& g, int64_t sb, int pr,
-                                          uint32_t* __restrict__ ring, uint32_t* __restrict__ stage) {
+                                          uint16_t* __restrict__ indel, DotRec* __restrict__ dots,
+                                          unsigned long long* __restrict__ dot_count, const Geom& g, int64_t sb,
+                                          int pr, uint32_t* __restrict__ ring, uint32_t* __restrict__ stage) {
+    static_assert(!SP || WS == 1, "strided and sparse plots store single windows");
     constexpr int RW = ring_words(WC);
     constexpr int FL = flush_windows(WC, WS);
     constexpr int PITCH = stage_pitch(WC, WS);
@@ -48,10 +105,12 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     const int64_t tB = tA + tlen;
     const int w = EXACT ? WC : g.w;
 
-    // x letters of this lane's strip, two rows per register
+    // x letters of this lane's strip, two rows per register (lanes past the
+    // last strip comb a copy of the last one; their results are never stored)
     uint32_t xc[WC / 2];
     {
-        const uint16_t* xp = xf + (s0 + lane) * g.xstride;
+        const int64_t sx = s0 + lane < g.rows ? s0 + lane : g.rows - 1;
+        const uint16_t* xp = xf + sx * g.xstride;
 #pragma unroll
         for (int j = 0; j < WC / 2; ++j) xc[j] = (uint32_t)xp[2 * j] | ((uint32_t)xp[2 * j + 1] << 16);
     }
@@ -162,6 +221,11 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
             // that completes the last bitmap word, or past the end of y);
             // with WS = 2 only the even ones are outputs
             const int nk = (int)(te - j0 < FL ? (te - j0 > 0 ? te - j0 : 0) : FL);
+            if (SP) {
+                if (g.hy > 1 || dot_count) strided_flush(out, indel, dots, dot_count, g, s0, j0, nk, w,
+                                                         (const uint8_t*)(stage + half * 64 * PITCH), PITCH);
+                if (g.hy > 1) continue;  // uniform
+            }
             const int nvalid = (nk + WS - 1) / WS;
             if (nvalid == 0 && (uint32_t)(o0 >> 5) >= bm_words) continue;  // uniform
             uint32_t d[FO / 4];
