@@ -186,7 +186,8 @@ int wlcs_pair_plot_dp(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, uint8_t *
  *   dots, dot_cap     device array of dot_cap records; the first
  *                     min(*dot_count, dot_cap) dots are written there.  dots
  *                     may be NULL to count only; non-NULL needs dot_count.
- * At least one of wlcs, bitmap, indel, dot_count must be given.  Window starts
+ * At least one of wlcs, bitmap, indel, dot_count must be given unless the plot
+ * is empty (then the call only sets *dot_count to 0).  Window starts
  * must fit 32 bits when dots are listed (WLCS_ERANGE otherwise). */
 typedef struct {
     uint32_t i, j;  /* window starts in x and y (0-based) */
@@ -222,9 +223,16 @@ typedef struct {
     int32_t threshold;
     uint16_t *indel;
     int64_t ld_indel;
+    /* strided and sparse outputs, as in wlcs_pair_plot_strided (a job left
+     * zero-filled here is a plain plot: steps 0 and 1 both mean every window) */
+    int32_t hx, hy;
+    wlcs_dot *dots;
+    int64_t dot_cap;
+    uint64_t *dot_count;
 } wlcs_job;
 
-/* Enqueue all njobs plots on `stream`.  Jobs are checked on the host first; a
+/* Enqueue all njobs plots on `stream`.  Jobs are checked on the host first
+ * (with the rules of wlcs_pair_plot_strided for steps and dot lists); a
  * bad job fails the whole call before anything is enqueued.  The job array and
  * the table built from it are consumed before the call returns; pairs and
  * outputs must stay valid until the stream has run the batch. */

@@ -52,7 +52,8 @@ class Job(ctypes.Structure):
                 ("wlcs", ctypes.c_void_p), ("ld", ctypes.c_int64),
                 ("bitmap", ctypes.c_void_p), ("ld_words", ctypes.c_int64),
                 ("threshold", ctypes.c_int32), ("indel", ctypes.c_void_p),
-                ("ld_indel", ctypes.c_int64)]
+                ("ld_indel", ctypes.c_int64), ("hx", ctypes.c_int32), ("hy", ctypes.c_int32),
+                ("dots", ctypes.c_void_p), ("dot_cap", ctypes.c_int64), ("dot_count", ctypes.c_void_p)]
 
 
 _lib = None
@@ -282,22 +283,47 @@ class Context:
 
     def _jobs(self, specs):
         """specs: dicts with pair, w and optional threshold, indel, full_range,
-        want_plot, out, bitmap_out, indel_out.  Returns (Job array, results)."""
+        want_plot, out, bitmap_out, indel_out, and for strided or sparse jobs
+        hx, hy, bitmap (default: a threshold and hy == 1 and no dot list),
+        dot_cap, dots_out, count_out (as Pair.plot_strided).  Returns (Job
+        array, results)."""
         arr = (Job * max(len(specs), 1))()
         results = []
+        dev = torch.device("cuda", self.device)
         for k, sp in enumerate(specs):
             pair, w = sp["pair"], int(sp["w"])
+            hx, hy = int(sp.get("hx", 1)), int(sp.get("hy", 1))
             full = bool(sp.get("full_range", False))
-            rows, cols = n_windows(pair.m, w, full), n_windows(pair.n, w, full)
+            rows = -(-n_windows(pair.m, w, full) // max(hx, 1))
+            cols = -(-n_windows(pair.n, w, full) // max(hy, 1))
             thr = sp.get("threshold")
-            out, bm, ind = self._outputs(rows, cols, thr, sp.get("indel", False), sp.get("out"),
-                                         sp.get("bitmap_out"), sp.get("indel_out"),
+            listing = sp.get("dot_cap") is not None or sp.get("dots_out") is not None
+            bitmap = sp.get("bitmap")
+            if bitmap is None:
+                bitmap = thr is not None and hy == 1 and not listing
+            out, bm, ind = self._outputs(rows, cols, thr if bitmap else None, sp.get("indel", False),
+                                         sp.get("out"), sp.get("bitmap_out"), sp.get("indel_out"),
                                          sp.get("want_plot", True))
             o = self._out_args(out, bm, ind, thr)
+            dots, count = sp.get("dots_out"), None
+            if listing:
+                if thr is None:
+                    raise ValueError("a dot list needs a threshold")
+                if dots is None and sp.get("dot_cap"):
+                    dots = torch.empty((int(sp["dot_cap"]), 3), dtype=torch.int32, device=dev)
+                count = sp.get("count_out")
+                if count is None:
+                    count = torch.empty(1, dtype=torch.int64, device=dev)
             arr[k] = Job(pair._h.value, w, WLCS_FULL_RANGE if full else 0, o[0].value if o[0] else None,
                          o[1], o[2].value if o[2] else None, o[3], o[4],
-                         o[5].value if o[5] else None, o[6])
-            results.append(self._result(out, bm, ind))
+                         o[5].value if o[5] else None, o[6], hx, hy,
+                         dots.data_ptr() if dots is not None else None,
+                         int(dots.shape[0]) if dots is not None else 0,
+                         count.data_ptr() if count is not None else None)
+            res = self._result(out, bm, ind)
+            if listing:
+                res["dots"], res["dot_count"] = dots, count
+            results.append(res)
         return arr, results
 
     def batch(self, specs, stream=None) -> list:

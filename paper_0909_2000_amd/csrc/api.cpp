@@ -339,7 +339,7 @@ int strided_common(Path path, wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, i
     const int64_t rows_all = n_windows(pair->m, w, full), cols_all = n_windows(pair->n, w, full);
     const int64_t rows = (rows_all + hx - 1) / hx, cols = (cols_all + hy - 1) / hy;
     if (bitmap && hy > 1) return WLCS_EINVAL;  // the dot list serves thresholds on a y-step
-    if (!out && !bitmap && !indel && !dot_count) return WLCS_EINVAL;
+    if (rows > 0 && cols > 0 && !out && !bitmap && !indel && !dot_count) return WLCS_EINVAL;
     if (rows > 0 && cols > 0 && (out || bitmap || indel)) {
         const int st = check_outputs(rows, cols, out, ld, bitmap, ld_words, threshold, indel, ld_indel);
         if (st != WLCS_OK) return st;
@@ -385,6 +385,7 @@ struct wlcs_graph {
     int device = 0;
     wlcs::JobDesc* table = nullptr;
     unsigned long long* counter = nullptr;
+    unsigned long long** counts = nullptr;  // the jobs' dot counters (zeroed by each replay)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -406,7 +407,9 @@ int32_t batch_tile(const wlcs_ctx* ctx, int64_t cols, int32_t w) {
 struct BatchPlan {
     std::vector<wlcs::JobDesc> table;  // jobs with w <= kBatchMaxW, by decreasing unit cost
     std::vector<wlcs::PlotArgs> singles;  // longer windows: single-plot launches
+    std::vector<unsigned long long*> counts;  // every job's dot counter, zeroed first
     int64_t total_units = 0;
+    bool sparse = false;  // some batched job is strided or lists dots
 };
 
 int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& plan) {
@@ -420,16 +423,32 @@ int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& pl
         const wlcs_job& j = jobs[k];
         if (j.flags & ~WLCS_FULL_RANGE) return WLCS_EINVAL;
         if (!j.pair || j.pair->device != ctx->device) return WLCS_EINVAL;
-        if (j.w < 1 || j.w > WLCS_MAX_W) return WLCS_ERANGE;
+        if (j.w < 1 || j.w > WLCS_MAX_W || j.hx < 0 || j.hy < 0) return WLCS_ERANGE;
+        const int64_t hx = j.hx > 1 ? j.hx : 1, hy = j.hy > 1 ? j.hy : 1;
         const bool full = (j.flags & WLCS_FULL_RANGE) != 0;
-        const int64_t rows = n_windows(j.pair->m, j.w, full), cols = n_windows(j.pair->n, j.w, full);
-        int st = check_outputs(rows, cols, j.wlcs, j.ld, j.bitmap, j.ld_words, j.threshold, j.indel, j.ld_indel);
-        if (st != WLCS_OK) return st;
+        const int64_t rows_all = n_windows(j.pair->m, j.w, full), cols = n_windows(j.pair->n, j.w, full);
+        const int64_t rows = (rows_all + hx - 1) / hx, ocols = (cols + hy - 1) / hy;
+        if (rows > 0 && ocols > 0 && !j.wlcs && !j.bitmap && !j.indel && !j.dot_count) return WLCS_EINVAL;
+        if ((j.bitmap && hy > 1) || (j.dots && !j.dot_count)) return WLCS_EINVAL;
+        if (j.dot_count && (j.threshold < 0 || j.threshold > 255 || j.dot_cap < 0)) return WLCS_EINVAL;
+        if (j.wlcs || j.bitmap || j.indel) {
+            const int st = check_outputs(rows, ocols, j.wlcs, j.ld, j.bitmap, j.ld_words, j.threshold, j.indel,
+                                         j.ld_indel);
+            if (st != WLCS_OK) return st;
+        }
+        if (j.dots && rows > 0 && ocols > 0 && ((rows - 1) * hx > 0xFFFFFFFFll || (ocols - 1) * hy > 0xFFFFFFFFll))
+            return WLCS_ERANGE;
+        if (j.dot_count) plan.counts.push_back((unsigned long long*)j.dot_count);
         if (rows == 0 || cols == 0) continue;
         wlcs::PlotArgs a =
             make_args(rows, cols, j.w, j.wlcs, j.ld, j.bitmap, j.ld_words, j.threshold, j.indel, j.ld_indel);
         a.xf = j.pair->xf;
         a.yg = j.pair->yg;
+        a.xstride = hx;
+        a.hy = hy;
+        a.dots = (wlcs::DotRec*)j.dots;
+        a.dot_cap = j.dots ? j.dot_cap : 0;
+        a.dot_count = (unsigned long long*)j.dot_count;
         if (j.w > wlcs::kBatchMaxW) {
             a.tile = choose_tile(ctx, rows, cols, j.w);
             a.npairs = (int32_t)(((cols + a.tile - 1) / a.tile + 1) / 2);
@@ -447,7 +466,10 @@ int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& pl
         it.d.out = a.wlcs;
         it.d.bm32 = a.bitmap32;
         it.d.indel = a.indel;
+        it.d.dots = a.dots;
+        it.d.dot_count = a.dot_count;
         it.d.g = wlcs::geom_of(a);
+        if (hy > 1 || a.dot_count) plan.sparse = true;
         it.d.unit0 = (rows + 63) / 64 * a.npairs;  // unit count for now
         it.d.variant = wlcs::batch_variant(j.w);
         it.d.pad = 0;
@@ -471,13 +493,14 @@ int batch_grid(const wlcs_ctx* ctx, int64_t total_units) {
     return (int)std::min<int64_t>(total_units, (int64_t)ctx->cus * per_cu);
 }
 
-// Enqueue a planned batch whose job table already sits at table_dev.
+// Enqueue a planned batch whose job table already sits at table_dev and the
+// list of its dot counters at counts_dev.
 hipError_t enqueue_batch(const wlcs_ctx* ctx, const BatchPlan& plan, const wlcs::JobDesc* table_dev,
-                         unsigned long long* counter, hipStream_t stream) {
-    hipError_t e = hipSuccess;
-    if (!plan.table.empty())
+                         unsigned long long* counter, unsigned long long* const* counts_dev, hipStream_t stream) {
+    hipError_t e = wlcs::launch_zero_each(counts_dev, (int32_t)plan.counts.size(), stream);
+    if (e == hipSuccess && !plan.table.empty())
         e = wlcs::launch_batch(table_dev, (int32_t)plan.table.size(), plan.total_units, counter,
-                               batch_grid(ctx, plan.total_units), stream);
+                               batch_grid(ctx, plan.total_units), plan.sparse, stream);
     for (size_t k = 0; e == hipSuccess && k < plan.singles.size(); ++k) e = wlcs::launch_seaweed(plan.singles[k], stream);
     return e;
 }
@@ -709,24 +732,28 @@ int wlcs_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, void* stream_
     BatchPlan plan;
     int st = plan_batch(ctx, jobs, njobs, plan);
     if (st != WLCS_OK) return st;
-    if (plan.table.empty() && plan.singles.empty()) return WLCS_OK;
+    if (plan.table.empty() && plan.singles.empty() && plan.counts.empty()) return WLCS_OK;
+    if (plan.counts.size() > 0x7FFFFFFF) return WLCS_ERANGE;
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
     hipStream_t stream = (hipStream_t)stream_;
     const size_t tbytes = plan.table.size() * sizeof(wlcs::JobDesc);
     const size_t cnt_off = (tbytes + 255) / 256 * 256;
-    uint8_t* dev = nullptr;  // job table, then the 8-byte work counter at cnt_off
-    hipError_t e = hipSuccess;
-    if (!plan.table.empty()) {
-        if ((e = hipMallocAsync((void**)&dev, cnt_off + 256, stream)) != hipSuccess) return fail(ctx, e);
-        st = stage_copy(ctx, plan.table.data(), tbytes, dev, stream);
-        if (st != WLCS_OK) {
-            (void)hipFreeAsync(dev, stream);
-            return st;
-        }
+    const size_t ptr_off = cnt_off + 256, pbytes = plan.counts.size() * sizeof(unsigned long long*);
+    // job table, the 8-byte work counter at cnt_off, the dot counters' addresses at ptr_off
+    std::vector<uint8_t> host(ptr_off + pbytes, 0);
+    if (tbytes) memcpy(host.data(), plan.table.data(), tbytes);
+    if (pbytes) memcpy(host.data() + ptr_off, plan.counts.data(), pbytes);
+    uint8_t* dev = nullptr;
+    hipError_t e = hipMallocAsync((void**)&dev, host.size(), stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    st = stage_copy(ctx, host.data(), host.size(), dev, stream);
+    if (st != WLCS_OK) {
+        (void)hipFreeAsync(dev, stream);
+        return st;
     }
-    e = enqueue_batch(ctx, plan, (const wlcs::JobDesc*)dev, dev ? (unsigned long long*)(dev + cnt_off) : nullptr,
-                      stream);
+    e = enqueue_batch(ctx, plan, (const wlcs::JobDesc*)dev, (unsigned long long*)(dev + cnt_off),
+                      (unsigned long long* const*)(dev + ptr_off), stream);
     if (dev) (void)hipFreeAsync(dev, stream);
     if (e != hipSuccess) return fail(ctx, e);
     return WLCS_OK;
@@ -745,13 +772,17 @@ int wlcs_batch_graph(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, wlcs_gr
     g->device = ctx->device;
     const size_t tbytes = plan.table.size() * sizeof(wlcs::JobDesc);
     hipStream_t cap = nullptr;
-    hipError_t e = hipMalloc((void**)&g->table, std::max<size_t>(tbytes, 64));
+    const size_t pbytes = plan.counts.size() * sizeof(unsigned long long*);
+    hipError_t e = plan.counts.size() > 0x7FFFFFFF ? hipErrorInvalidValue : hipSuccess;
+    if (e == hipSuccess) e = hipMalloc((void**)&g->table, std::max<size_t>(tbytes, 64));
     if (e == hipSuccess) e = hipMalloc((void**)&g->counter, 256);
+    if (e == hipSuccess) e = hipMalloc((void**)&g->counts, std::max<size_t>(pbytes, 64));
     if (e == hipSuccess && tbytes) e = hipMemcpy(g->table, plan.table.data(), tbytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && pbytes) e = hipMemcpy(g->counts, plan.counts.data(), pbytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t el = enqueue_batch(ctx, plan, g->table, g->counter, cap);
+        hipError_t el = enqueue_batch(ctx, plan, g->table, g->counter, g->counts, cap);
         e = hipStreamEndCapture(cap, &g->graph);
         if (el != hipSuccess) e = el;
     }
@@ -780,6 +811,7 @@ int wlcs_graph_destroy(wlcs_graph* graph) {
     if (graph->graph && hipGraphDestroy(graph->graph) != hipSuccess) st = WLCS_EHIP;
     if (graph->table && hipFree(graph->table) != hipSuccess) st = WLCS_EHIP;
     if (graph->counter && hipFree(graph->counter) != hipSuccess) st = WLCS_EHIP;
+    if (graph->counts && hipFree(graph->counts) != hipSuccess) st = WLCS_EHIP;
     delete graph;
     return st;
 }

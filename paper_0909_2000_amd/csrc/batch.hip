@@ -10,21 +10,25 @@
 // kernel.  Jobs are ordered by decreasing unit cost so the tail of the queue
 // holds the cheapest units.  Windows up to 128 run here; longer windows run
 // as separate single-plot launches on the same stream.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "seaweed_unit.hpp"
 
 namespace wlcs {
 namespace {
 
-template <int WC, bool EXACT>
+template <int WC, bool EXACT, bool SP>
 __device__ __forceinline__ void run_unit(const JobDesc& jd, int64_t local, uint32_t* ring, uint32_t* stage) {
     // pair-major within a job, as in the single-plot kernel
     const int64_t nblocks = (jd.g.rows + 63) / 64;
     const int pr = (int)(local / nblocks);
     const int64_t sb = local - (int64_t)pr * nblocks;
-    comb_unit<WC, EXACT>(jd.xf, jd.yg32, jd.out, jd.bm32, jd.indel, nullptr, nullptr, jd.g, sb, pr, ring, stage);
+    comb_unit<WC, EXACT, 1, SP>(jd.xf, jd.yg32, jd.out, jd.bm32, jd.indel, SP ? jd.dots : nullptr,
+                                SP ? jd.dot_count : nullptr, jd.g, sb, pr, ring, stage);
 }
 
+template <bool SP>
 __global__ __launch_bounds__(64, 2) void batch_kernel(const JobDesc* __restrict__ jobs, int32_t njobs,
                                                       int64_t total_units, unsigned long long* __restrict__ counter) {
     __shared__ uint32_t ring[ring_words(128) * 64];
@@ -51,17 +55,21 @@ __global__ __launch_bounds__(64, 2) void batch_kernel(const JobDesc* __restrict_
         const JobDesc jd = jobs[lo];
         const int64_t local = (int64_t)u - jd.unit0;
         switch (jd.variant) {
-            case 0: run_unit<16, true>(jd, local, ring, stage); break;
-            case 1: run_unit<32, true>(jd, local, ring, stage); break;
-            case 2: run_unit<64, true>(jd, local, ring, stage); break;
-            case 3: run_unit<128, true>(jd, local, ring, stage); break;
-            default: run_unit<128, false>(jd, local, ring, stage); break;
+            case 0: run_unit<16, true, SP>(jd, local, ring, stage); break;
+            case 1: run_unit<32, true, SP>(jd, local, ring, stage); break;
+            case 2: run_unit<64, true, SP>(jd, local, ring, stage); break;
+            case 3: run_unit<128, true, SP>(jd, local, ring, stage); break;
+            default: run_unit<128, false, SP>(jd, local, ring, stage); break;
         }
     }
 }
 
 __global__ void zero_counter(unsigned long long* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
+}
+
+__global__ void zero_each(unsigned long long* const* __restrict__ ptrs, int32_t n) {
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) *ptrs[k] = 0ull;
 }
 
 }  // namespace
@@ -77,13 +85,24 @@ int batch_variant(int w) {
 }
 
 hipError_t launch_batch(const JobDesc* jobs_dev, int32_t njobs, int64_t total_units, unsigned long long* counter,
-                        int32_t grid, hipStream_t stream) {
+                        int32_t grid, bool sparse, hipStream_t stream) {
     if (total_units <= 0 || njobs <= 0) return hipSuccess;
     hipLaunchKernelGGL(zero_counter, dim3(1), dim3(64), 0, stream, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_kernel, dim3((uint32_t)grid), dim3(64), 0, stream, jobs_dev, njobs, total_units,
-                       counter);
+    if (sparse)
+        hipLaunchKernelGGL(batch_kernel<true>, dim3((uint32_t)grid), dim3(64), 0, stream, jobs_dev, njobs,
+                           total_units, counter);
+    else
+        hipLaunchKernelGGL(batch_kernel<false>, dim3((uint32_t)grid), dim3(64), 0, stream, jobs_dev, njobs,
+                           total_units, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_each(unsigned long long* const* ptrs, int32_t n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int32_t blocks = std::min<int32_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(zero_each, dim3((uint32_t)blocks), dim3(256), 0, stream, ptrs, n);
     return hipGetLastError();
 }
 

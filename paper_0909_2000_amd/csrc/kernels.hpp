@@ -106,6 +106,8 @@ struct JobDesc {
     uint8_t* out;
     uint32_t* bm32;
     uint16_t* indel;
+    DotRec* dots;
+    unsigned long long* dot_count;
     Geom g;
     int64_t unit0;    // index of the job's first unit in the global unit list
     int32_t variant;  // per-unit code path (batch_variant)
@@ -123,7 +125,11 @@ hipError_t launch_dp(const PlotArgs& a, hipStream_t stream);
 int batch_variant(int w);
 constexpr int kBatchMaxW = 128;            // longer windows leave the batched kernel
 constexpr int kBatchWavesPerCu = 8;        // resident waves per CU of batch_kernel
+// sparse: some job stores strided windows or lists dots (the kernel variant
+// with those flushes)
 hipError_t launch_batch(const JobDesc* jobs_dev, int32_t njobs, int64_t total_units,
-                        unsigned long long* counter, int32_t grid, hipStream_t stream);
+                        unsigned long long* counter, int32_t grid, bool sparse, hipStream_t stream);
+// *ptrs[k] = 0 for k < n
+hipError_t launch_zero_each(unsigned long long* const* ptrs, int32_t n, hipStream_t stream);
 
 }  // namespace wlcs

@@ -2,7 +2,9 @@
 continuous batching.
 
 A job is one plot request (strings x and y, window w, alphabet, bitmap
-threshold, optional indel output).  The server keeps a FIFO of waiting jobs
+threshold, optional indel output; optionally step sizes and, instead of the
+dense bitmap, the list of dots at or above the threshold, which holds far
+fewer bytes than the dense outputs of a large plot).  The server keeps a FIFO of waiting jobs
 and admits the head while its device footprint (resident letter codes plus
 its outputs) fits the memory budget and a job slot is free.  Admitted jobs
 are launched together as one batch (one persistent work-stealing launch,
@@ -39,6 +41,9 @@ class Request:
     indel: bool = True
     want_plot: bool = False
     arrival: float = 0.0       # seconds on the server's clock
+    hx: int = 1                # step sizes (Section 3): x-windows r*hx, y-windows c*hy
+    hy: int = 1
+    dot_cap: int | None = None  # list the dots (up to dot_cap records) instead of a bitmap
 
 
 @dataclass
@@ -56,14 +61,20 @@ def windows(length: int, w: int) -> int:
     return max(length - w, 0)
 
 
+DOT_BYTES = 12  # one wlcs_dot record
+
+
 def footprint_bytes(req: Request) -> int:
     """HBM a job holds while admitted: its resident codes and its outputs."""
-    rows, cols = windows(req.x.size, req.w), windows(req.y.size, req.w)
+    rows = -(-windows(req.x.size, req.w) // req.hx)
+    cols = -(-windows(req.y.size, req.w) // req.hy)
     b = 2 * (req.x.size + req.y.size) + PAIR_PAD_BYTES
     if req.want_plot:
         b += rows * cols
-    if req.threshold is not None:
+    if req.threshold is not None and req.dot_cap is None and req.hy == 1:
         b += rows * ((cols + 63) // 64) * 8
+    if req.dot_cap is not None:
+        b += DOT_BYTES * req.dot_cap + 8
     if req.indel:
         b += rows * cols * 2
     return b
@@ -99,8 +110,11 @@ class GpuExecutor:
         for js in jobs:
             r = js.req
             pair = self.ctx.pair(r.x, r.y, alphabet=r.alphabet, stream=s)
-            specs.append({"pair": pair, "w": r.w, "threshold": r.threshold, "indel": r.indel,
-                          "want_plot": r.want_plot})
+            sp = {"pair": pair, "w": r.w, "threshold": r.threshold, "indel": r.indel,
+                  "want_plot": r.want_plot, "hx": r.hx, "hy": r.hy}
+            if r.dot_cap is not None:
+                sp["dot_cap"] = r.dot_cap
+            specs.append(sp)
         with self.torch.cuda.stream(s):
             results = self.ctx.batch(specs, stream=s)
             ev = self.torch.cuda.Event()
@@ -245,12 +259,24 @@ class Server:
         }
 
 
-def requests_from_workload(jobs, rate_scale: float = 1.0, want_plot: bool = False) -> list:
+def default_dot_cap(rows: int, cols: int) -> int:
+    """List capacity of a sparse job: one record per 1024 window pairs, at
+    least 4096 (the device count tells when a list was too short)."""
+    return max(4096, rows * cols // 1024)
+
+
+def requests_from_workload(jobs, rate_scale: float = 1.0, want_plot: bool = False, dots: bool = False,
+                           hx: int = 1, hy: int = 1) -> list:
     """Turn workloads.serving_jobs() into Requests; arrival times are divided
-    by rate_scale (so rate_scale > 1 compresses the stream)."""
+    by rate_scale (so rate_scale > 1 compresses the stream).  dots: ask for
+    the dot list (with its indel distances) instead of the dense bitmap and
+    indel matrices."""
     out = []
     for j in jobs:
         p = j.pair
-        out.append(Request(j.jid, p.x, p.y, p.w, p.alphabet, threshold=j.threshold, indel=True,
-                           want_plot=want_plot, arrival=j.arrival / rate_scale))
+        cap = None
+        if dots:
+            cap = default_dot_cap(-(-windows(p.x.size, p.w) // hx), -(-windows(p.y.size, p.w) // hy))
+        out.append(Request(j.jid, p.x, p.y, p.w, p.alphabet, threshold=j.threshold, indel=not dots,
+                           want_plot=want_plot, arrival=j.arrival / rate_scale, hx=hx, hy=hy, dot_cap=cap))
     return out

@@ -98,3 +98,28 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(wl, "_lib", None)
     with pytest.raises(wl.WlcsUnavailable):
         wl._load()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes records (wlcs_job, wlcs_dot) have the sizes and
+    field offsets a C compiler gives the header's structs."""
+    import subprocess
+    import paper_0909_2000_amd as wl
+    job_fields = [f for f, _ in wl.Job._fields_]
+    prog = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {',
+            'printf("%zu %zu\\n", sizeof(wlcs_job), sizeof(wlcs_dot));']
+    prog += [f'printf("%zu\\n", offsetof(wlcs_job, {f}));' for f in job_fields]
+    prog += [f'printf("%zu\\n", offsetof(wlcs_dot, {f}));' for f in ("i", "j", "wlcs", "indel")]
+    prog += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(prog) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(wl.Job) and vals[1] == wl.DOT.itemsize
+    assert vals[2:2 + len(job_fields)] == [getattr(wl.Job, f).offset for f in job_fields]
+    assert vals[2 + len(job_fields):] == [wl.DOT.fields[f][1] for f in ("i", "j", "wlcs", "indel")]
+
+
+def test_status_string_for_file_errors(lib):
+    assert lib.wlcs_status_str(-6) == b"file could not be written"

@@ -169,3 +169,70 @@ def test_batch_configuration_full_size(ctx, oracle_mod):
         np.testing.assert_array_equal(got, oracle_mod.wlcs_at(p.x, p.y, p.w, ii, jj))
     for k in (0, 17, 101, 255):
         assert torch.equal(res[k]["wlcs"], specs[k]["pair"].plot(specs[k]["w"])["wlcs"])
+
+
+def _sorted_dots(res):
+    import paper_0909_2000_amd as wl
+    return wl.dot_records(res)
+
+
+def test_strided_and_sparse_jobs_equal_alone(oracle_mod):
+    """Batched jobs with step sizes and dot lists (windows up to 128 in the
+    persistent launch, 200 as a separate launch) give exactly what each job
+    gives alone through wlcs_pair_plot_strided; a graph replay zeroes the dot
+    counters again each time."""
+    import torch
+    import paper_0909_2000_amd as wl
+    g = workloads.rng(44)
+    ctx = wl.Context(0)
+    specs, alone_args = [], []
+    for k, (w, hx, hy, sparse) in enumerate([(16, 1, 1, True), (32, 2, 3, True), (64, 5, 1, False),
+                                              (64, 3, 2, True), (100, 1, 4, True), (128, 4, 1, True),
+                                              (200, 5, 2, True), (48, 1, 1, False)]):
+        m, n = int(g.integers(400, 2500)) + w, int(g.integers(400, 2500)) + w
+        x = workloads.iid(g, m, workloads.DNA)
+        y = workloads.iid(g, n, workloads.DNA)
+        y[100:100 + 2 * w] = x[50:50 + 2 * w]  # a homology, so the lists are not empty
+        pair = ctx.pair(x, y)
+        thr = (3 * w + 3) // 4
+        sp = {"pair": pair, "w": w, "hx": hx, "hy": hy, "threshold": thr, "indel": k % 2 == 0,
+              "x": x, "y": y}
+        if sparse:
+            sp["dot_cap"] = 100000
+        specs.append(sp)
+    print("jobs:", [(s["pair"].m, s["pair"].n, s["w"], s["hx"], s["hy"], "dot_cap" in s) for s in specs], flush=True)
+    batch_specs = [{k: v for k, v in s.items() if k not in ("x", "y")} for s in specs]
+    res = ctx.batch(batch_specs)
+    torch.cuda.synchronize()
+    for s, r in zip(specs, res):
+        alone = s["pair"].plot_strided(s["w"], s["hx"], s["hy"], threshold=s["threshold"], indel=s["indel"],
+                                       dot_cap=s.get("dot_cap"))
+        torch.cuda.synchronize()
+        assert torch.equal(r["wlcs"], alone["wlcs"])
+        for key in ("bitmap", "indel"):
+            assert (key in r) == (key in alone)
+            if key in r:
+                assert torch.equal(r[key], alone[key])
+        if "dot_cap" in s:
+            got, n_got = _sorted_dots(r)
+            want, n_want = _sorted_dots(alone)
+            assert n_got == n_want > 0
+            np.testing.assert_array_equal(got.view(np.uint8), want.view(np.uint8))
+    # the oracle on two of them
+    for s, r in list(zip(specs, res))[1:3]:
+        want = oracle_mod.wlcs_strided(s["x"], s["y"], s["w"], s["hx"], s["hy"])
+        np.testing.assert_array_equal(r["wlcs"].cpu().numpy(), want)
+    # a captured graph: every replay zeroes and refills the counters
+    graph = ctx.batch_graph(batch_specs)
+    counts = [r["dot_count"] for r in graph.results if "dot_count" in r]
+    first = None
+    for rep in range(3):
+        graph.launch()
+        torch.cuda.synchronize()
+        now = [int(c.item()) for c in counts]
+        first = first or now
+        assert now == first, rep
+        for c in counts:  # eager work between replays
+            c.fill_(999)
+        torch.cuda.synchronize()
+    graph.close()

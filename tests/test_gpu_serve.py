@@ -52,3 +52,45 @@ def test_serving_results_equal_alone(oracle_mod):
         want = oracle_mod.wlcs(r.x, r.y, r.w)
         np.testing.assert_array_equal(srv.result(r.jid)["indel"].cpu().numpy().view(np.uint16),
                                       oracle_mod.indel(want, r.w))
+
+
+def test_sparse_serving_results_equal_alone(oracle_mod):
+    """Serving with step sizes and dot lists instead of dense outputs: every
+    job's dot list equals the job's own wlcs_pair_plot_strided list (sorted;
+    the set is unique), and the oracle on a sample."""
+    import torch
+    import paper_0909_2000_amd as wl
+    from paper_0909_2000_amd import serve
+
+    g = workloads.rng(32)
+    reqs = []
+    t = 0.0
+    for k in range(36):
+        t += float(g.exponential(1.0 / 4000.0))
+        alpha = workloads.PROTEIN if k % 2 else workloads.DNA
+        w = int((16, 32, 64, 128)[k % 4])
+        m, n = int(g.integers(200, 2500)) + w, int(g.integers(200, 2500)) + w
+        x, y = workloads.iid(g, m, alpha), workloads.iid(g, n, alpha)
+        y[10:10 + w] = x[5:5 + w]
+        reqs.append(serve.Request(k, x, y, w, alpha, threshold=(3 * w + 3) // 4, indel=False,
+                                  arrival=t, hx=1 + k % 5, hy=1 + k % 2, dot_cap=200000))
+    budget = 10 * max(serve.footprint_bytes(r) for r in reqs)
+    ctx = wl.Context(0)
+    ex = serve.GpuExecutor(0, streams=3, ctx=ctx)
+    srv = serve.Server(ex, budget_bytes=budget, max_jobs=24, max_batch=6, keep_results=True)
+    rep = srv.run(reqs)
+    torch.cuda.synchronize()
+    print("sparse serving report", rep, flush=True)
+    assert rep["rejected"] == 0 and rep["batches"] > 1
+    for r in reqs:
+        got, n_got = wl.dot_records(srv.result(r.jid))
+        alone = ctx.pair(r.x, r.y, alphabet=r.alphabet).plot_strided(r.w, r.hx, r.hy, threshold=r.threshold,
+                                                                       want_plot=False, dot_cap=200000)
+        want, n_want = wl.dot_records(alone)
+        assert n_got == n_want and n_got <= 200000, r.jid
+        np.testing.assert_array_equal(got.view(np.uint8), want.view(np.uint8))
+    for r in reqs[:4]:
+        plot = oracle_mod.wlcs_strided(r.x, r.y, r.w, r.hx, r.hy)
+        want = oracle_mod.dot_list(plot, r.w, r.threshold, r.hx, r.hy)
+        got, _ = wl.dot_records(srv.result(r.jid))
+        np.testing.assert_array_equal(got.view(np.uint8), want.view(np.uint8))

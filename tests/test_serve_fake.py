@@ -40,12 +40,14 @@ class FakeExecutor:
         self.launch_log.append((self.t, batch_id, running))
         for j in jobs:
             r = j.req
-            plot = self.oracle.wlcs(r.x, r.y, r.w)
+            plot = self.oracle.wlcs_strided(r.x, r.y, r.w, r.hx, r.hy)
             res = {}
             if r.want_plot:
                 res["wlcs"] = plot
-            if r.threshold is not None:
+            if r.threshold is not None and r.dot_cap is None and r.hy == 1:
                 res["bitmap"] = self.oracle.dot_bitmap(plot, r.threshold)
+            if r.dot_cap is not None:
+                res["dots"] = self.oracle.dot_list(plot, r.w, r.threshold, r.hx, r.hy)[:r.dot_cap]
             if r.indel:
                 res["indel"] = self.oracle.indel(plot, r.w)
             j.results = res
@@ -147,3 +149,29 @@ def test_footprint_formula():
     rows, cols = 936, 1936
     want = 2 * 3000 + serve.PAIR_PAD_BYTES + rows * cols + rows * ((cols + 63) // 64) * 8 + rows * cols * 2
     assert serve.footprint_bytes(r) == want
+
+
+def test_footprint_of_sparse_and_strided_jobs():
+    x, y = np.zeros(1000, np.uint8), np.zeros(2000, np.uint8)
+    r = serve.Request(0, x, y, 64, b"A", threshold=48, indel=False, hx=5, hy=2, dot_cap=5000)
+    rows, cols = -(-936 // 5), -(-1936 // 2)
+    assert serve.footprint_bytes(r) == 2 * 3000 + serve.PAIR_PAD_BYTES + 12 * 5000 + 8
+    r = serve.Request(0, x, y, 64, b"A", threshold=48, indel=True, hx=5, hy=1)
+    assert serve.footprint_bytes(r) == (2 * 3000 + serve.PAIR_PAD_BYTES + rows * ((1936 + 63) // 64) * 8
+                                        + rows * 1936 * 2)
+    assert serve.default_dot_cap(10, 10) == 4096 and serve.default_dot_cap(4096, 4096) == 16384
+
+
+def test_sparse_jobs_results_equal_alone(oracle_mod):
+    reqs = _requests(20, 6, rate=800.0)
+    for k, r in enumerate(reqs):
+        r.hx, r.hy = 1 + k % 3, 1 + (k // 3) % 2
+        r.indel = False
+        r.dot_cap = 10**6
+    srv = serve.Server(FakeExecutor(oracle_mod, streams=2), budget_bytes=1 << 40, max_batch=4)
+    rep = srv.run(reqs)
+    assert rep["jobs"] == 20 and rep["rejected"] == 0
+    for r in reqs:
+        alone = oracle_mod.wlcs_strided(r.x, r.y, r.w, r.hx, r.hy)
+        np.testing.assert_array_equal(srv.result(r.jid)["dots"],
+                                      oracle_mod.dot_list(alone, r.w, r.threshold, r.hx, r.hy))
