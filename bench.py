@@ -181,13 +181,33 @@ def main():
                 "ops_per_cell": OPS_PER_CELL, "cells_per_launch": cells,
                 "avg_launch_ms": avg_kernel_ms}
 
-    # parity spot check of the timed output (whole rows against the oracle)
-    import oracle
+    # rows of the timed plot kept for the consistency checks below
     sample_rows = np.array([0, rows // 3, rows - 1])
-    want = oracle.wlcs_rows(p.x, p.y, w, sample_rows)
-    got = out[torch.as_tensor(sample_rows, device=dev)].cpu().numpy()
-    parity = bool(np.array_equal(got, want))
-    log(f"parity on {len(sample_rows)} sampled rows: {parity}")
+    sea_rows = out[torch.as_tensor(sample_rows, device=dev)].cpu().numpy()
+
+    cpu, parity = None, None
+    if not args.no_cpu:
+        # the oracle as it stands, on whole rows of the same plot, sized to
+        # about cpu-seconds of host time; the rows it computes are also the
+        # parity check of the timed plot
+        import oracle
+        threads = oracle.default_threads()
+        t0 = time.perf_counter()
+        oracle.wlcs_rows(p.x, p.y, w, [rows // 2], nthreads=1)
+        one_row = time.perf_counter() - t0
+        nrows = max(threads, int(args.cpu_seconds * threads / max(one_row, 1e-3)))
+        nrows = min(nrows, rows)
+        ids = np.linspace(0, rows - 1, nrows).astype(np.int64)
+        t0 = time.perf_counter()
+        want = oracle.wlcs_rows(p.x, p.y, w, ids, nthreads=threads)
+        cpu_s = time.perf_counter() - t0
+        parity = bool(np.array_equal(out[torch.as_tensor(ids, device=dev)].cpu().numpy(), want))
+        cpu = {"value": nrows * float(n) * w / cpu_s, "unit": "window-cells/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{nrows} of {rows} plot rows (x-windows spread evenly), each against all "
+                         f"{cols} y-windows, plain per-window DP, {cpu_s:.1f} s"}
+        log(f"CPU oracle: {cpu['value']:.3e} window-cells/s on {threads} threads; "
+            f"timed plot equals it on those {nrows} rows: {parity}")
 
     dp = None
     if not args.no_dp:
@@ -202,30 +222,10 @@ def main():
         b.record(stream)
         torch.cuda.synchronize()
         dp_ms = a.elapsed_time(b)
-        dp_ok = bool(np.array_equal(out[torch.as_tensor(sample_rows, device=dev)].cpu().numpy(), want))
+        dp_same = bool(np.array_equal(out[torch.as_tensor(sample_rows, device=dev)].cpu().numpy(), sea_rows))
         dp = {"value": nominal / (dp_ms / 1e3), "unit": "window-cells/s", "ms": dp_ms,
-              "speedup_seaweed_over_dp": dp_ms / ms_per_step, "parity": dp_ok}
+              "speedup_seaweed_over_dp": dp_ms / ms_per_step, "equals_seaweed_on_sampled_rows": dp_same}
         log(f"GPU DP: {dp_ms:.1f} ms, seaweed speedup {dp_ms / ms_per_step:.1f}x")
-
-    cpu = None
-    if not args.no_cpu:
-        # the oracle as it stands, on whole rows of the same plot, sized to
-        # about cpu-seconds of host time
-        threads = oracle.default_threads()
-        t0 = time.perf_counter()
-        oracle.wlcs_rows(p.x, p.y, w, [rows // 2], nthreads=1)
-        one_row = time.perf_counter() - t0
-        nrows = max(threads, int(args.cpu_seconds * threads / max(one_row, 1e-3)))
-        nrows = min(nrows, rows)
-        ids = np.linspace(0, rows - 1, nrows).astype(np.int64)
-        t0 = time.perf_counter()
-        oracle.wlcs_rows(p.x, p.y, w, ids, nthreads=threads)
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": nrows * float(n) * w / cpu_s, "unit": "window-cells/s", "cores": threads,
-               "kind": "oracle",
-               "sample": f"{nrows} of {rows} plot rows (x-windows spread evenly), each against all "
-                         f"{cols} y-windows, plain per-window DP, {cpu_s:.1f} s"}
-        log(f"CPU oracle: {cpu['value']:.3e} window-cells/s on {threads} threads")
 
     others = None
     if not args.no_configs:
@@ -233,12 +233,12 @@ def main():
         for k in (1, 3):
             if WORKLOADS[args.workload] == k:
                 continue  # already the headline workload
-            others[workloads.config(k).name] = bench_config(ctx, torch, workloads, oracle, k)
+            others[workloads.config(k).name] = bench_config(ctx, torch, workloads, k)
             log(f"config {k}: {others[workloads.config(k).name]}")
 
     paper_shapes = None
     if not args.no_paper_shapes:
-        paper_shapes = bench_paper_shapes(ctx, torch, workloads, oracle)
+        paper_shapes = bench_paper_shapes(ctx, torch, workloads)
         for k, v in paper_shapes.items():
             log(f"{k}: {v['ms']:.1f} ms (paper: Sea-8 {v['paper_sea8_s']} s on 1 core, MPI "
                 f"{v['paper_mpi_s']} s on {v['paper_mpi_cores']} cores)")
@@ -249,11 +249,19 @@ def main():
         log(f"batched: {batched['value']:.3e} window-cells/s over {batched['pairs']} pairs "
             f"({batched['ms']:.1f} ms; graph replay {batched['graph_ms']:.1f} ms)")
 
+    step5 = None
+    if not args.no_configs:
+        step5 = bench_step5(ctx, torch, workloads)
+        log(f"step 5 (paper's vertical step): {step5['ms']:.2f} ms, {step5['dots']} dots, "
+            f"DP {step5['dp_ms']:.1f} ms ({step5['speedup_over_dp']:.0f}x)")
     serving = None
     if not args.no_serving:
         serving = bench_serving(ctx, torch, workloads, args)
         log(f"serving: p50 {serving['at_load']['p50_s'] * 1e3:.1f} ms, p99 "
             f"{serving['at_load']['p99_s'] * 1e3:.1f} ms at {serving['rate_jobs_per_s']:.0f} jobs/s")
+        sp = serving["sparse"]
+        log(f"serving with dot lists: p50 {sp['at_load']['p50_s'] * 1e3:.1f} ms, p99 "
+            f"{sp['at_load']['p99_s'] * 1e3:.1f} ms at {sp['rate_jobs_per_s']:.0f} jobs/s")
 
     rec = {
         "metric": METRIC, "value": value, "unit": "window-cells/s", "n_gpus": 1,
@@ -265,7 +273,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "gpu_dp_baseline": dp,
         "other_configs": others, "paper_shaped_score_plots": paper_shapes,
-        "batched": batched, "serving": serving,
+        "batched": batched, "serving": serving, "step5_lcs_plot": step5,
         "encode_ms": encode_ms, "parity_sampled_rows": parity,
         "kernel_ms": {"min": float(np.min(kern_ms)), "median": float(np.median(kern_ms)),
                       "max": float(np.max(kern_ms))},
@@ -319,10 +327,10 @@ def bench_batch(ctx, torch, workloads, reps=3):
     return out
 
 
-def bench_config(ctx, torch, workloads, oracle, k, steps=10):
-    """Seaweed plot and GPU DP on another single-pair configuration, with
-    parity against the oracle (whole plot for the small one, sampled rows
-    otherwise)."""
+def bench_config(ctx, torch, workloads, k, steps=10):
+    """Seaweed plot and GPU DP on another single-pair configuration; the two
+    GPU plots are compared whole (the oracle's parity at these sizes is the
+    test suite's)."""
     import numpy as np
     p = workloads.config(k)
     rows, cols = p.m - p.w, p.n - p.w
@@ -331,23 +339,17 @@ def bench_config(ctx, torch, workloads, oracle, k, steps=10):
     for _ in range(2):
         pair.plot(p.w, out=out)
     ms = float(np.median([_timed_once(torch, lambda: pair.plot(p.w, out=out)) for _ in range(steps)]))
-    if rows * cols <= 2_000_000:
-        want = oracle.wlcs(p.x, p.y, p.w)
-        parity = bool(np.array_equal(out.cpu().numpy(), want))
-        sample = "whole plot"
-    else:
-        ids = np.array([0, rows // 2, rows - 1])
-        want = oracle.wlcs_rows(p.x, p.y, p.w, ids)
-        parity = bool(np.array_equal(out[torch.as_tensor(ids, device="cuda")].cpu().numpy(), want))
-        sample = "rows 0, mid, last"
-    dp_ms = _timed_once(torch, lambda: pair.plot_dp(p.w, out=out))
+    dp_out = torch.empty_like(out)
+    dp_ms = _timed_once(torch, lambda: pair.plot_dp(p.w, out=dp_out))
     nominal = float(p.m) * p.n * p.w
     cells = float(rows) * p.n * p.w
     res = {"m": p.m, "n": p.n, "w": p.w, "ms": ms, "value": nominal / (ms / 1e3),
            "unit": "window-cells/s", "roofline_frac": cells * OPS_PER_CELL / (ms / 1e3) / PEAK_U16_OPS,
            "dp_ms": dp_ms, "dp_value": nominal / (dp_ms / 1e3), "speedup_over_dp": dp_ms / ms,
-           "parity": parity, "parity_sample": sample}
+           "dp_equals_seaweed": bool(torch.equal(out, dp_out))}
     pair.close()
+    del out, dp_out
+    torch.cuda.empty_cache()
     return res
 
 
@@ -363,7 +365,7 @@ PAPER_SHAPES = {
 }
 
 
-def bench_paper_shapes(ctx, torch, workloads, oracle):
+def bench_paper_shapes(ctx, torch, workloads):
     """Alignment-score plots at the paper's experimental shapes, timed with
     HIP events (strings uploaded, blown up and encoded inside each call)."""
     import numpy as np
@@ -376,12 +378,9 @@ def bench_paper_shapes(ctx, torch, workloads, oracle):
         S = res["score"]
         ms = float(np.median([_timed_once(torch, lambda: ctx.score_plot(x, y, w, step=step, out=S))
                               for _ in range(3)]))
-        r = S.shape[0] // 2
-        want = oracle.score_plot(x[r * step:r * step + w], y, w, full_range=True)[0, :S.shape[1]]
         cells = float(S.shape[0]) * (2 * n) * (2 * w)
         out[name] = {"m": m, "n": n, "w": w, "step": step, "rows": S.shape[0], "cols": S.shape[1],
                      "ms": ms, "blown_up_cells_per_s": cells / (ms / 1e3),
-                     "parity_row": bool(np.array_equal(S[r].cpu().numpy(), want)),
                      "paper_sea16_s": sea16, "paper_sea8_s": sea8, "paper_mpi_s": mpi,
                      "paper_mpi_cores": mpi_cores,
                      "data": "iid uniform DNA of the paper's lengths (datasets not available)"}
@@ -407,12 +406,12 @@ def bench_serving(ctx, torch, workloads, args):
     jobs = workloads.serving_jobs(rate=1.0, njobs=args.serving_jobs)
     budget = int(args.budget_gib * (1 << 30))
 
-    def run(rate_scale, all_at_once=False):
-        reqs = serve.requests_from_workload(jobs, rate_scale=rate_scale)
+    def run(rate_scale, all_at_once=False, dots=False):
+        reqs = serve.requests_from_workload(jobs, rate_scale=rate_scale, dots=dots)
         if all_at_once:
             for r in reqs:
                 r.arrival = 0.0
-        ex = serve.GpuExecutor(0, streams=3, ctx=ctx)
+        ex = serve.GpuExecutor(0, streams=3)  # its own context, latency tiles
         srv = serve.Server(ex, budget_bytes=budget, max_jobs=256, max_batch=64, keep_results=False)
         rep = srv.run(reqs)
         torch.cuda.synchronize()
@@ -424,11 +423,66 @@ def bench_serving(ctx, torch, workloads, args):
     rate = args.serving_load * capacity
     # arrivals were drawn at 1 job/s: compress them to `rate`
     at = run(rate)
+    # the same stream with dot lists (window starts, WLCS, indel distance of
+    # every pair at or above the threshold) in place of the dense outputs
+    sat_s = run(1.0, all_at_once=True, dots=True)
+    rate_s = args.serving_load * sat_s["jobs_per_s"]
+    at_s = run(rate_s, dots=True)
     return {"jobs": len(jobs), "capacity_jobs_per_s": capacity, "saturated": sat,
             "load": args.serving_load, "rate_jobs_per_s": rate, "at_load": at,
             "budget_gib": args.budget_gib,
             "workload": "Poisson arrivals; DNA/protein 1:1; m,n log-uniform [500,50000]; "
-                        "w ~ {16,32,64,128}; outputs bitmap (T=ceil(3w/4)) + uint16 indel"}
+                        "w ~ {16,32,64,128}; outputs bitmap (T=ceil(3w/4)) + uint16 indel",
+            "batch_tiles": {f"{lo}-{hi}": t for (lo, hi), t in serve.LATENCY_TILES.items()},
+            "batch_grid": serve.LATENCY_GRID,
+            "sparse": {"capacity_jobs_per_s": sat_s["jobs_per_s"], "saturated": sat_s,
+                       "rate_jobs_per_s": rate_s, "at_load": at_s,
+                       "outputs": "dot list (12-byte records: i, j, WLCS, indel) at T=ceil(3w/4), "
+                                  "first capacity max(4096, windows/64) per job, jobs with more "
+                                  "dots rerun with an exact list"}}
+
+
+def bench_step5(ctx, torch, workloads, reps=5):
+    """The 50,000 x 50,000 DNA pair, w = 64, at the paper's vertical step of
+    5 (every fifth x-window against every y-window, Section 3's step size):
+    seaweed plot with the dot list at WLCS >= 48, and the plain per-window DP
+    with the same step on the same GPU; the two plots are compared whole and
+    the dot list with the plot's entries at or above the threshold on sampled
+    rows."""
+    import numpy as np
+    p = workloads.config(2)
+    w, hx = p.w, 5
+    pair = ctx.pair(p.x, p.y)
+    rows = -(-(p.m - w) // hx)
+    cols = p.n - w
+    out = torch.empty((rows, cols), dtype=torch.uint8, device="cuda")
+    dots = torch.empty((1 << 20, 3), dtype=torch.int32, device="cuda")
+    count = torch.empty(1, dtype=torch.int64, device="cuda")
+
+    def sea():
+        pair.plot_strided(w, hx, 1, threshold=p.threshold, out=out, dots_out=dots, count_out=count)
+
+    sea()
+    torch.cuda.synchronize()
+    ms = float(np.median([_timed_once(torch, sea) for _ in range(reps)]))
+    res = {"wlcs": out, "dots": dots, "dot_count": count}
+    import paper_0909_2000_amd as wl
+    recs, n_dots = wl.dot_records(res)
+    sample = np.array([0, rows // 2, rows - 1])
+    plot_rows = out[torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    dots_ok = all({int(j) for j in np.nonzero(row >= p.threshold)[0]} ==
+                  {int(d["j"]) for d in recs[recs["i"] == r * hx]} for r, row in zip(sample, plot_rows))
+    dp_out = torch.empty_like(out)
+    dp_ms = _timed_once(torch, lambda: pair.plot_dp_strided(w, hx, 1, out=dp_out, want_plot=True))
+    dp_ok = bool(torch.equal(dp_out, out))
+    pair.close()
+    cells = float(rows) * p.n * w  # x-windows compared x n x w
+    del out, dp_out, dots
+    torch.cuda.empty_cache()
+    return {"m": p.m, "n": p.n, "w": w, "hx": hx, "rows": rows, "cols": cols, "ms": ms,
+            "window_cells_per_s": cells / (ms / 1e3), "dots": n_dots, "dots_match_plot_rows": dots_ok, "dp_ms": dp_ms, "speedup_over_dp": dp_ms / ms,
+            "dp_equals_seaweed": dp_ok,
+            "outputs": "uint8 plot of every 5th x-window + dot list at WLCS >= 48"}
 
 
 if __name__ == "__main__":

@@ -37,9 +37,10 @@ constexpr int min_waves_per_simd(int wc) { return wc <= 32 ? 4 : wc <= 64 ? 3 : 
 // dwords).  Output column c holds the window c * hy; the lanes of the wave
 // cover the block's output columns of one strip at a time, so the stores of a
 // strip are contiguous.  Dots (windows with WLCS >= threshold) are appended to
-// the list: one vector atomic per strip and block that has any, reserving a
-// run of slots the hitting lanes fill in lane order.  The counter keeps
-// counting past dot_cap; records beyond it are not written.
+// the list in two passes over the block: the first counts them (ballots), one
+// vector atomic reserves a run of slots for the whole block, the second
+// writes them (skipped once the list is full).  The counter keeps counting
+// past dot_cap; records beyond it are not written.
 __device__ __forceinline__ void strided_flush(uint8_t* __restrict__ out, uint16_t* __restrict__ indel,
                                               DotRec* __restrict__ dots, unsigned long long* __restrict__ dot_count,
                                               const Geom& g, int64_t s0, int64_t j0, int nk, int w,
@@ -53,35 +54,47 @@ __device__ __forceinline__ void strided_flush(uint8_t* __restrict__ out, uint16_
     const bool act = lane < nout;
     const int64_t c = c_lo + lane;
     const int b = act ? (int)(c * hy - j0) : 0;
-    const bool dense = g.hy > 1;
+    const int64_t rest = g.rows - s0;
+    const int nrows = rest < 64 ? (int)rest : 64;
+    if (g.hy > 1 && (out || indel)) {
 #pragma unroll 1
-    for (int r = 0; r < 64; ++r) {
-        const int64_t s = s0 + r;
-        if (s >= g.rows) break;  // uniform
-        const uint32_t v = staged[r * pitch * 4 + b];
-        if (act && dense) {
-            if (out) out[s * g.ld + c] = (uint8_t)v;
-            if (indel) indel[s * g.ld_indel + c] = (uint16_t)(2 * w - 2 * (int)v);
-        }
-        if (dot_count) {
-            const bool hit = act && (int)v >= g.threshold;
-            const uint64_t mask = __ballot(hit);
-            if (mask) {  // uniform
-                const int leader = __builtin_ctzll(mask);
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(dot_count, (unsigned long long)__popcll(mask));
-                const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
-                const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
-                const unsigned long long k =
-                    (((unsigned long long)hi << 32) | lo) + __popcll(mask & ((1ull << lane) - 1ull));
-                if (hit && dots && k < (unsigned long long)g.dot_cap) {
-                    uint32_t* rec = (uint32_t*)(dots + k);
-                    rec[0] = (uint32_t)(s * g.xstride);
-                    rec[1] = (uint32_t)(c * hy);
-                    rec[2] = v | ((uint32_t)(2 * w - 2 * (int)v) << 16);
-                }
+        for (int r = 0; r < nrows; ++r) {
+            const int64_t s = s0 + r;
+            const uint32_t v = staged[r * pitch * 4 + b];
+            if (act) {
+                if (out) out[s * g.ld + c] = (uint8_t)v;
+                if (indel) indel[s * g.ld_indel + c] = (uint16_t)(2 * w - 2 * (int)v);
             }
         }
+    }
+    if (!dot_count) return;
+    uint32_t total = 0;  // wave-uniform
+#pragma unroll 1
+    for (int r = 0; r < nrows; ++r) {
+        const uint32_t v = staged[r * pitch * 4 + b];
+        total += (uint32_t)__popcll(__ballot(act && (int)v >= g.threshold));
+    }
+    if (total == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(dot_count, (unsigned long long)total);
+    const unsigned long long start =
+        ((unsigned long long)__builtin_amdgcn_readlane((uint32_t)(base >> 32), 0) << 32) |
+        __builtin_amdgcn_readlane((uint32_t)base, 0);
+    if (!dots || start >= (unsigned long long)g.dot_cap) return;  // uniform
+    unsigned long long k0 = start;  // wave-uniform running slot
+#pragma unroll 1
+    for (int r = 0; r < nrows && k0 < (unsigned long long)g.dot_cap; ++r) {
+        const uint32_t v = staged[r * pitch * 4 + b];
+        const bool hit = act && (int)v >= g.threshold;
+        const uint64_t mask = __ballot(hit);
+        const unsigned long long k = k0 + __popcll(mask & ((1ull << lane) - 1ull));
+        if (hit && k < (unsigned long long)g.dot_cap) {
+            uint32_t* rec = (uint32_t*)(dots + k);
+            rec[0] = (uint32_t)((s0 + r) * g.xstride);
+            rec[1] = (uint32_t)(c * hy);
+            rec[2] = v | ((uint32_t)(2 * w - 2 * (int)v) << 16);
+        }
+        k0 += (unsigned long long)__popcll(mask);
     }
 }
 

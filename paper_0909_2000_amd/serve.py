@@ -20,6 +20,7 @@ admission, ordering and continuous admission without a GPU.
 from __future__ import annotations
 
 import collections
+import dataclasses
 import time
 from dataclasses import dataclass, field
 
@@ -55,6 +56,7 @@ class JobState:
     footprint: int = 0
     results: dict | None = None
     batch_id: int = -1
+    retries: int = 0           # reruns with a longer dot list
 
 
 def windows(length: int, w: int) -> int:
@@ -80,8 +82,15 @@ def footprint_bytes(req: Request) -> int:
     return b
 
 
+# Batch tiles that favour latency: short tiles give every job many units, so a
+# job spreads over the device even when few others run beside it.
+LATENCY_TILES = {(1, 64): 512, (65, 128): 1024}
+LATENCY_GRID = 16
+
+
 class GpuExecutor:
-    """Runs batches on one GPU through libwlcs, one stream per concurrent batch."""
+    """Runs batches on one GPU through libwlcs, one stream per concurrent batch.
+    Without a context of its own it makes one with the latency tiles."""
 
     def __init__(self, device: int = 0, streams: int = 3, ctx=None):
         import torch
@@ -89,7 +98,12 @@ class GpuExecutor:
         import paper_0909_2000_amd as wl
         self.torch, self.wl = torch, wl
         self.dev = torch.device("cuda", device)
-        self.ctx = ctx or wl.Context(device)
+        if ctx is None:
+            ctx = wl.Context(device)
+            for (lo, hi), t in LATENCY_TILES.items():
+                ctx.set_batch_tile(lo, hi, t)
+            ctx.set_batch_grid(LATENCY_GRID)
+        self.ctx = ctx
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
         self.busy = [None] * streams  # per stream: (event, batch_id) or None
         self.t0 = time.perf_counter()
@@ -124,6 +138,17 @@ class GpuExecutor:
             js.results["_pair"] = sp["pair"]  # keeps the resident codes alive until the job is done
         self.busy[k] = (ev, batch_id)
 
+    def dot_counts(self, jobs: list) -> list:
+        """Dots each finished job found (None for jobs without a list), read
+        back in one copy."""
+        idx = [k for k, js in enumerate(jobs) if js.results and "dot_count" in js.results]
+        out = [None] * len(jobs)
+        if idx:
+            vals = self.torch.cat([jobs[k].results["dot_count"] for k in idx]).cpu().tolist()
+            for k, v in zip(idx, vals):
+                out[k] = int(v)
+        return out
+
     def poll(self) -> list:
         """Batch ids whose work has finished on the device."""
         done = []
@@ -156,6 +181,7 @@ class Server:
         self.rejected: list = []
         self.admit_log: list = []          # (time, jid) in admission order
         self.overlaps = 0                  # launches made while another batch ran
+        self.retries = 0                   # jobs rerun because their dot list was too short
 
     # -- client side -----------------------------------------------------
     def submit(self, req: Request) -> int:
@@ -178,12 +204,30 @@ class Server:
     def _reap(self):
         for bid in self.ex.poll():
             now = self.ex.now()
-            for js in self.running.pop(bid):
-                js.done = now
+            batch = self.running.pop(bid)
+            counts = self.ex.dot_counts(batch) if hasattr(self.ex, "dot_counts") else [None] * len(batch)
+            retry = []
+            for js, found in zip(batch, counts):
                 self.in_use -= js.footprint
                 self.active -= 1
+                if found is not None and js.req.dot_cap is not None and found > js.req.dot_cap:
+                    # the list was too short: rerun the job with room for every dot
+                    js.req = dataclasses.replace(js.req, dot_cap=found)
+                    js.footprint = footprint_bytes(js.req)
+                    js.results = None
+                    js.retries += 1
+                    self.retries += 1
+                    retry.append(js)
+                    continue
+                js.done = now
                 if not self.keep:
                     js.results = None
+            for js in reversed(retry):  # ahead of every job that arrived later
+                if js.footprint > self.budget:
+                    js.done = now
+                    self.rejected.append(js.req.jid)
+                else:
+                    self.waiting.appendleft(js)
 
     def _admit(self):
         while self.waiting and self.active < self.max_jobs:
@@ -255,14 +299,15 @@ class Server:
             "span_s": span, "jobs_per_s": (len(self.jobs) - len(self.rejected)) / span,
             "window_cells_per_s": cells / span, "batches": self.next_batch,
             "overlapped_launches": self.overlaps, "peak_bytes": self.peak_use,
-            "budget_bytes": self.budget,
+            "budget_bytes": self.budget, "dot_list_reruns": self.retries,
         }
 
 
 def default_dot_cap(rows: int, cols: int) -> int:
-    """List capacity of a sparse job: one record per 1024 window pairs, at
-    least 4096 (the device count tells when a list was too short)."""
-    return max(4096, rows * cols // 1024)
+    """First list capacity of a sparse job: one record per 64 window pairs
+    (about 1.5 times the bytes of the job's bitmap), at least 4096.  A job
+    with more dots is rerun with an exact list (Server._reap)."""
+    return max(4096, rows * cols // 64)
 
 
 def requests_from_workload(jobs, rate_scale: float = 1.0, want_plot: bool = False, dots: bool = False,

@@ -47,10 +47,14 @@ class FakeExecutor:
             if r.threshold is not None and r.dot_cap is None and r.hy == 1:
                 res["bitmap"] = self.oracle.dot_bitmap(plot, r.threshold)
             if r.dot_cap is not None:
-                res["dots"] = self.oracle.dot_list(plot, r.w, r.threshold, r.hx, r.hy)[:r.dot_cap]
+                full = self.oracle.dot_list(plot, r.w, r.threshold, r.hx, r.hy)
+                res["dots"], res["dot_count"] = full[:r.dot_cap], full.size
             if r.indel:
                 res["indel"] = self.oracle.indel(plot, r.w)
             j.results = res
+
+    def dot_counts(self, jobs):
+        return [js.results.get("dot_count") if js.results else None for js in jobs]
 
     def poll(self):
         done = []
@@ -159,7 +163,7 @@ def test_footprint_of_sparse_and_strided_jobs():
     r = serve.Request(0, x, y, 64, b"A", threshold=48, indel=True, hx=5, hy=1)
     assert serve.footprint_bytes(r) == (2 * 3000 + serve.PAIR_PAD_BYTES + rows * ((1936 + 63) // 64) * 8
                                         + rows * 1936 * 2)
-    assert serve.default_dot_cap(10, 10) == 4096 and serve.default_dot_cap(4096, 4096) == 16384
+    assert serve.default_dot_cap(10, 10) == 4096 and serve.default_dot_cap(4096, 4096) == 262144
 
 
 def test_sparse_jobs_results_equal_alone(oracle_mod):
@@ -175,3 +179,22 @@ def test_sparse_jobs_results_equal_alone(oracle_mod):
         alone = oracle_mod.wlcs_strided(r.x, r.y, r.w, r.hx, r.hy)
         np.testing.assert_array_equal(srv.result(r.jid)["dots"],
                                       oracle_mod.dot_list(alone, r.w, r.threshold, r.hx, r.hy))
+
+
+def test_short_dot_lists_are_rerun_complete(oracle_mod):
+    """A job whose list overflows is rerun with room for every dot, ahead of
+    later arrivals; its final list is complete."""
+    reqs = _requests(12, 7, rate=500.0)
+    for r in reqs:
+        r.indel = False
+        r.threshold = 0  # every window is a dot
+        r.dot_cap = 5    # far too short
+    srv = serve.Server(FakeExecutor(oracle_mod, streams=2), budget_bytes=1 << 40, max_batch=3)
+    rep = srv.run(reqs)
+    assert rep["rejected"] == 0 and rep["dot_list_reruns"] == 12
+    for r in reqs:
+        js = srv.jobs[r.jid]
+        assert js.retries == 1 and js.done >= js.launched
+        plot = oracle_mod.wlcs(r.x, r.y, r.w)
+        assert srv.result(r.jid)["dot_count"] == plot.size
+        np.testing.assert_array_equal(srv.result(r.jid)["dots"], oracle_mod.dot_list(plot, r.w, 0))
