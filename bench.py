@@ -46,7 +46,8 @@ def measured_traffic(workload: str, cells: float = 0.0):
     wave instructions x 64 lanes per cell (5 packed instructions per two cells
     is 2.5), and the share of SIMD cycles that issued a VALU instruction (a
     wave64 instruction holds a 16-lane SIMD for 4 cycles; GRBM_GUI_ACTIVE is
-    the busy cycles summed over the 8 XCDs, each with 32 CUs x 4 SIMDs)."""
+    the busy cycles summed over the 8 XCDs, each with 32 CUs x 4 SIMDs; the
+    4-cycle rule is approximate, so a saturated VALU can read slightly above 1)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"seaweed_counters_{workload.replace('-planted', '')}.json")
     if not os.path.exists(path):
