@@ -51,7 +51,7 @@ extern "C" {
 #define WLCS_EIO (-6)       /* a file could not be written (wlcs_tune's cache) */
 
 #define WLCS_MAX_W 255         /* WLCS values must fit the uint8 output */
-#define WLCS_MAX_SIGMA 64      /* letters per alphabet */
+#define WLCS_MAX_SIGMA 63      /* letters per alphabet (a 64th code is kept for padding rows) */
 #define WLCS_MAX_LEN 100000000 /* longest string accepted (bytes) */
 #define WLCS_MAX_SCORE_W 127   /* alignment-score plots: scores in [-w, w] fit int8 */
 

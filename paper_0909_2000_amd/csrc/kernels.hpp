@@ -1,6 +1,6 @@
 // Internal interface between the host runtime and the gfx950 kernels.
 //
-// Letter codes.  Every letter of the alphabet gets a code c in [0, 64).  The
+// Letter codes.  Every letter of the alphabet gets a code c in [0, 63).  The
 // kernels never compare letters directly: x letters are stored as
 // f(c) = c << 10 and y letters as g(c) = ((64 - c) mod 64) << 10, so that the
 // 16-bit sum f(a) + g(b) is 0 when a == b and at least 1024 otherwise.  With
@@ -17,6 +17,9 @@ namespace wlcs {
 constexpr int kCodeShift = 10;
 constexpr uint16_t f_code(uint32_t c) { return (uint16_t)(c << kCodeShift); }
 constexpr uint16_t g_code(uint32_t c) { return (uint16_t)(((64u - c) & 63u) << kCodeShift); }
+// A code no letter gets: an x row of it mismatches every y letter (padding
+// rows of the strip, seaweed_unit.hpp).
+constexpr uint32_t kPadCode = 63;
 
 // Windows between two relabellings of the seaweed labels (a multiple of 32).
 constexpr int kRebase = 512;

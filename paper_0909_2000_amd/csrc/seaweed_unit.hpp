@@ -118,14 +118,29 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     const int64_t tB = tA + tlen;
     const int w = EXACT ? WC : g.w;
 
+    // Rows.  A window shorter than its class runs in a strip padded at the
+    // top to wpad = w rounded up to 16 rows: the pad rows hold a code that no
+    // y letter has, so every cell there is a mismatch whose left-boundary
+    // label (0) stays put while each seaweed from the top (label >= 1) passes
+    // straight down -- the padded strip has the same exits as the strip of
+    // height w.  Rows from wpad on are skipped 16 at a time by one uniform
+    // branch, so no cell carries a test of its own.
+    const int pad = EXACT ? 0 : ((w + 15) & ~15) - w;
+    const int wpad = EXACT ? WC : w + pad;
     // x letters of this lane's strip, two rows per register (lanes past the
     // last strip comb a copy of the last one; their results are never stored)
     uint32_t xc[WC / 2];
     {
         const int64_t sx = s0 + lane < g.rows ? s0 + lane : g.rows - 1;
         const uint16_t* xp = xf + sx * g.xstride;
+        constexpr uint32_t PADF = f_code(kPadCode);
 #pragma unroll
-        for (int j = 0; j < WC / 2; ++j) xc[j] = (uint32_t)xp[2 * j] | ((uint32_t)xp[2 * j + 1] << 16);
+        for (int j = 0; j < WC / 2; ++j) {
+            const int i0 = 2 * j - pad, i1 = 2 * j + 1 - pad;
+            const uint32_t lo = (EXACT || i0 >= 0) ? (uint32_t)xp[EXACT ? 2 * j : i0] : PADF;
+            const uint32_t hi = (EXACT || i1 >= 0) ? (uint32_t)xp[EXACT ? 2 * j + 1 : i1] : PADF;
+            xc[j] = lo | (hi << 16);
+        }
     }
     uint32_t h[WC];
 #pragma unroll
@@ -166,9 +181,8 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         uint32_t t = seaweed_cell_top(h[0], pk_rep(l - org + 1), xc[0], Y);
 #pragma unroll
         for (int k = 1; k < WC; ++k) {
-            if (EXACT || k < w) {
-                t = (k & 1) ? seaweed_cell<1>(h[k], t, xc[k >> 1], Y) : seaweed_cell<0>(h[k], t, xc[k >> 1], Y);
-            }
+            if (!EXACT && (k & 15) == 0 && k >= wpad) break;  // uniform, once per 16 rows
+            t = (k & 1) ? seaweed_cell<1>(h[k], t, xc[k >> 1], Y) : seaweed_cell<0>(h[k], t, xc[k >> 1], Y);
         }
         // consume the mark of start column l - w (prefetched after the
         // previous column's marks were set)

@@ -64,7 +64,7 @@ def test_argument_checks_before_any_device_work(lib, fn):
     # alphabet problems
     assert _plot(lib, alpha=b"ACGA", fn=fn) == EALPHABET          # repeated letter
     assert _plot(lib, alpha=b"", sigma=0, fn=fn) == EALPHABET
-    assert _plot(lib, alpha=bytes(range(65)), fn=fn) == EALPHABET  # more than 64 letters
+    assert _plot(lib, alpha=bytes(range(64)), fn=fn) == EALPHABET  # more than 63 letters
     assert _plot(lib, x=b"ACGTNCGT", fn=fn) == EALPHABET           # letter outside
     assert _plot(lib, y=b"ACGTACGTAc", fn=fn) == EALPHABET         # case-sensitive
     # missing inputs / outputs and short strides

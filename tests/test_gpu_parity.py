@@ -166,11 +166,16 @@ def test_degenerate(lib, ctx, oracle_mod):
     x = workloads.iid(g, 300, workloads.PROTEIN)
     d = np.diag(_cpu(ctx.plot(x, x, 77, alphabet=workloads.PROTEIN)["wlcs"]))
     assert np.all(d == 77)
-    # the full 64-letter alphabet
-    alpha = bytes(range(40, 104))
+    # the largest alphabet (63 letters; the 64th code pads short windows), at
+    # a window length that is padded (20 -> 32 rows) and one that is not (32)
+    alpha = bytes(range(40, 103))
     x, y = workloads.iid(g, 200, alpha), workloads.iid(g, 300, alpha)
-    np.testing.assert_array_equal(_cpu(ctx.plot(x, y, 20, alphabet=alpha)["wlcs"]),
-                                  oracle_mod.wlcs(x, y, 20))
+    for w in (20, 32):
+        np.testing.assert_array_equal(_cpu(ctx.plot(x, y, w, alphabet=alpha)["wlcs"]),
+                                      oracle_mod.wlcs(x, y, w))
+    with pytest.raises(lib.WlcsError) as e:
+        ctx.plot(x, y, 20, alphabet=bytes(range(40, 104)))  # 64 letters
+    assert e.value.status == -3
 
 
 def test_errors(lib, ctx):
