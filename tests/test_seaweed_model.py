@@ -20,7 +20,10 @@ kernels:
   bound of Propositions 3.3 and 3.4), leave every count unchanged;
 * the branch-free cell form of the kernels: with Z = 0 on a match and Z at
   least every label on a mismatch, bottom = max(s, min(t, Z)) and
-  right = s xor t xor bottom.
+  right = s xor t xor bottom;
+* the padding rows of the kernels: rows of a letter that y never holds, put on
+  top of the strip, let every seaweed from the top pass straight down, so the
+  padded strip has exactly the exits of the strip itself.
 """
 import itertools
 
@@ -252,3 +255,24 @@ def test_branch_free_cell_form():
             assert (bottom, right) == (sv, tv)
         else:
             assert (bottom, right) == (max(sv, tv), min(sv, tv))
+
+
+@pytest.mark.parametrize("pad", [1, 7, 15])
+def test_padding_rows_are_transparent(oracle_mod, pad):
+    """Strips padded on top with rows of a letter absent from y give the same
+    exits in every column as the unpadded strip, hence the same plot; a pad
+    letter that does occur in y changes them (the check is not vacuous)."""
+    g = workloads.rng(600 + pad)
+    for w in (5, 9, 16):
+        x = workloads.iid(g, w + 20, workloads.DNA).tobytes()
+        y = workloads.iid(g, 120, workloads.DNA).tobytes()
+        want = oracle_mod.wlcs(x, y, w)
+        changed = False
+        for i in range(want.shape[0]):
+            plain, _ = comb(x[i:i + w], y)
+            padded, _ = comb(b"#" * pad + x[i:i + w], y)
+            assert padded == plain
+            assert ring_count(padded, w, want.shape[1]) == list(want[i])
+            matching, _ = comb(b"A" * pad + x[i:i + w], y)
+            changed |= matching != plain
+        assert changed
