@@ -227,6 +227,20 @@ def main():
         dp = {"value": nominal / (dp_ms / 1e3), "unit": "window-cells/s", "ms": dp_ms,
               "speedup_seaweed_over_dp": dp_ms / ms_per_step, "equals_seaweed_on_sampled_rows": dp_same}
         log(f"GPU DP: {dp_ms:.1f} ms, seaweed speedup {dp_ms / ms_per_step:.1f}x")
+        # bit-parallel LCS per window pair (the BLCS comparison of Section 4)
+        pair.plot_blcs(w, out=out[:64])  # warm-up on a slice
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        pair.plot_blcs(w, threshold=thr, out=out, bitmap_out=bm, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        blcs_ms = a.elapsed_time(b)
+        dp["blcs"] = {"value": nominal / (blcs_ms / 1e3), "ms": blcs_ms,
+                      "speedup_seaweed_over_blcs": blcs_ms / ms_per_step,
+                      "equals_seaweed_on_sampled_rows":
+                          bool(np.array_equal(out[torch.as_tensor(sample_rows, device=dev)].cpu().numpy(), sea_rows))}
+        log(f"GPU BLCS: {blcs_ms:.1f} ms, seaweed speedup {blcs_ms / ms_per_step:.1f}x")
 
     others = None
     if not args.no_configs:
@@ -342,12 +356,16 @@ def bench_config(ctx, torch, workloads, k, steps=10):
     ms = float(np.median([_timed_once(torch, lambda: pair.plot(p.w, out=out)) for _ in range(steps)]))
     dp_out = torch.empty_like(out)
     dp_ms = _timed_once(torch, lambda: pair.plot_dp(p.w, out=dp_out))
+    dp_same = bool(torch.equal(out, dp_out))
+    pair.plot_blcs(p.w, out=dp_out)  # warm-up
+    blcs_ms = _timed_once(torch, lambda: pair.plot_blcs(p.w, out=dp_out))
     nominal = float(p.m) * p.n * p.w
     cells = float(rows) * p.n * p.w
     res = {"m": p.m, "n": p.n, "w": p.w, "ms": ms, "value": nominal / (ms / 1e3),
            "unit": "window-cells/s", "roofline_frac": cells * OPS_PER_CELL / (ms / 1e3) / PEAK_U16_OPS,
            "dp_ms": dp_ms, "dp_value": nominal / (dp_ms / 1e3), "speedup_over_dp": dp_ms / ms,
-           "dp_equals_seaweed": bool(torch.equal(out, dp_out))}
+           "dp_equals_seaweed": dp_same, "blcs_ms": blcs_ms, "speedup_over_blcs": blcs_ms / ms,
+           "blcs_equals_seaweed": bool(torch.equal(out, dp_out))}
     pair.close()
     del out, dp_out
     torch.cuda.empty_cache()

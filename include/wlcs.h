@@ -114,6 +114,17 @@ int wlcs_plot_dp(wlcs_ctx *ctx, const uint8_t *x, int64_t m, const uint8_t *y, i
                  uint64_t *bitmap, int64_t ld_words, int32_t threshold, uint16_t *indel,
                  int64_t ld_indel, uint32_t flags, void *stream);
 
+/* The same plot by bit-parallel LCS per window pair (the BLCS method of
+ * Crochemore et al. that Section 4 compares against): for each x-window a
+ * w-bit vector per y-window takes, letter by letter, U = V & M[c],
+ * V = (V + U) | (V - U), and WLCS is the number of its zero bits; O(m n w
+ * ceil(w/32)) word operations.  A second baseline; same outputs and errors
+ * as wlcs_plot. */
+int wlcs_plot_blcs(wlcs_ctx *ctx, const uint8_t *x, int64_t m, const uint8_t *y, int64_t n,
+                   int32_t w, const uint8_t *alphabet, int32_t sigma, uint8_t *wlcs, int64_t ld,
+                   uint64_t *bitmap, int64_t ld_words, int32_t threshold, uint16_t *indel,
+                   int64_t ld_indel, uint32_t flags, void *stream);
+
 /* Alignment-score plot (Section 2's scoring: match 1, mismatch 0, gap -1/2)
  * with a vertical step, as in the paper's experiments (Section 4).  Row r is
  * the x-window starting at x[r * step] (r < ceil((m - w) / step)), column j the
@@ -159,6 +170,9 @@ int wlcs_pair_plot(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, uint8_t *wlc
 int wlcs_pair_plot_dp(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, uint8_t *wlcs, int64_t ld,
                       uint64_t *bitmap, int64_t ld_words, int32_t threshold, uint16_t *indel,
                       int64_t ld_indel, uint32_t flags, void *stream);
+int wlcs_pair_plot_blcs(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, uint8_t *wlcs, int64_t ld,
+                        uint64_t *bitmap, int64_t ld_words, int32_t threshold, uint16_t *indel,
+                        int64_t ld_indel, uint32_t flags, void *stream);
 
 /* ---- strided and sparse plots ---------------------------------------------
  * Section 3's step size: only windows starting at multiples of a step are

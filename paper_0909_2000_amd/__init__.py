@@ -85,11 +85,13 @@ def _load():
     plot_args = [vp, u8p, i64, u8p, i64, i32, u8p, i32, vp, i64, vp, i64, i32, vp, i64, u32, vp]
     lib.wlcs_plot.argtypes = plot_args
     lib.wlcs_plot_dp.argtypes = plot_args
+    lib.wlcs_plot_blcs.argtypes = plot_args
     lib.wlcs_pair_create.argtypes = [vp, u8p, i64, u8p, i64, u8p, i32, vp, ctypes.POINTER(vp)]
     lib.wlcs_pair_destroy.argtypes = [vp]
     pair_args = [vp, vp, i32, vp, i64, vp, i64, i32, vp, i64, u32, vp]
     lib.wlcs_pair_plot.argtypes = pair_args
     lib.wlcs_pair_plot_dp.argtypes = pair_args
+    lib.wlcs_pair_plot_blcs.argtypes = pair_args
     lib.wlcs_score_plot.argtypes = [vp, u8p, i64, u8p, i64, i32, i32, u8p, i32, vp, i64, vp, i64, i32,
                                     u32, vp]
     lib.wlcs_batch.argtypes = [vp, ctypes.POINTER(Job), i32, vp]
@@ -109,7 +111,8 @@ def _load():
               "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
               "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
               "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
-              "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided"):
+              "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs",
+              "wlcs_pair_plot_blcs"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -122,7 +125,7 @@ def exported_symbols() -> list:
             "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
             "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
             "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
-            "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided"]
+            "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs", "wlcs_pair_plot_blcs"]
 
 
 # the wlcs_dot record
@@ -395,6 +398,13 @@ class Context:
         return self._call("wlcs_plot_dp", x, y, w, alphabet, threshold, indel, full_range, out,
                           bitmap_out, indel_out, want_plot, stream)
 
+    def plot_blcs(self, x, y, w: int, alphabet=DNA, threshold: int | None = None, indel: bool = False,
+                  full_range: bool = False, out=None, bitmap_out=None, indel_out=None,
+                  want_plot: bool = True, stream=None) -> dict:
+        """The same plot by bit-parallel LCS per window pair on the GPU."""
+        return self._call("wlcs_plot_blcs", x, y, w, alphabet, threshold, indel, full_range, out,
+                          bitmap_out, indel_out, want_plot, stream)
+
 
 class Pair:
     """x and y resident on the device as letter codes (wlcs_pair)."""
@@ -446,6 +456,11 @@ class Pair:
     def plot_dp(self, w, threshold=None, indel=False, full_range=False, out=None, bitmap_out=None,
                 indel_out=None, want_plot=True, stream=None) -> dict:
         return self._run("wlcs_pair_plot_dp", w, threshold, indel, full_range, out, bitmap_out,
+                         indel_out, want_plot, stream)
+
+    def plot_blcs(self, w, threshold=None, indel=False, full_range=False, out=None, bitmap_out=None,
+                  indel_out=None, want_plot=True, stream=None) -> dict:
+        return self._run("wlcs_pair_plot_blcs", w, threshold, indel, full_range, out, bitmap_out,
                          indel_out, want_plot, stream)
 
     def _run_strided(self, fn, w, hx, hy, threshold, indel, want_plot, bitmap, dot_cap, full_range,

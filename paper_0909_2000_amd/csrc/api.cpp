@@ -198,7 +198,7 @@ void release(Prepared& p, hipStream_t stream) {
     p = Prepared();
 }
 
-enum class Path { Seaweed, Dp };
+enum class Path { Seaweed, Dp, Blcs };
 
 // Code-array lengths (16-bit elements) the kernels read for a plot: x is read
 // up to 64 strips past the last block plus a window, y up to two tiles past
@@ -244,6 +244,14 @@ wlcs::PlotArgs make_args(int64_t rows, int64_t cols, int32_t w, uint8_t* out, in
     return a;
 }
 
+hipError_t launch_path(Path path, const wlcs::PlotArgs& a, hipStream_t stream) {
+    switch (path) {
+        case Path::Seaweed: return wlcs::launch_seaweed(a, stream);
+        case Path::Dp: return wlcs::launch_dp(a, stream);
+        default: return wlcs::launch_blcs(a, stream);
+    }
+}
+
 int plot_common(Path path, wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, int32_t w,
                 const uint8_t* alphabet, int32_t sigma, uint8_t* out, int64_t ld, uint64_t* bitmap,
                 int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel, uint32_t flags,
@@ -277,7 +285,8 @@ int plot_common(Path path, wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uin
     }
     a.xf = p.xf;
     a.yg = p.yg;
-    hipError_t e = path == Path::Seaweed ? wlcs::launch_seaweed(a, stream) : wlcs::launch_dp(a, stream);
+    a.sigma = sigma;
+    hipError_t e = launch_path(path, a, stream);
     release(p, stream);
     if (e != hipSuccess) return fail(ctx, e);
     return WLCS_OK;
@@ -290,6 +299,7 @@ struct wlcs_pair {
     int device = 0;
     hipStream_t stream = nullptr;  // creation stream: the codes are allocated and freed in its order
     int64_t m = 0, n = 0;
+    int32_t sigma = 0;  // letters of the pair's alphabet
     uint16_t* xf = nullptr;  // capacity xf_cap
     uint16_t* yg = nullptr;  // capacity yg_cap
     int64_t xf_cap = 0, yg_cap = 0;
@@ -321,8 +331,9 @@ int pair_plot_common(Path path, wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w,
     if (xf_len > pair->xf_cap || yg_len > pair->yg_cap) return WLCS_EINVAL;  // cannot happen for valid tiles
     a.xf = pair->xf;
     a.yg = pair->yg;
+    a.sigma = pair->sigma;
     hipStream_t stream = (hipStream_t)stream_;
-    hipError_t e = path == Path::Seaweed ? wlcs::launch_seaweed(a, stream) : wlcs::launch_dp(a, stream);
+    hipError_t e = launch_path(path, a, stream);
     if (e != hipSuccess) return fail(ctx, e);
     return WLCS_OK;
 }
@@ -374,7 +385,8 @@ int strided_common(Path path, wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, i
     if (pair->m + wlcs::w_class(w) > pair->xf_cap || yg_len > pair->yg_cap) return WLCS_EINVAL;
     a.xf = pair->xf;
     a.yg = pair->yg;
-    const hipError_t e = path == Path::Seaweed ? wlcs::launch_seaweed(a, stream) : wlcs::launch_dp(a, stream);
+    a.sigma = pair->sigma;
+    const hipError_t e = launch_path(path, a, stream);
     if (e != hipSuccess) return fail(ctx, e);
     return WLCS_OK;
 }
@@ -587,6 +599,14 @@ int wlcs_plot(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int6
                        indel, ld_indel, flags, stream);
 }
 
+int wlcs_plot_blcs(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, int32_t w,
+                   const uint8_t* alphabet, int32_t sigma, uint8_t* wlcs, int64_t ld, uint64_t* bitmap,
+                   int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel, uint32_t flags,
+                   void* stream) {
+    return plot_common(Path::Blcs, ctx, x, m, y, n, w, alphabet, sigma, wlcs, ld, bitmap, ld_words, threshold,
+                       indel, ld_indel, flags, stream);
+}
+
 int wlcs_plot_dp(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, int32_t w,
                  const uint8_t* alphabet, int32_t sigma, uint8_t* wlcs, int64_t ld, uint64_t* bitmap,
                  int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel, uint32_t flags,
@@ -660,6 +680,7 @@ int wlcs_pair_create(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* 
     pr->device = ctx->device;
     pr->m = m;
     pr->n = n;
+    pr->sigma = sigma;
     // room for any window (<= 256 capacity) and any tile (<= kMaxTile)
     pr->xf_cap = m + 64 + 256 + 64;
     pr->yg_cap = n + 2 * (int64_t)kMaxTile + 128 + 256 + 64;
@@ -719,6 +740,13 @@ int wlcs_pair_plot_dp_strided(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, i
                               uint64_t* dot_count, uint32_t flags, void* stream) {
     return strided_common(Path::Dp, ctx, pair, w, hx, hy, wlcs, ld, bitmap, ld_words, threshold, indel, ld_indel,
                           dots, dot_cap, dot_count, flags, stream);
+}
+
+int wlcs_pair_plot_blcs(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, uint8_t* wlcs, int64_t ld,
+                        uint64_t* bitmap, int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel,
+                        uint32_t flags, void* stream) {
+    return pair_plot_common(Path::Blcs, ctx, pair, w, wlcs, ld, bitmap, ld_words, threshold, indel, ld_indel,
+                            flags, stream);
 }
 
 int wlcs_pair_plot_dp(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, uint8_t* wlcs, int64_t ld,

@@ -171,22 +171,24 @@ hipError_t launch_dp(const PlotArgs& a, hipStream_t stream) {
         case 128: e = dp_wc<128>(a, wout, ldo, stream); break;
         default: e = dp_wc<256>(a, wout, ldo, stream); break;
     }
-    if (e == hipSuccess && epi) {
-        const int64_t waves = a.rows * ((a.cols + 63) / 64);
-        const int64_t blocks = (waves + 3) / 4;
-        if (blocks > 0x7FFFFFFFll) e = hipErrorInvalidValue;
-        else {
-            hipLaunchKernelGGL(epilogue_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, wout, ldo, a.rows,
-                               a.cols, a.w, a.bitmap32, a.ld_words32, a.threshold, a.indel, a.ld_indel, a.dots,
-                               a.dot_cap, a.dot_count, a.xstride, a.hy);
-            e = hipGetLastError();
-        }
-    }
+    if (e == hipSuccess && epi) e = launch_epilogue(a, wout, ldo, stream);
     if (!a.wlcs) {
         hipError_t e2 = hipFreeAsync(wout, stream);
         if (e == hipSuccess) e = e2;
     }
     return e;
+}
+
+hipError_t launch_epilogue(const PlotArgs& a, const uint8_t* wout, int64_t ldo, hipStream_t stream) {
+    if (!a.bitmap32 && !a.indel && !a.dot_count) return hipSuccess;
+    const int64_t waves = a.rows * ((a.cols + 63) / 64);
+    const int64_t blocks = (waves + 3) / 4;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(epilogue_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, wout, ldo, a.rows, a.cols,
+                       a.w, a.bitmap32, a.ld_words32, a.threshold, a.indel, a.ld_indel, a.dots, a.dot_cap,
+                       a.dot_count, a.xstride, a.hy);
+    return hipGetLastError();
 }
 
 hipError_t launch_encode(const uint8_t* raw, int64_t len, const uint8_t* map256, int x_side, uint16_t* out,

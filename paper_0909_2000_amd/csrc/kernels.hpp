@@ -38,6 +38,7 @@ struct PlotArgs {
     int32_t ws = 1;          // store every ws-th combed window (1 or 2)
     int32_t bias = 0;        // subtracted from every stored value
     int64_t hy = 1;          // strided plots: output column c is the window c * hy
+    int32_t sigma = 64;      // letters of the alphabet (the BLCS baseline keeps a mask per letter)
     DotRec* dots = nullptr;  // sparse output (may be null while counting)
     int64_t dot_cap = 0;
     unsigned long long* dot_count = nullptr;  // non-null: list the dots
@@ -125,6 +126,9 @@ hipError_t launch_encode(const uint8_t* raw, int64_t len, const uint8_t* map256,
 hipError_t launch_seaweed(const PlotArgs& a, hipStream_t stream);
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream);
 hipError_t launch_dp(const PlotArgs& a, hipStream_t stream);
+hipError_t launch_blcs(const PlotArgs& a, hipStream_t stream);
+// bitmap, indel and dot list of a finished plot (at wout, row stride ldo)
+hipError_t launch_epilogue(const PlotArgs& a, const uint8_t* wout, int64_t ldo, hipStream_t stream);
 int batch_variant(int w);
 constexpr int kBatchMaxW = 128;            // longer windows leave the batched kernel
 constexpr int kBatchWavesPerCu = 8;        // resident waves per CU of batch_kernel
