@@ -94,3 +94,44 @@ def test_sparse_serving_results_equal_alone(oracle_mod):
         want = oracle_mod.dot_list(plot, r.w, r.threshold, r.hx, r.hy)
         got, _ = wl.dot_records(srv.result(r.jid))
         np.testing.assert_array_equal(got.view(np.uint8), want.view(np.uint8))
+
+
+def test_serving_stream_prefix(oracle_mod):
+    """The first 120 jobs of the serving configuration's own stream (Poisson
+    arrivals, DNA/protein, m, n log-uniform in [500, 50000], w in {16, 32, 64,
+    128}, bitmap at ceil(3w/4) and indel), compressed in time so batches
+    overlap: every job's outputs equal the job run alone on the device, 20
+    seeded jobs match the oracle on a sampled row, and the budget holds."""
+    import torch
+    import paper_0909_2000_amd as wl
+    from paper_0909_2000_amd import serve
+
+    jobs = workloads.serving_jobs(rate=1.0, njobs=120)
+    reqs = serve.requests_from_workload(jobs, rate_scale=2000.0)
+    budget = 48 << 30
+    ctx = wl.Context(0)
+    ex = serve.GpuExecutor(0, streams=3)  # latency tiles, as served
+    srv = serve.Server(ex, budget_bytes=budget, max_jobs=64, max_batch=16, keep_results=True)
+    print("serving stream prefix: 120 jobs", flush=True)
+    rep = srv.run(reqs)
+    torch.cuda.synchronize()
+    print("report", rep, flush=True)
+    assert rep["rejected"] == 0 and srv.peak_use <= budget and rep["overlapped_launches"] > 0
+    g = workloads.rng(505)
+    checked = set(int(k) for k in g.choice(len(reqs), 20, replace=False))
+    for k, r in enumerate(reqs):
+        res = srv.result(r.jid)
+        pair = ctx.pair(r.x, r.y, alphabet=r.alphabet)
+        alone = pair.plot(r.w, threshold=r.threshold, indel=True, want_plot=k in checked)
+        assert torch.equal(res["bitmap"], alone["bitmap"]), r.jid
+        assert torch.equal(res["indel"], alone["indel"]), r.jid
+        if k in checked:
+            rows = alone["wlcs"].shape[0]
+            row = int(g.integers(0, rows))
+            want = oracle_mod.wlcs_rows(r.x, r.y, r.w, [row])
+            np.testing.assert_array_equal(alone["wlcs"][row:row + 1].cpu().numpy(), want)
+            np.testing.assert_array_equal(res["indel"][row:row + 1].cpu().numpy().view(np.uint16),
+                                          oracle_mod.indel(want, r.w))
+        srv.jobs[r.jid].results = None  # release the job's outputs as the check goes
+        pair.close()
+        del alone, res
