@@ -23,7 +23,13 @@ kernels:
   right = s xor t xor bottom;
 * the padding rows of the kernels: rows of a letter that y never holds, put on
   top of the strip, let every seaweed from the top pass straight down, so the
-  padded strip has exactly the exits of the strip itself.
+  padded strip has exactly the exits of the strip itself;
+* the score-plot schedule: in strings blown up with a separator before every
+  letter (Section 2's reduction of the alignment score), a separator column
+  reduces to one max and one min per (separator row, letter row) pair taken
+  bottom-up, and a letter column to a mismatch min/max on the separator row
+  followed by the general cell; the kernels' form of it, with up to 15 unused
+  pairs skipped at the top of the strip, gives the same exits.
 """
 import itertools
 
@@ -276,3 +282,67 @@ def test_padding_rows_are_transparent(oracle_mod, pad):
             matching, _ = comb(b"A" * pad + x[i:i + w], y)
             changed |= matching != plain
         assert changed
+
+
+def comb_blown_up(letters, yl, cap):
+    """The kernels' schedule for blown-up strings ('$' a1 '$' a2 ... against
+    '$' b1 '$' b2 ...): cap pair slots, the first cap - len(letters) (< 16)
+    unused; returns the exit label of every column."""
+    npairs = len(letters)
+    pad = cap - npairs
+    assert 0 <= pad < 16
+    h = [LEFT] * (2 * cap)
+    code = [None] * pad + list(letters)
+    exits = []
+    for l in range(2 * len(yl)):
+        if l % 2 == 0:  # separator column: bottom-up pairs, then the new top seaweed
+            out = None
+            for r in range(cap - 1, -1, -1):
+                if r >= pad:
+                    a, b = h[2 * r], h[2 * r + 1]
+                    if r == cap - 1:
+                        out = max(a, b)
+                    else:
+                        h[2 * r + 2] = max(a, b)
+                    h[2 * r + 1] = min(a, b)
+                elif r == pad - 1:
+                    h[2 * r + 2] = l
+            if pad == 0:
+                h[0] = l
+        else:           # letter column: top-down
+            c, out = yl[l // 2], l
+            for r in range(pad, cap):
+                a = h[2 * r]
+                h[2 * r], out = min(a, out), max(a, out)  # separator row: a mismatch
+                s_ = h[2 * r + 1]
+                if code[r] == c:
+                    h[2 * r + 1], out = out, s_
+                else:
+                    h[2 * r + 1], out = min(s_, out), max(s_, out)
+        exits.append(out)
+    return exits
+
+
+@pytest.mark.parametrize("cap", [16, 32])
+def test_blown_up_schedule_equals_combing(oracle_mod, cap):
+    """The score-plot schedule against plain combing of the blown-up strings,
+    and its window counts against the score oracle through the blow-up."""
+    g = workloads.rng(700 + cap)
+    for trial in range(60):
+        npairs = int(g.integers(cap - 15, cap + 1))
+        letters = bytes(workloads.iid(g, npairs, workloads.DNA))
+        yl = bytes(workloads.iid(g, int(g.integers(1, 14)), workloads.DNA))
+        xb = b"".join(b"$" + bytes([c]) for c in letters)
+        yb = b"".join(b"$" + bytes([c]) for c in yl)
+        plain, _ = comb(xb, yb)
+        assert comb_blown_up(letters, yl, cap) == plain
+    # one window of 2w columns: w - count is LLCS(x', y') and score = LLCS - w
+    w = cap - 3
+    letters = bytes(workloads.iid(g, w, workloads.DNA))
+    yl = bytes(workloads.iid(g, w + 9, workloads.DNA))
+    exits = comb_blown_up(letters, yl, cap)
+    for j in range(0, 2 * (len(yl) - w) + 1, 2):
+        d = sum(1 for l in range(j, j + 2 * w) if exits[l] >= j)
+        score2 = 2 * (2 * w - d) - 2 * w
+        want = oracle_mod.score(letters, yl[j // 2:j // 2 + w])
+        assert score2 == 2 * want
