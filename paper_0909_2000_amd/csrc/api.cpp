@@ -63,8 +63,12 @@ int64_t n_windows(int64_t len, int32_t w, bool full) {
 // register budget; LDS allows 4 more at 8.7 KB per wave for the 32-window
 // flush and 3 at 12.8 KB for the 64-window one).
 int waves_per_simd(int wc, int ws) {
+    if (ws == 2) {  // score plots: the separator schedule, classes of 32 rows
+        const int dc = (wc + 31) / 32 * 32;
+        return dc <= 64 ? 3 : dc <= 128 ? 2 : 1;
+    }
     const int regs = wc <= 32 ? 4 : wc == 64 ? 3 : wc == 128 ? 2 : 1;
-    const int lds = (wc >= 64 || ws == 2) ? 3 : 4;
+    const int lds = wc >= 64 ? 3 : 4;
     return std::min(regs, lds);
 }
 
@@ -80,7 +84,7 @@ int32_t choose_tile(const wlcs_ctx* ctx, int64_t rows, int64_t cols, int32_t w, 
     static const int32_t cand[] = {64, 128, 192, 256, 384, 512, 768, 1024, 1280, 1536, 2048, 2560, 3072, 4096, 6144, 8192, 12288, 16384};
     const int64_t nblocks = (rows + 63) / 64;
     const double simds = 4.0 * ctx->cus;
-    const double tail = 2.0 / waves_per_simd(wlcs::w_class(w), ws);
+    const double tail = 2.0 / waves_per_simd(ws == 2 ? w : wlcs::w_class(w), ws);
     const int64_t cap = std::max<int64_t>(64, (cols + 63) / 64 * 64);
     int32_t best = 64;
     double best_cost = 1e300;

@@ -90,6 +90,19 @@ __device__ __forceinline__ uint32_t seaweed_cell_top(uint32_t& s, uint32_t t, ui
     return down;
 }
 
+// Sort two labels per half: lo <- min(lo, b), returns max(lo, b).  One
+// volatile block per call keeps the calls in program order, so that a column
+// of them does not keep many results live at once.  Pure ALU.
+__device__ __forceinline__ uint32_t pk_sort2(uint32_t& lo, uint32_t b) {
+    uint32_t hi;
+    asm volatile(
+        "v_pk_max_u16 %0, %1, %2\n\t"
+        "v_pk_min_u16 %1, %1, %2"
+        : "=&v"(hi), "+v"(lo)
+        : "v"(b));
+    return hi;
+}
+
 // One cell of the plain LCS dynamic program for two windows at once:
 //     z = x_code (half HI of x, both lanes) + y_codes    (0 iff the letters match)
 //     L = max(up, left, sat(diag + 1 - z))               (diag + 1 on a match, else 0)

@@ -56,8 +56,9 @@
 namespace wlcs {
 namespace {
 
-template <int WC, bool EXACT, int WS, bool SP>
-__global__ __launch_bounds__(64, min_waves_per_simd(WC)) void seaweed_kernel(const uint16_t* __restrict__ xf,
+template <int WC, bool EXACT, int WS, bool SP, bool DL = false>
+__global__ __launch_bounds__(64, DL ? min_waves_per_simd_dl(WC) : min_waves_per_simd(WC)) void seaweed_kernel(
+                                                                              const uint16_t* __restrict__ xf,
                                                                               const uint32_t* __restrict__ yg32,
                                                                               uint8_t* __restrict__ out,
                                                                               uint32_t* __restrict__ bm32,
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(64, min_waves_per_simd(WC)) void seaweed_kernel(con
     const int64_t unit = blockIdx.x;
     const int pr = (int)(unit / nblocks);
     const int64_t sb = unit - (int64_t)pr * nblocks;
-    comb_unit<WC, EXACT, WS, SP>(xf, yg32, out, bm32, indel, dots, dot_count, g, sb, pr, ring, stage);
+    comb_unit<WC, EXACT, WS, SP, DL>(xf, yg32, out, bm32, indel, dots, dot_count, g, sb, pr, ring, stage);
 }
 
 __global__ void zero_u64(unsigned long long* p) {
@@ -92,6 +93,20 @@ void launch_ws(const PlotArgs& a, const Geom& g, uint32_t units, hipStream_t str
                            a.bitmap32, a.indel, a.dots, a.dot_count, g);
 }
 
+// score plots: the separator schedule in the class of the window rounded up
+// to 32 rows
+template <int WC>
+hipError_t launch_dl(const PlotArgs& a, hipStream_t stream) {
+    const int64_t nblocks = (a.rows + 63) / 64;
+    const int64_t units = nblocks * a.npairs;
+    if (units <= 0) return hipSuccess;
+    if (units > 0x7FFFFFFFll) return hipErrorInvalidValue;
+    const Geom g = geom_of(a);
+    hipLaunchKernelGGL((seaweed_kernel<WC, false, 2, false, true>), dim3((uint32_t)units), dim3(64), 0, stream,
+                       a.xf, (const uint32_t*)a.yg, a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+    return hipGetLastError();
+}
+
 template <int WC>
 hipError_t launch_wc(const PlotArgs& a, hipStream_t stream) {
     const int64_t nblocks = (a.rows + 63) / 64;
@@ -99,9 +114,7 @@ hipError_t launch_wc(const PlotArgs& a, hipStream_t stream) {
     if (units <= 0) return hipSuccess;
     if (units > 0x7FFFFFFFll) return hipErrorInvalidValue;
     const Geom g = geom_of(a);
-    if (a.ws == 2)
-        launch_ws<WC, 2, false>(a, g, (uint32_t)units, stream);
-    else if (a.hy > 1 || a.dot_count)
+    if (a.hy > 1 || a.dot_count)
         launch_ws<WC, 1, true>(a, g, (uint32_t)units, stream);
     else
         launch_ws<WC, 1, false>(a, g, (uint32_t)units, stream);
@@ -116,6 +129,19 @@ hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream) {
 }
 
 hipError_t launch_seaweed(const PlotArgs& a, hipStream_t stream) {
+    if (a.ws == 2) {  // blown-up strings: even window, separator rows and columns
+        if (a.w % 2 || a.w < 2 || a.w > 256) return hipErrorInvalidValue;
+        switch ((a.w + 31) / 32) {
+            case 1: return launch_dl<32>(a, stream);
+            case 2: return launch_dl<64>(a, stream);
+            case 3: return launch_dl<96>(a, stream);
+            case 4: return launch_dl<128>(a, stream);
+            case 5: return launch_dl<160>(a, stream);
+            case 6: return launch_dl<192>(a, stream);
+            case 7: return launch_dl<224>(a, stream);
+            default: return launch_dl<256>(a, stream);
+        }
+    }
     switch (w_class(a.w)) {
         case 16: return launch_wc<16>(a, stream);
         case 32: return launch_wc<32>(a, stream);

@@ -4,6 +4,8 @@
 // method and the mapping are described at the top of seaweed.hip.
 #pragma once
 
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "packed.hpp"
 
@@ -31,6 +33,9 @@ constexpr int stage_dwords(int wc, int ws = 1) { return 2 * 64 * stage_pitch(wc,
 // Occupancy each window class is compiled for (waves per SIMD): the w labels
 // and w/2 code registers per lane plus the flush temporaries must fit.
 constexpr int min_waves_per_simd(int wc) { return wc <= 32 ? 4 : wc <= 64 ? 3 : wc <= 128 ? 2 : 1; }
+// The same for the score-plot schedule (DL), whose strip of wc rows keeps
+// codes for its wc / 2 letter rows only (wc / 4 registers).
+constexpr int min_waves_per_simd_dl(int wc) { return wc <= 64 ? 3 : wc <= 128 ? 2 : 1; }
 
 // Stores of a strided or sparse plot for one flushed block: window j0 + b of
 // strip s0 + r sits in byte b of row r of the staged block (stride pitch
@@ -100,13 +105,25 @@ __device__ __forceinline__ void strided_flush(uint8_t* __restrict__ out, uint16_
 
 // SP: the strided / sparse variant (store every g.hy-th window and list the
 // dots of the windows at or above the threshold; WS = 1 only).
-template <int WC, bool EXACT, int WS = 1, bool SP = false>
+// DL: the score-plot schedule for strings blown up with a separator before
+// every letter (WS = 2; Section 2's reduction of the alignment score).  Rows
+// alternate separator, letter, separator, ...; so do the columns (tile starts
+// are even).  In a separator column every separator row matches and every
+// letter row mismatches, so taken bottom-up the pair (2r, 2r + 1) sends the
+// larger label to row 2r + 2 (or out of the strip) and keeps the smaller one,
+// and the new top seaweed enters row 0: one max and one min per pair.  In a
+// letter column the separator row is a mismatch (min/max) and the letter row
+// the general cell.  The strip has WC / 2 pair slots; a window of w / 2 < WC / 2
+// pairs leaves the top WC / 2 - w / 2 (< 16) slots unused, skipped by uniform
+// branches on the first 16 slots only.
+template <int WC, bool EXACT, int WS = 1, bool SP = false, bool DL = false>
 __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32,
                                           uint8_t* __restrict__ out, uint32_t* __restrict__ bm32,
                                           uint16_t* __restrict__ indel, DotRec* __restrict__ dots,
                                           unsigned long long* __restrict__ dot_count, const Geom& g, int64_t sb,
                                           int pr, uint32_t* __restrict__ ring, uint32_t* __restrict__ stage) {
     static_assert(!SP || WS == 1, "strided and sparse plots store single windows");
+    static_assert(!DL || (WS == 2 && !EXACT && WC % 32 == 0), "the score-plot schedule");
     constexpr int RW = ring_words(WC);
     constexpr int FL = flush_windows(WC, WS);
     constexpr int PITCH = stage_pitch(WC, WS);
@@ -125,20 +142,31 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     // straight down -- the padded strip has the same exits as the strip of
     // height w.  Rows from wpad on are skipped 16 at a time by one uniform
     // branch, so no cell carries a test of its own.
-    const int pad = EXACT ? 0 : ((w + 15) & ~15) - w;
-    const int wpad = EXACT ? WC : w + pad;
+    const int pad = (EXACT || DL) ? 0 : ((w + 15) & ~15) - w;
+    const int wpad = (EXACT || DL) ? WC : w + pad;
+    constexpr int NP = WC / 2;                 // DL: pair slots
+    const int ppad = DL ? NP - w / 2 : 0;      // DL: unused slots at the top
     // x letters of this lane's strip, two rows per register (lanes past the
-    // last strip comb a copy of the last one; their results are never stored)
-    uint32_t xc[WC / 2];
+    // last strip comb a copy of the last one; their results are never stored);
+    // DL: the letters of the letter rows only, two slots per register
+    constexpr int NXC = DL ? WC / 4 : WC / 2;
+    uint32_t xc[NXC];
     {
         const int64_t sx = s0 + lane < g.rows ? s0 + lane : g.rows - 1;
         const uint16_t* xp = xf + sx * g.xstride;
         constexpr uint32_t PADF = f_code(kPadCode);
 #pragma unroll
-        for (int j = 0; j < WC / 2; ++j) {
-            const int i0 = 2 * j - pad, i1 = 2 * j + 1 - pad;
-            const uint32_t lo = (EXACT || i0 >= 0) ? (uint32_t)xp[EXACT ? 2 * j : i0] : PADF;
-            const uint32_t hi = (EXACT || i1 >= 0) ? (uint32_t)xp[EXACT ? 2 * j + 1 : i1] : PADF;
+        for (int j = 0; j < NXC; ++j) {
+            uint32_t lo, hi;
+            if (DL) {  // slot r holds letter r - ppad, at row 2 (r - ppad) + 1 of the strip
+                const int i0 = 2 * j - ppad, i1 = 2 * j + 1 - ppad;
+                lo = i0 >= 0 ? (uint32_t)xp[2 * i0 + 1] : PADF;
+                hi = i1 >= 0 ? (uint32_t)xp[2 * i1 + 1] : PADF;
+            } else {
+                const int i0 = 2 * j - pad, i1 = 2 * j + 1 - pad;
+                lo = (EXACT || i0 >= 0) ? (uint32_t)xp[EXACT ? 2 * j : i0] : PADF;
+                hi = (EXACT || i1 >= 0) ? (uint32_t)xp[EXACT ? 2 * j + 1 : i1] : PADF;
+            }
             xc[j] = lo | (hi << 16);
         }
     }
@@ -174,15 +202,40 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     uint32_t ynext = yload(0);
 
     // Comb column l (tile-relative) through the w rows and update the sliding
-    // count; returns w - count for the window starting at l - w + 1.
-    auto column = [&](int l) -> uint32_t {
+    // count; returns w - count for the window starting at l - w + 1.  par is
+    // the parity of l (DL: 0 = separator column, 1 = letter column).
+    auto column = [&](int l, auto par) -> uint32_t {
         const uint32_t Y = ynext;
         ynext = yload(l + 1);
-        uint32_t t = seaweed_cell_top(h[0], pk_rep(l - org + 1), xc[0], Y);
+        const uint32_t top = pk_rep(l - org + 1);
+        uint32_t t = top;
+        if constexpr (!DL) {
+            t = seaweed_cell_top(h[0], top, xc[0], Y);
 #pragma unroll
-        for (int k = 1; k < WC; ++k) {
-            if (!EXACT && (k & 15) == 0 && k >= wpad) break;  // uniform, once per 16 rows
-            t = (k & 1) ? seaweed_cell<1>(h[k], t, xc[k >> 1], Y) : seaweed_cell<0>(h[k], t, xc[k >> 1], Y);
+            for (int k = 1; k < WC; ++k) {
+                if (!EXACT && (k & 15) == 0 && k >= wpad) break;  // uniform, once per 16 rows
+                t = (k & 1) ? seaweed_cell<1>(h[k], t, xc[k >> 1], Y) : seaweed_cell<0>(h[k], t, xc[k >> 1], Y);
+            }
+        } else if constexpr (decltype(par)::value == 0) {  // separator column, bottom-up
+#pragma unroll
+            for (int r = NP - 1; r >= 0; --r) {
+                if (r >= 16 || r >= ppad) {  // uniform (always true from slot 16 on)
+                    const uint32_t hi = pk_sort2(h[2 * r + 1], h[2 * r]);
+                    if (r == NP - 1) t = hi;
+                    else h[2 * r + 2] = hi;
+                } else if (r == ppad - 1) {
+                    h[2 * r + 2] = top;  // the first used slot's separator row
+                }
+            }
+            if (ppad == 0) h[0] = top;
+        } else {  // letter column, top-down
+#pragma unroll
+            for (int r = 0; r < NP; ++r) {
+                if (r < 16 && r < ppad) continue;  // uniform
+                const uint32_t d = pk_sort2(h[2 * r], t);  // separator row: a mismatch
+                t = (r & 1) ? seaweed_cell<1>(h[2 * r + 1], d, xc[r >> 1], Y)
+                            : seaweed_cell<0>(h[2 * r + 1], d, xc[r >> 1], Y);
+            }
         }
         // consume the mark of start column l - w (prefetched after the
         // previous column's marks were set)
@@ -206,8 +259,19 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         return rem2;
     };
 
-    // warm-up columns: no window is complete yet
-    for (int l = 0; l < w - 1; ++l) (void)column(l);
+    using P0 = std::integral_constant<int, 0>;
+    using P1 = std::integral_constant<int, 1>;
+    // warm-up columns: no window is complete yet (DL: w is even, so the w - 1
+    // warm-up columns end on a separator column)
+    if constexpr (DL) {
+        for (int l = 0; l + 1 < w - 1; l += 2) {
+            (void)column(l, P0{});
+            (void)column(l + 1, P1{});
+        }
+        (void)column(w - 2, P0{});
+    } else {
+        for (int l = 0; l < w - 1; ++l) (void)column(l, P0{});
+    }
 
     const uint32_t bm_words = (uint32_t)(((g.ocols + 63) >> 6) * 2);
     for (int jb = 0; jb < nproc; jb += FL) {
@@ -221,11 +285,11 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                 for (int k = 0; k < WC; ++k) h[k] = pk_sub_sat(h[k], d2);
                 org = norg;
             }
-            const int l = jj + w - 1;
-            const uint32_t r0 = column(l);
-            const uint32_t r1 = column(l + 1);
-            const uint32_t r2 = column(l + 2);
-            const uint32_t r3 = column(l + 3);
+            const int l = jj + w - 1;  // DL: odd (w even, jj a multiple of 4)
+            const uint32_t r0 = column(l, P1{});
+            const uint32_t r1 = column(l + 1, P0{});
+            const uint32_t r2 = column(l + 2, P1{});
+            const uint32_t r3 = column(l + 3, P0{});
             // bytes 0 (tile A) and 2 (tile B) of the four results, gathered
             // into one dword per tile: r0.b0 r0.b2 r1.b0 r1.b2, then the same
             // for r2, r3, then the even and the odd bytes of the two
