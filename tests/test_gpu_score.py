@@ -25,7 +25,10 @@ def _say(*a):
     sys.stdout.flush()
 
 
-CASES = [(w, step) for w in (1, 2, 5, 8, 16, 31, 32, 50, 64, 100, 127) for step in (1, 5)] + [(7, 3), (64, 2)]
+# windows across every 32-row class of the blown-up strip (2w rows) and
+# every count of unused top pairs from 0 to 15
+CASES = ([(w, step) for w in (1, 2, 5, 8, 16, 31, 32, 50, 64, 100, 127) for step in (1, 5)] + [(7, 3), (64, 2)]
+         + [(w, 1) for w in (17, 33, 40, 48, 49, 65, 70, 80, 81, 90, 96, 97, 112, 113)])
 
 
 @pytest.mark.parametrize("w,step", CASES)
@@ -89,3 +92,19 @@ def test_paper_shaped_score_plot_sampled(ctx, oracle_mod):
         np.testing.assert_array_equal(S[r].cpu().numpy(), want)
     d = S.to(torch.int16)
     assert int(d.max()) <= w and int(d.min()) >= -w
+
+
+@pytest.mark.parametrize("w,tile", [(12, 64), (40, 128), (100, 576)])
+def test_score_across_tiles_and_relabelling(ctx, oracle_mod, w, tile):
+    """Long rows (many tiles, the ragged last pair, label rebases every 512
+    windows of the blown-up strings) against the oracle on sampled rows."""
+    import paper_0909_2000_amd as wl
+    g = workloads.rng(480 + w)
+    x, y = workloads.iid(g, w + 70, workloads.DNA), workloads.iid(g, 2 * w + 1700, workloads.DNA)
+    c = wl.Context(0)
+    c.set_tile(1, 255, tile)
+    res = c.score_plot(x, y, w, step=3)["score"].cpu().numpy()
+    rows = res.shape[0]
+    for r in sorted({0, rows // 2, rows - 1}):
+        want = oracle_mod.score_plot(x[3 * r:3 * r + w], y, w, full_range=True)[0, :res.shape[1]]
+        np.testing.assert_array_equal(res[r], want)
