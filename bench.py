@@ -366,6 +366,29 @@ def bench_config(ctx, torch, workloads, k, steps=10):
            "dp_ms": dp_ms, "dp_value": nominal / (dp_ms / 1e3), "speedup_over_dp": dp_ms / ms,
            "dp_equals_seaweed": dp_same, "blcs_ms": blcs_ms, "speedup_over_blcs": blcs_ms / ms,
            "blcs_equals_seaweed": bool(torch.equal(out, dp_out))}
+    if ms < 0.5:
+        # a launch-bound plot: also time it captured in a HIP graph, 100 plots
+        # per replay (the plot call enqueues kernels only: no allocation, no
+        # memset), the per-plot time taken over the replay
+        reps = 100
+        graph = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cap):
+            pair.plot(p.w, out=out, stream=cap)  # warm-up on the capture stream
+            cap.synchronize()
+            with torch.cuda.graph(graph, stream=cap):
+                for _ in range(reps):
+                    pair.plot(p.w, out=out, stream=cap)
+        torch.cuda.current_stream().wait_stream(cap)
+        graph.replay()
+        torch.cuda.synchronize()
+        g_ms = float(np.median([_timed_once(torch, graph.replay) for _ in range(5)])) / reps
+        graph_same = bool(torch.equal(out, dp_out))
+        res.update({"graph_ms_per_plot": g_ms, "graph_value": nominal / (g_ms / 1e3),
+                    "graph_roofline_frac": cells * OPS_PER_CELL / (g_ms / 1e3) / PEAK_U16_OPS,
+                    "graph_equals_blcs": graph_same})
+        del graph
     pair.close()
     del out, dp_out
     torch.cuda.empty_cache()
