@@ -90,18 +90,87 @@ __device__ __forceinline__ uint32_t seaweed_cell_top(uint32_t& s, uint32_t t, ui
     return down;
 }
 
-// Sort two labels per half: lo <- min(lo, b), returns max(lo, b).  One
-// volatile block per call keeps the calls in program order, so that a column
-// of them does not keep many results live at once.  Pure ALU.
-__device__ __forceinline__ uint32_t pk_sort2(uint32_t& lo, uint32_t b) {
-    uint32_t hi;
-    asm volatile(
-        "v_pk_max_u16 %0, %1, %2\n\t"
-        "v_pk_min_u16 %1, %1, %2"
-        : "=&v"(hi), "+v"(lo)
-        : "v"(b));
-    return hi;
+// One pair slot of the score-plot schedule for strings blown up with a
+// separator before every letter: the separator column and the letter column
+// after it, combed in one top-down pass.  Row 2r of the strip (label a) is a
+// separator row, row 2r + 1 (label b) a letter row.
+//   separator column:  mx = max(a, b) moves down to the next slot's
+//                      separator row, b = min(a, b) stays
+//   letter column:     its separator row is a mismatch:  d = max(c, t),
+//                      a = min(c, t), where c is the label the separator
+//                      column sent down from the slot above; its letter row is
+//                      the general cell:  z = x + y,  down = max(b, min(d, z)),
+//                      b = b ^ d ^ down,  t = down
+// Returns mx (the next slot's c).  Pure ALU.
+#define WLCS_FUSED_SLOT_BODY(XSEL)                 \
+    "v_pk_add_u16 %5, %7, %8 " XSEL "\n\t"       \
+    "v_pk_max_u16 %3, %0, %1\n\t"                \
+    "v_pk_min_u16 %1, %0, %1\n\t"                \
+    "v_pk_max_u16 %4, %6, %2\n\t"                \
+    "v_pk_min_u16 %0, %6, %2\n\t"                \
+    "v_pk_min_u16 %5, %4, %5\n\t"                \
+    "v_pk_max_u16 %2, %1, %5\n\t"                \
+    "v_xor_b32 %1, %1, %4\n\t"                   \
+    "v_xor_b32 %1, %1, %2"
+template <int HI>
+__device__ __forceinline__ uint32_t fused_slot(uint32_t& a, uint32_t& b, uint32_t& t, uint32_t c, uint32_t x,
+                                               uint32_t y) {
+    uint32_t mx, d, z;
+    if (HI)
+        asm volatile(WLCS_FUSED_SLOT_BODY("op_sel:[1,0]")
+                     : "+v"(a), "+v"(b), "+v"(t), "=&v"(mx), "=&v"(d), "=&v"(z)
+                     : "v"(c), "v"(x), "s"(y));
+    else
+        asm volatile(WLCS_FUSED_SLOT_BODY("op_sel_hi:[0,1]")
+                     : "+v"(a), "+v"(b), "+v"(t), "=&v"(mx), "=&v"(d), "=&v"(z)
+                     : "v"(c), "v"(x), "s"(y));
+    return mx;
 }
+#undef WLCS_FUSED_SLOT_BODY
+
+// Two such slots of two independent passes (P: operands 0-5 and 12-14, Q:
+// operands 6-11 and 15-17), their instructions alternated so that no
+// instruction directly follows the one it depends on.  HP picks the half of
+// P's x register (Q takes the other).  Each pass's c becomes its mx.  Pure
+// ALU.
+#define WLCS_FUSED_SLOT2_BODY(PSEL, QSEL)             \
+    "v_pk_add_u16 %5, %13, %14 " PSEL "\n\t"       \
+    "v_pk_add_u16 %11, %16, %17 " QSEL "\n\t"      \
+    "v_pk_max_u16 %3, %0, %1\n\t"                   \
+    "v_pk_max_u16 %9, %6, %7\n\t"                   \
+    "v_pk_min_u16 %1, %0, %1\n\t"                   \
+    "v_pk_min_u16 %7, %6, %7\n\t"                   \
+    "v_pk_max_u16 %4, %12, %2\n\t"                  \
+    "v_pk_max_u16 %10, %15, %8\n\t"                 \
+    "v_pk_min_u16 %0, %12, %2\n\t"                  \
+    "v_pk_min_u16 %6, %15, %8\n\t"                  \
+    "v_pk_min_u16 %5, %4, %5\n\t"                   \
+    "v_pk_min_u16 %11, %10, %11\n\t"                \
+    "v_pk_max_u16 %2, %1, %5\n\t"                   \
+    "v_pk_max_u16 %8, %7, %11\n\t"                  \
+    "v_xor_b32 %1, %1, %4\n\t"                      \
+    "v_xor_b32 %7, %7, %10\n\t"                     \
+    "v_xor_b32 %1, %1, %2\n\t"                      \
+    "v_xor_b32 %7, %7, %8"
+#define WLCS_FUSED_SLOT2_OPS                                                                        \
+    : "+v"(pa), "+v"(pb), "+v"(pt), "=&v"(pmx), "=&v"(pd), "=&v"(pz), "+v"(qa), "+v"(qb), "+v"(qt), \
+      "=&v"(qmx), "=&v"(qd), "=&v"(qz)                                                               \
+    : "v"(pc), "v"(px), "s"(py), "v"(qc), "v"(qx), "s"(qy)
+// (the two passes are one slot apart, so their x halves always differ)
+template <int HP>
+__device__ __forceinline__ void fused_slot2(uint32_t& pa, uint32_t& pb, uint32_t& pt, uint32_t& pc, uint32_t px,
+                                            uint32_t py, uint32_t& qa, uint32_t& qb, uint32_t& qt, uint32_t& qc,
+                                            uint32_t qx, uint32_t qy) {
+    uint32_t pmx, pd, pz, qmx, qd, qz;
+    if (HP)
+        asm volatile(WLCS_FUSED_SLOT2_BODY("op_sel:[1,0]", "op_sel_hi:[0,1]") WLCS_FUSED_SLOT2_OPS);
+    else
+        asm volatile(WLCS_FUSED_SLOT2_BODY("op_sel_hi:[0,1]", "op_sel:[1,0]") WLCS_FUSED_SLOT2_OPS);
+    pc = pmx;
+    qc = qmx;
+}
+#undef WLCS_FUSED_SLOT2_BODY
+#undef WLCS_FUSED_SLOT2_OPS
 
 // One cell of the plain LCS dynamic program for two windows at once:
 //     z = x_code (half HI of x, both lanes) + y_codes    (0 iff the letters match)

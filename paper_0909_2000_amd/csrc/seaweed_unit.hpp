@@ -109,13 +109,18 @@ __device__ __forceinline__ void strided_flush(uint8_t* __restrict__ out, uint16_
 // every letter (WS = 2; Section 2's reduction of the alignment score).  Rows
 // alternate separator, letter, separator, ...; so do the columns (tile starts
 // are even).  In a separator column every separator row matches and every
-// letter row mismatches, so taken bottom-up the pair (2r, 2r + 1) sends the
-// larger label to row 2r + 2 (or out of the strip) and keeps the smaller one,
-// and the new top seaweed enters row 0: one max and one min per pair.  In a
-// letter column the separator row is a mismatch (min/max) and the letter row
-// the general cell.  The strip has WC / 2 pair slots; a window of w / 2 < WC / 2
-// pairs leaves the top WC / 2 - w / 2 (< 16) slots unused, skipped by uniform
-// branches on the first 16 slots only.
+// letter row mismatches, so the pair of rows (2r, 2r + 1) sends the larger of
+// its two labels down to row 2r + 2 (or out of the strip) and keeps the
+// smaller one, and the new top seaweed enters row 0: one max and one min per
+// pair, with no chain down the column.  In a letter column the separator row
+// is a mismatch (min/max) and the letter row the general cell.  One top-down
+// pass combs a separator column and the letter column after it together: at
+// each pair slot the separator column's max is carried to the next slot
+// instead of being written there (fused_slot).  Two passes run at once, one
+// slot apart, so that two independent chains share the instruction stream.
+// The strip has WC / 2 pair slots; a window of w / 2 < WC / 2 pairs leaves the
+// top WC / 2 - w / 2 (< 16) slots unused, skipped by uniform branches on the
+// first 16 slots only.
 template <int WC, bool EXACT, int WS = 1, bool SP = false, bool DL = false>
 __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32,
                                           uint8_t* __restrict__ out, uint32_t* __restrict__ bm32,
@@ -199,44 +204,12 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         return __builtin_amdgcn_readfirstlane(((a >> sh) & 0xFFFFu) | (((b >> sh) & 0xFFFFu) << 16));
     };
     const uint32_t one2 = 0x00010001u;
-    uint32_t ynext = yload(0);
+    uint32_t ynext = DL ? 0u : yload(0);
 
-    // Comb column l (tile-relative) through the w rows and update the sliding
-    // count; returns w - count for the window starting at l - w + 1.  par is
-    // the parity of l (DL: 0 = separator column, 1 = letter column).
-    auto column = [&](int l, auto par) -> uint32_t {
-        const uint32_t Y = ynext;
-        ynext = yload(l + 1);
-        const uint32_t top = pk_rep(l - org + 1);
-        uint32_t t = top;
-        if constexpr (!DL) {
-            t = seaweed_cell_top(h[0], top, xc[0], Y);
-#pragma unroll
-            for (int k = 1; k < WC; ++k) {
-                if (!EXACT && (k & 15) == 0 && k >= wpad) break;  // uniform, once per 16 rows
-                t = (k & 1) ? seaweed_cell<1>(h[k], t, xc[k >> 1], Y) : seaweed_cell<0>(h[k], t, xc[k >> 1], Y);
-            }
-        } else if constexpr (decltype(par)::value == 0) {  // separator column, bottom-up
-#pragma unroll
-            for (int r = NP - 1; r >= 0; --r) {
-                if (r >= 16 || r >= ppad) {  // uniform (always true from slot 16 on)
-                    const uint32_t hi = pk_sort2(h[2 * r + 1], h[2 * r]);
-                    if (r == NP - 1) t = hi;
-                    else h[2 * r + 2] = hi;
-                } else if (r == ppad - 1) {
-                    h[2 * r + 2] = top;  // the first used slot's separator row
-                }
-            }
-            if (ppad == 0) h[0] = top;
-        } else {  // letter column, top-down
-#pragma unroll
-            for (int r = 0; r < NP; ++r) {
-                if (r < 16 && r < ppad) continue;  // uniform
-                const uint32_t d = pk_sort2(h[2 * r], t);  // separator row: a mismatch
-                t = (r & 1) ? seaweed_cell<1>(h[2 * r + 1], d, xc[r >> 1], Y)
-                            : seaweed_cell<0>(h[2 * r + 1], d, xc[r >> 1], Y);
-            }
-        }
+    // The sliding count after column l (tile-relative), from the packed label
+    // t leaving its bottom; returns w - count for the window starting at
+    // l - w + 1.
+    auto count = [&](int l, uint32_t t) -> uint32_t {
         // consume the mark of start column l - w (prefetched after the
         // previous column's marks were set)
         uint32_t f2 = 0;
@@ -259,18 +232,92 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         return rem2;
     };
 
-    using P0 = std::integral_constant<int, 0>;
-    using P1 = std::integral_constant<int, 1>;
-    // warm-up columns: no window is complete yet (DL: w is even, so the w - 1
-    // warm-up columns end on a separator column)
-    if constexpr (DL) {
-        for (int l = 0; l + 1 < w - 1; l += 2) {
-            (void)column(l, P0{});
-            (void)column(l + 1, P1{});
+    // Comb column l (tile-relative) through the w rows; returns the count
+    // (general schedule).
+    auto column = [&](int l) -> uint32_t {
+        const uint32_t Y = ynext;
+        ynext = yload(l + 1);
+        uint32_t t = seaweed_cell_top(h[0], pk_rep(l - org + 1), xc[0], Y);
+#pragma unroll
+        for (int k = 1; k < WC; ++k) {
+            if (!EXACT && (k & 15) == 0 && k >= wpad) break;  // uniform, once per 16 rows
+            t = (k & 1) ? seaweed_cell<1>(h[k], t, xc[k >> 1], Y) : seaweed_cell<0>(h[k], t, xc[k >> 1], Y);
         }
-        (void)column(w - 2, P0{});
+        return count(l, t);
+    };
+
+    // DL: a pass down the pair slots combs the separator column c - 1 and
+    // the letter column c (c odd) together; two passes (c and c + 2) run at
+    // once, the second one slot behind the first, which leaves every slot of
+    // the first pass done before the second reads it.  The y codes of the
+    // letter columns are loaded one call ahead.  Returns the counts after
+    // columns c, c + 1 and c + 2 (the last two of a pair of passes only).
+    uint32_t yq0 = 0, yq1 = 0;
+    if constexpr (DL) {
+        yq0 = yload(1);
+        yq1 = yload(3);
+    }
+    struct Counts { uint32_t c0, c1, c2; };
+    auto passes = [&](int c, auto two_t) -> Counts {
+        constexpr bool TWO = decltype(two_t)::value;
+        const uint32_t YP = yq0, YQ = yq1;
+        if (TWO) {
+            yq0 = yload(c + 4);
+            yq1 = yload(c + 6);
+        } else {
+            yq0 = yq1;
+            yq1 = yload(c + 4);
+        }
+        uint32_t pcar = pk_rep(c - org), pt = pk_rep(c + 1 - org);
+        uint32_t qcar = pk_rep(c + 2 - org), qt = pk_rep(c + 3 - org);
+        // step k: pass P at slot k, pass Q at slot k - 1
+        auto step = [&](int k, bool p_on, bool q_on) {
+            const int kp = k < NP ? k : NP - 1, kq = k >= 1 ? k - 1 : 0;
+            if (p_on && q_on) {
+                if (k & 1)
+                    fused_slot2<1>(h[2 * kp], h[2 * kp + 1], pt, pcar, xc[kp >> 1], YP, h[2 * kq], h[2 * kq + 1],
+                                   qt, qcar, xc[kq >> 1], YQ);
+                else
+                    fused_slot2<0>(h[2 * kp], h[2 * kp + 1], pt, pcar, xc[kp >> 1], YP, h[2 * kq], h[2 * kq + 1],
+                                   qt, qcar, xc[kq >> 1], YQ);
+            } else if (p_on) {
+                pcar = (k & 1) ? fused_slot<1>(h[2 * kp], h[2 * kp + 1], pt, pcar, xc[kp >> 1], YP)
+                               : fused_slot<0>(h[2 * kp], h[2 * kp + 1], pt, pcar, xc[kp >> 1], YP);
+            } else if (q_on) {
+                qcar = (kq & 1) ? fused_slot<1>(h[2 * kq], h[2 * kq + 1], qt, qcar, xc[kq >> 1], YQ)
+                                : fused_slot<0>(h[2 * kq], h[2 * kq + 1], qt, qcar, xc[kq >> 1], YQ);
+            }
+        };
+        // steps 0 .. 16 may meet unused slots (uniform tests); the rest may not
+#pragma unroll
+        for (int k = 0; k <= 16; ++k)
+            step(k, k < NP && k >= ppad, TWO && k >= 1 && k - 1 >= ppad && k - 1 < NP);
+#pragma unroll
+        for (int k = 17; k < NP; ++k) step(k, true, TWO);
+        if (NP > 16) step(NP, false, TWO);
+        (void)count(c - 1, pcar);
+        Counts r;
+        r.c0 = count(c, pt);
+        if (TWO) {
+            r.c1 = count(c + 1, qcar);
+            r.c2 = count(c + 2, qt);
+        } else {
+            r.c1 = r.c2 = r.c0;
+        }
+        return r;
+    };
+
+    using P0 = std::integral_constant<bool, false>;
+    using P1 = std::integral_constant<bool, true>;
+    // warm-up columns: no window is complete yet (DL: w is even, so the
+    // w - 1 warm-up columns 0 .. w - 2 end on a separator column, which the
+    // first pass of the main loop combs)
+    if constexpr (DL) {
+        int c = 1;
+        for (; c + 2 <= w - 3; c += 4) (void)passes(c, P1{});
+        if (c <= w - 3) (void)passes(c, P0{});
     } else {
-        for (int l = 0; l < w - 1; ++l) (void)column(l, P0{});
+        for (int l = 0; l < w - 1; ++l) (void)column(l);
     }
 
     const uint32_t bm_words = (uint32_t)(((g.ocols + 63) >> 6) * 2);
@@ -286,10 +333,20 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                 org = norg;
             }
             const int l = jj + w - 1;  // DL: odd (w even, jj a multiple of 4)
-            const uint32_t r0 = column(l, P1{});
-            const uint32_t r1 = column(l + 1, P0{});
-            const uint32_t r2 = column(l + 2, P1{});
-            const uint32_t r3 = column(l + 3, P0{});
+            uint32_t r0, r1, r2, r3;
+            if constexpr (DL) {
+                // columns l - 1 .. l + 2; the window after column l + 3
+                // (odd, never stored) takes r2's place
+                const Counts r = passes(l, P1{});
+                r0 = r.c0;
+                r1 = r.c1;
+                r2 = r3 = r.c2;
+            } else {
+                r0 = column(l);
+                r1 = column(l + 1);
+                r2 = column(l + 2);
+                r3 = column(l + 3);
+            }
             // bytes 0 (tile A) and 2 (tile B) of the four results, gathered
             // into one dword per tile: r0.b0 r0.b2 r1.b0 r1.b2, then the same
             // for r2, r3, then the even and the odd bytes of the two

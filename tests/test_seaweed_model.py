@@ -323,6 +323,78 @@ def comb_blown_up(letters, yl, cap):
     return exits
 
 
+def fused_pass(h, code, pad, cap, c, yl_c):
+    """One top-down pass through the pair slots combing the separator column
+    c - 1 and the letter column c together: at slot r the separator column
+    sends max(h[2r], h[2r+1]) to row 2r + 2 (carried to slot r + 1) and keeps
+    the min in row 2r + 1, and the letter column then crosses the carried label
+    on the separator row and meets its letter on the letter row.  Returns the
+    exits of both columns."""
+    carry, out = c - 1, c
+    for r in range(pad, cap):
+        yield r
+        a, b = h[2 * r], h[2 * r + 1]
+        mx, b = max(a, b), min(a, b)
+        h[2 * r], d = min(carry, out), max(carry, out)
+        if code[r] == yl_c:
+            h[2 * r + 1], out = d, b
+        else:
+            h[2 * r + 1], out = min(b, d), max(b, d)
+        carry = mx
+    yield (carry, out)
+
+
+def comb_blown_up_fused(letters, yl, cap, interleave):
+    """The fused schedule: separator column c - 1 and letter column c in one
+    pass; with interleave, two such passes (columns c - 1, c and c + 1, c + 2)
+    advance together, the second one slot behind the first."""
+    npairs = len(letters)
+    pad = cap - npairs
+    h = [LEFT] * (2 * cap)
+    code = [None] * pad + list(letters)
+    exits = []
+    ncols = 2 * len(yl)
+    c = 1
+    while c < ncols:
+        if interleave and c + 2 < ncols:
+            A = fused_pass(h, code, pad, cap, c, yl[c // 2])
+            B = fused_pass(h, code, pad, cap, c + 2, yl[(c + 2) // 2])
+            ra = next(A)            # A enters its first slot
+            rb = None
+            while True:
+                if not isinstance(ra, tuple):
+                    ra = next(A)    # A: one slot down
+                if rb is None:
+                    rb = next(B)
+                elif not isinstance(rb, tuple):
+                    rb = next(B)    # B: one slot down, behind A
+                if isinstance(ra, tuple) and isinstance(rb, tuple):
+                    break
+            exits += [ra[0], ra[1], rb[0], rb[1]]
+            c += 4
+        else:
+            res = list(fused_pass(h, code, pad, cap, c, yl[c // 2]))[-1]
+            exits += [res[0], res[1]]
+            c += 2
+    return exits
+
+
+@pytest.mark.parametrize("interleave", [False, True])
+@pytest.mark.parametrize("cap", [16, 32])
+def test_fused_blown_up_schedule_equals_combing(cap, interleave):
+    """The fused (and the interleaved fused) score-plot schedule against plain
+    combing of the blown-up strings: the same exit for every column."""
+    g = workloads.rng(900 + cap + 7 * interleave)
+    for trial in range(60):
+        npairs = int(g.integers(cap - 15, cap + 1))
+        letters = bytes(workloads.iid(g, npairs, workloads.DNA))
+        yl = bytes(workloads.iid(g, int(g.integers(1, 14)), workloads.DNA))
+        xb = b"".join(b"$" + bytes([c]) for c in letters)
+        yb = b"".join(b"$" + bytes([c]) for c in yl)
+        plain, _ = comb(xb, yb)
+        assert comb_blown_up_fused(letters, yl, cap, interleave) == plain
+
+
 @pytest.mark.parametrize("cap", [16, 32])
 def test_blown_up_schedule_equals_combing(oracle_mod, cap):
     """The score-plot schedule against plain combing of the blown-up strings,
