@@ -63,8 +63,8 @@ int64_t n_windows(int64_t len, int32_t w, bool full) {
 // register budget; LDS allows 4 more at 8.7 KB per wave for the 32-window
 // flush and 3 at 12.8 KB for the 64-window one).
 int waves_per_simd(int wc, int ws) {
-    if (ws == 2) {  // score plots: the separator schedule, classes of 32 rows
-        const int dc = (wc + 31) / 32 * 32;
+    if (ws == 2) {  // score plots: the separator schedule, classes of 8 rows
+        const int dc = (wc + 7) / 8 * 8;
         return dc <= 64 ? 3 : dc <= 128 ? 2 : 1;
     }
     const int regs = wc <= 32 ? 4 : wc == 64 ? 3 : wc == 128 ? 2 : 1;

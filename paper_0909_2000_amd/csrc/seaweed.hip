@@ -94,7 +94,7 @@ void launch_ws(const PlotArgs& a, const Geom& g, uint32_t units, hipStream_t str
 }
 
 // score plots: the separator schedule in the class of the window rounded up
-// to 32 rows
+// to 2 * kDlSlots rows
 template <int WC>
 hipError_t launch_dl(const PlotArgs& a, hipStream_t stream) {
     const int64_t nblocks = (a.rows + 63) / 64;
@@ -105,6 +105,17 @@ hipError_t launch_dl(const PlotArgs& a, hipStream_t stream) {
     hipLaunchKernelGGL((seaweed_kernel<WC, false, 2, false, true>), dim3((uint32_t)units), dim3(64), 0, stream,
                        a.xf, (const uint32_t*)a.yg, a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
     return hipGetLastError();
+}
+
+// the class wc (a multiple of 2 * kDlSlots up to 256) picks its kernel
+template <int WC>
+hipError_t dispatch_dl(const PlotArgs& a, int wc, hipStream_t stream) {
+    if constexpr (WC >= 256) {
+        return launch_dl<256>(a, stream);
+    } else {
+        if (wc <= WC) return launch_dl<WC>(a, stream);
+        return dispatch_dl<WC + 2 * kDlSlots>(a, wc, stream);
+    }
 }
 
 template <int WC>
@@ -131,16 +142,7 @@ hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream) {
 hipError_t launch_seaweed(const PlotArgs& a, hipStream_t stream) {
     if (a.ws == 2) {  // blown-up strings: even window, separator rows and columns
         if (a.w % 2 || a.w < 2 || a.w > 256) return hipErrorInvalidValue;
-        switch ((a.w + 31) / 32) {
-            case 1: return launch_dl<32>(a, stream);
-            case 2: return launch_dl<64>(a, stream);
-            case 3: return launch_dl<96>(a, stream);
-            case 4: return launch_dl<128>(a, stream);
-            case 5: return launch_dl<160>(a, stream);
-            case 6: return launch_dl<192>(a, stream);
-            case 7: return launch_dl<224>(a, stream);
-            default: return launch_dl<256>(a, stream);
-        }
+        return dispatch_dl<2 * kDlSlots>(a, (a.w + 2 * kDlSlots - 1) / (2 * kDlSlots) * (2 * kDlSlots), stream);
     }
     switch (w_class(a.w)) {
         case 16: return launch_wc<16>(a, stream);

@@ -36,6 +36,9 @@ constexpr int min_waves_per_simd(int wc) { return wc <= 32 ? 4 : wc <= 64 ? 3 : 
 // The same for the score-plot schedule (DL), whose strip of wc rows keeps
 // codes for its wc / 2 letter rows only (wc / 4 registers).
 constexpr int min_waves_per_simd_dl(int wc) { return wc <= 64 ? 3 : wc <= 128 ? 2 : 1; }
+// Score-plot classes come in steps of this many pair slots (2 rows each), so a
+// window leaves fewer than kDlSlots slots of its class unused.
+constexpr int kDlSlots = 4;
 
 // Stores of a strided or sparse plot for one flushed block: window j0 + b of
 // strip s0 + r sits in byte b of row r of the staged block (stride pitch
@@ -119,8 +122,7 @@ __device__ __forceinline__ void strided_flush(uint8_t* __restrict__ out, uint16_
 // instead of being written there (fused_slot).  Two passes run at once, one
 // slot apart, so that two independent chains share the instruction stream.
 // The strip has WC / 2 pair slots; a window of w / 2 < WC / 2 pairs leaves the
-// top WC / 2 - w / 2 (< 16) slots unused, skipped by uniform branches on the
-// first 16 slots only.
+// top WC / 2 - w / 2 (< kDlSlots) slots unused.
 template <int WC, bool EXACT, int WS = 1, bool SP = false, bool DL = false>
 __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32,
                                           uint8_t* __restrict__ out, uint32_t* __restrict__ bm32,
@@ -128,7 +130,7 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                                           unsigned long long* __restrict__ dot_count, const Geom& g, int64_t sb,
                                           int pr, uint32_t* __restrict__ ring, uint32_t* __restrict__ stage) {
     static_assert(!SP || WS == 1, "strided and sparse plots store single windows");
-    static_assert(!DL || (WS == 2 && !EXACT && WC % 32 == 0), "the score-plot schedule");
+    static_assert(!DL || (WS == 2 && !EXACT && WC % (2 * kDlSlots) == 0), "the score-plot schedule");
     constexpr int RW = ring_words(WC);
     constexpr int FL = flush_windows(WC, WS);
     constexpr int PITCH = stage_pitch(WC, WS);
@@ -150,7 +152,7 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     const int pad = (EXACT || DL) ? 0 : ((w + 15) & ~15) - w;
     const int wpad = (EXACT || DL) ? WC : w + pad;
     constexpr int NP = WC / 2;                 // DL: pair slots
-    const int ppad = DL ? NP - w / 2 : 0;      // DL: unused slots at the top
+    const int ppad = DL ? NP - w / 2 : 0;      // DL: unused slots at the top (< kDlSlots)
     // x letters of this lane's strip, two rows per register (lanes past the
     // last strip comb a copy of the last one; their results are never stored);
     // DL: the letters of the letter rows only, two slots per register
@@ -270,31 +272,35 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         }
         uint32_t pcar = pk_rep(c - org), pt = pk_rep(c + 1 - org);
         uint32_t qcar = pk_rep(c + 2 - org), qt = pk_rep(c + 3 - org);
+        // The unused top slots (their letter is the pad code, which matches
+        // nothing) run the same steps: the letter column's label, the largest
+        // of all, passes through them unchanged, and after each of them the
+        // separator column's carry is raised to its own top label (larger
+        // than every label the slot holds), so that both columns enter the
+        // first used slot with their top labels.
+        const uint32_t sP = pcar, sQ = qcar;
         // step k: pass P at slot k, pass Q at slot k - 1
-        auto step = [&](int k, bool p_on, bool q_on) {
+        auto step = [&](int k, bool q_on) {
             const int kp = k < NP ? k : NP - 1, kq = k >= 1 ? k - 1 : 0;
-            if (p_on && q_on) {
+            if (k < NP && q_on) {
                 if (k & 1)
                     fused_slot2<1>(h[2 * kp], h[2 * kp + 1], pt, pcar, xc[kp >> 1], YP, h[2 * kq], h[2 * kq + 1],
                                    qt, qcar, xc[kq >> 1], YQ);
                 else
                     fused_slot2<0>(h[2 * kp], h[2 * kp + 1], pt, pcar, xc[kp >> 1], YP, h[2 * kq], h[2 * kq + 1],
                                    qt, qcar, xc[kq >> 1], YQ);
-            } else if (p_on) {
+            } else if (k < NP) {
                 pcar = (k & 1) ? fused_slot<1>(h[2 * kp], h[2 * kp + 1], pt, pcar, xc[kp >> 1], YP)
                                : fused_slot<0>(h[2 * kp], h[2 * kp + 1], pt, pcar, xc[kp >> 1], YP);
             } else if (q_on) {
                 qcar = (kq & 1) ? fused_slot<1>(h[2 * kq], h[2 * kq + 1], qt, qcar, xc[kq >> 1], YQ)
                                 : fused_slot<0>(h[2 * kq], h[2 * kq + 1], qt, qcar, xc[kq >> 1], YQ);
             }
+            if (k < kDlSlots && k < NP) pcar = pk_max(pcar, k < ppad ? sP : 0u);
+            if (q_on && kq < kDlSlots) qcar = pk_max(qcar, kq < ppad ? sQ : 0u);
         };
-        // steps 0 .. 16 may meet unused slots (uniform tests); the rest may not
 #pragma unroll
-        for (int k = 0; k <= 16; ++k)
-            step(k, k < NP && k >= ppad, TWO && k >= 1 && k - 1 >= ppad && k - 1 < NP);
-#pragma unroll
-        for (int k = 17; k < NP; ++k) step(k, true, TWO);
-        if (NP > 16) step(NP, false, TWO);
+        for (int k = 0; k <= NP; ++k) step(k, TWO && k >= 1);
         (void)count(c - 1, pcar);
         Counts r;
         r.c0 = count(c, pt);

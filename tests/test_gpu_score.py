@@ -25,10 +25,13 @@ def _say(*a):
     sys.stdout.flush()
 
 
-# windows across every 32-row class of the blown-up strip (2w rows) and
-# every count of unused top pairs from 0 to 15
+# windows across the classes of the blown-up strip (2w rows, classes of 8
+# rows = 4 pair slots, up to 256 rows), every count of unused top pairs from 0
+# to 3 in small and large classes, and the register-budget boundaries (64 and
+# 128 rows)
 CASES = ([(w, step) for w in (1, 2, 5, 8, 16, 31, 32, 50, 64, 100, 127) for step in (1, 5)] + [(7, 3), (64, 2)]
-         + [(w, 1) for w in (17, 33, 40, 48, 49, 65, 70, 80, 81, 90, 96, 97, 112, 113)])
+         + [(w, 1) for w in (3, 4, 6, 9, 10, 11, 17, 33, 40, 48, 49, 65, 70, 80, 81, 90, 96, 97, 99, 101, 102,
+                             112, 113, 125, 126)])
 
 
 @pytest.mark.parametrize("w,step", CASES)
@@ -94,7 +97,7 @@ def test_paper_shaped_score_plot_sampled(ctx, oracle_mod):
     assert int(d.max()) <= w and int(d.min()) >= -w
 
 
-@pytest.mark.parametrize("w,tile", [(12, 64), (40, 128), (100, 576)])
+@pytest.mark.parametrize("w,tile", [(12, 64), (40, 128), (100, 576), (99, 320), (126, 1024)])
 def test_score_across_tiles_and_relabelling(ctx, oracle_mod, w, tile):
     """Long rows (many tiles, the ragged last pair, label rebases every 512
     windows of the blown-up strings) against the oracle on sampled rows."""

@@ -328,10 +328,16 @@ def fused_pass(h, code, pad, cap, c, yl_c):
     c - 1 and the letter column c together: at slot r the separator column
     sends max(h[2r], h[2r+1]) to row 2r + 2 (carried to slot r + 1) and keeps
     the min in row 2r + 1, and the letter column then crosses the carried label
-    on the separator row and meets its letter on the letter row.  Returns the
-    exits of both columns."""
-    carry, out = c - 1, c
-    for r in range(pad, cap):
+    on the separator row and meets its letter on the letter row.
+
+    The unused top slots (r < pad, whose letter matches nothing) run the same
+    steps: the letter column's label is the largest of all and passes through
+    them unchanged, and after each of them the separator column's carry is
+    raised to its top label (larger than anything the slot holds), so both
+    columns enter slot pad with their own top labels.  Returns the exits."""
+    top = c - 1
+    carry, out = top, c
+    for r in range(cap):
         yield r
         a, b = h[2 * r], h[2 * r + 1]
         mx, b = max(a, b), min(a, b)
@@ -340,7 +346,7 @@ def fused_pass(h, code, pad, cap, c, yl_c):
             h[2 * r + 1], out = d, b
         else:
             h[2 * r + 1], out = min(b, d), max(b, d)
-        carry = mx
+        carry = max(mx, top) if r < pad else mx
     yield (carry, out)
 
 
