@@ -82,6 +82,18 @@ const char *wlcs_status_str(int status);
  * w_lo <= w <= w_hi. */
 int wlcs_ctx_set_tile(wlcs_ctx *ctx, int32_t w_lo, int32_t w_hi, int32_t tile_windows);
 
+/* Two tile lengths (the built-in choice uses two as well): in every block of
+ * 64 x-windows the first long_pairs tile pairs (at most as many as fit in the
+ * row) have tiles of long_tile windows, the later ones tiles of short_tile;
+ * the last pair's remaining windows are split evenly between its two tiles.
+ * Long tiles comb fewer columns before their first complete window, short
+ * ones shorten the tail of a launch.  Both lengths as for wlcs_ctx_set_tile;
+ * long_pairs >= 0; long_tile = 0 drops the rules covering [w_lo, w_hi].
+ * Applies to single plots (wlcs_plot, wlcs_pair_plot, their strided forms,
+ * wlcs_score_plot, and batch jobs with w > 128). */
+int wlcs_ctx_set_tiles(wlcs_ctx *ctx, int32_t w_lo, int32_t w_hi, int32_t long_tile, int32_t short_tile,
+                       int32_t long_pairs);
+
 /* Alignment plot by the windowed seaweed algorithm (Theorem 3.1, with the
  * combing rule of Section 2 and the bit bounds of Propositions 3.3-3.4).
  *

@@ -82,6 +82,7 @@ def _load():
     lib.wlcs_status_str.argtypes = [ctypes.c_int]
     lib.wlcs_status_str.restype = ctypes.c_char_p
     lib.wlcs_ctx_set_tile.argtypes = [vp, i32, i32, i32]
+    lib.wlcs_ctx_set_tiles.argtypes = [vp, i32, i32, i32, i32, i32]
     plot_args = [vp, u8p, i64, u8p, i64, i32, u8p, i32, vp, i64, vp, i64, i32, vp, i64, u32, vp]
     lib.wlcs_plot.argtypes = plot_args
     lib.wlcs_plot_dp.argtypes = plot_args
@@ -106,7 +107,7 @@ def _load():
     strided_args = [vp, vp, i32, i32, i32, vp, i64, vp, i64, i32, vp, i64, vp, i64, vp, ctypes.c_uint32, vp]
     lib.wlcs_pair_plot_strided.argtypes = strided_args
     lib.wlcs_pair_plot_dp_strided.argtypes = strided_args
-    for f in ("wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_ctx_set_tile",
+    for f in ("wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_ctx_set_tile", "wlcs_ctx_set_tiles",
               "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot",
               "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
               "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
@@ -121,8 +122,8 @@ def _load():
 def exported_symbols() -> list:
     """Names of the C ABI entry points the binding uses."""
     return ["wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_status_str",
-            "wlcs_ctx_set_tile", "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy",
-            "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
+            "wlcs_ctx_set_tile", "wlcs_ctx_set_tiles", "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create",
+            "wlcs_pair_destroy", "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
             "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
             "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
             "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs", "wlcs_pair_plot_blcs"]
@@ -195,6 +196,13 @@ class Context:
         st = _load().wlcs_ctx_set_tile(self._h, w_lo, w_hi, tile)
         if st != 0:
             raise WlcsError(st, "wlcs_ctx_set_tile")
+
+    def set_tiles(self, w_lo: int, w_hi: int, long_tile: int, short_tile: int, long_pairs: int):
+        """wlcs_ctx_set_tiles: long tiles for the first long_pairs tile pairs
+        of every strip block, short tiles after them."""
+        st = _load().wlcs_ctx_set_tiles(self._h, w_lo, w_hi, long_tile, short_tile, long_pairs)
+        if st != 0:
+            raise WlcsError(st, "wlcs_ctx_set_tiles")
 
     def _outputs(self, rows, cols, threshold, indel, out, bitmap_out, indel_out, want_plot):
         dev = torch.device("cuda", self.device)

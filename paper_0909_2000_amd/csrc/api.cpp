@@ -72,37 +72,138 @@ int waves_per_simd(int wc, int ws) {
     return std::min(regs, lds);
 }
 
-// Tile length for the seaweed kernel.  A unit (64 strips, two tiles) combs
-// min(T, rest) + w - 1 columns; units are handed out to the SIMDs as they free
-// up.  The estimate is the combing work per SIMD plus a tail of one unit that
-// shrinks with the number of waves sharing a SIMD; the tile with the lowest
-// estimate wins (the longer one on ties).  A context rule set by
-// wlcs_ctx_set_tile overrides it.
-int32_t choose_tile(const wlcs_ctx* ctx, int64_t rows, int64_t cols, int32_t w, int ws = 1) {
-    for (int r = ctx->nrules - 1; r >= 0; --r)
-        if (w >= ctx->rules[r].lo && w <= ctx->rules[r].hi) return ctx->rules[r].tile;
-    static const int32_t cand[] = {64, 128, 192, 256, 384, 512, 768, 1024, 1280, 1536, 2048, 2560, 3072, 4096, 6144, 8192, 12288, 16384};
-    const int64_t nblocks = (rows + 63) / 64;
-    const double simds = 4.0 * ctx->cus;
-    const double tail = 2.0 / waves_per_simd(ws == 2 ? w : wlcs::w_class(w), ws);
-    const int64_t cap = std::max<int64_t>(64, (cols + 63) / 64 * 64);
-    int32_t best = 64;
-    double best_cost = 1e300;
-    for (int32_t t : cand) {
-        if (t > cap && t > 64) break;
-        const int64_t ntiles = (cols + t - 1) / t;
-        const int64_t npairs = (ntiles + 1) / 2;
-        const int64_t last = wlcs::pair_tile(cols, t, npairs - 1);  // the last pair's (split) tiles
-        const double full = (double)(t + w - 1), part = (double)(last + w - 1);
-        const double work = (double)nblocks * ((double)(npairs - 1) * full + part);
-        const double cost = work / simds + tail * full;
-        if (cost <= best_cost) {
-            best_cost = cost;
-            best = t;
+// Tile pairs of a row of cols windows with long tiles of `tile` windows for
+// at most nbig_max leading pairs (never past the row's end) and tiles of tile2
+// after them.
+void set_tiles(wlcs::PlotArgs& a, int64_t cols, int32_t tile, int32_t tile2, int64_t nbig_max) {
+    const int64_t nbig = tile2 == tile ? 0 : std::max<int64_t>(0, std::min<int64_t>(nbig_max, cols / (2 * (int64_t)tile)));
+    const int64_t rest = cols - 2 * nbig * tile;
+    a.tile = tile;
+    a.tile2 = tile2;
+    a.nbig = (int32_t)nbig;
+    a.npairs = (int32_t)(nbig + (rest + 2 * (int64_t)tile2 - 1) / (2 * (int64_t)tile2));
+}
+
+// Greedy list scheduling of units over `slots` equal slots, in launch order:
+// each unit starts on the slot that frees first.  The slots are kept as levels
+// (free time, number of slots); k units of d columns each are placed level by
+// level, a whole level at a time.
+struct SlotLevels {
+    std::vector<std::pair<int64_t, int64_t>> lv;  // ascending free time
+    explicit SlotLevels(int64_t slots) : lv{{0, slots}} {}
+    void add(int64_t t, int64_t c) {
+        if (c <= 0) return;
+        auto it = std::lower_bound(lv.begin(), lv.end(), std::make_pair(t, (int64_t)0));
+        if (it != lv.end() && it->first == t)
+            it->second += c;
+        else
+            lv.insert(it, {t, c});
+    }
+    void place(int64_t k, int64_t d) {
+        while (k > 0) {
+            const int64_t tau = lv[0].first, c = lv[0].second;
+            lv.erase(lv.begin());
+            if (lv.empty() || k < c * ((lv[0].first - tau + d - 1) / d)) {
+                // the units run out before this level reaches the next one
+                const int64_t r = k / c, q = k % c;
+                add(tau + r * d, c - q);
+                add(tau + (r + 1) * d, q);
+                return;
+            }
+            const int64_t n = (lv[0].first - tau + d - 1) / d;  // rounds until the next level
+            k -= c * n;
+            add(tau + n * d, c);
         }
     }
-    return best;
+    int64_t makespan() const { return lv.back().first; }
+};
+
+// Time (in combed columns per slot) of a plot's units under a tiling.
+int64_t tiling_makespan(const wlcs::PlotArgs& a, int64_t nblocks, int64_t cols, int32_t w, int64_t slots) {
+    SlotLevels s(slots);
+    const int64_t t2 = a.tile2 > 0 ? a.tile2 : a.tile;
+    const int64_t nbig = a.tile2 > 0 ? a.nbig : 0;
+    const int64_t n2 = a.npairs - nbig;
+    if (nbig > 0) s.place(nbig * nblocks, a.tile + w - 1);
+    if (n2 > 1) s.place((n2 - 1) * nblocks, t2 + w - 1);
+    if (n2 > 0) {
+        int64_t start;
+        const int64_t last = wlcs::pair_tile(cols, a.tile, t2, nbig, a.npairs - 1, &start);
+        s.place(nblocks, last + w - 1);
+    }
+    return s.makespan();
 }
+
+// Tiles for the seaweed kernel.  A unit (64 strips, one tile pair) combs
+// tlen + w - 1 columns; the units start in launch order on the wave slots of
+// the SIMDs as these free up.  Long tiles waste little on the w - 1 columns
+// that each tile combs before its first complete window; short ones keep the
+// launch's tail short.  So the pairs of every strip block may start with long
+// tiles and end with short ones.  Every candidate (one length, or two with a
+// few counts of long pairs) is scored by the finishing time of a greedy list
+// schedule of its units over SIMDs x resident waves equal slots; the fastest
+// wins (the longer tiles on ties).  A context rule (wlcs_ctx_set_tile or
+// wlcs_ctx_set_tiles) overrides the choice.
+// The choice for a shape is kept in a small cache of the context.
+void choose_tiles(wlcs_ctx* ctx, wlcs::PlotArgs& a, int64_t rows, int64_t cols, int32_t w, int ws = 1) {
+    for (int r = ctx->nrules - 1; r >= 0; --r) {
+        const TileRule& R = ctx->rules[r];
+        if (w >= R.lo && w <= R.hi) {
+            set_tiles(a, cols, R.tile, R.tile2 > 0 ? R.tile2 : R.tile, R.nbig);
+            return;
+        }
+    }
+    for (const wlcs_rt::TileChoice& c : ctx->tile_cache) {
+        if (c.rows == rows && c.cols == cols && c.w == w && c.ws == ws) {
+            a.tile = c.tile;
+            a.tile2 = c.tile2;
+            a.nbig = c.nbig;
+            a.npairs = c.npairs;
+            return;
+        }
+    }
+    static const int32_t cand[] = {64, 128, 192, 256, 384, 512, 768, 1024, 1280, 1536, 2048, 2560, 3072, 4096, 6144, 8192, 12288, 16384};
+    const int64_t nblocks = (rows + 63) / 64;
+    const int64_t slots = 4 * (int64_t)ctx->cus * waves_per_simd(ws == 2 ? w : wlcs::w_class(w), ws);
+    const int64_t cap = std::max<int64_t>(64, (cols + 63) / 64 * 64);
+    int64_t best_t = INT64_MAX;
+    wlcs::PlotArgs best = a;
+    auto consider = [&](int32_t t, int32_t t2, int64_t nbig) {
+        wlcs::PlotArgs c = a;
+        set_tiles(c, cols, t, t2, nbig);
+        const int64_t mk = tiling_makespan(c, nblocks, cols, w, slots);
+        if (mk <= best_t) {
+            best_t = mk;
+            best = c;
+        }
+    };
+    for (int32_t t : cand) {
+        if (t > cap && t > 64) break;
+        consider(t, t, 0);
+        const int64_t nb_max = cols / (2 * (int64_t)t);
+        for (int32_t t2 : cand) {
+            if (t2 >= t) break;
+            for (int64_t nb = std::max<int64_t>(1, nb_max - 7); nb <= nb_max; ++nb) consider(t, t2, nb);
+        }
+    }
+    a.tile = best.tile;
+    a.tile2 = best.tile2;
+    a.nbig = best.nbig;
+    a.npairs = best.npairs;
+    wlcs_rt::TileChoice& slot = ctx->tile_cache[ctx->tile_cache_next];
+    ctx->tile_cache_next = (ctx->tile_cache_next + 1) % wlcs_rt::kTileCache;
+    slot.rows = rows;
+    slot.cols = cols;
+    slot.w = w;
+    slot.ws = ws;
+    slot.tile = a.tile;
+    slot.tile2 = a.tile2;
+    slot.nbig = a.nbig;
+    slot.npairs = a.npairs;
+}
+
+// One tile length (the DP and BLCS paths, the batched kernel).
+void uniform_tiles(wlcs::PlotArgs& a, int64_t cols, int32_t tile) { set_tiles(a, cols, tile, tile, 0); }
 
 struct Prepared {
     int64_t rows = 0, cols = 0;
@@ -205,16 +306,17 @@ void release(Prepared& p, hipStream_t stream) {
 enum class Path { Seaweed, Dp, Blcs };
 
 // Code-array lengths (16-bit elements) the kernels read for a plot: x is read
-// up to 64 strips past the last block plus a window, y up to two tiles past
-// the last one (seaweed) or one 128-window chunk (DP), plus a window.
-void needed_lengths(Path path, int64_t rows, int64_t cols, int32_t w, int32_t tile, int64_t& xf_len,
+// up to 64 strips past the last block plus a window, y up to the end of the
+// last tile pair (seaweed) or one 128-window chunk (DP) past the last window,
+// plus a window.
+void needed_lengths(Path path, int64_t rows, int64_t cols, int32_t w, const wlcs::PlotArgs& a, int64_t& xf_len,
                     int64_t& yg_len) {
     const int wc = wlcs::w_class(w);
     xf_len = (rows + 63) / 64 * 64 + wc + 64;
     if (path == Path::Seaweed) {
-        const int64_t ntiles = (cols + tile - 1) / tile;
-        const int64_t npairs = (ntiles + 1) / 2;
-        yg_len = 2 * npairs * tile + wc + 64;
+        const int64_t t2 = a.tile2 > 0 ? a.tile2 : a.tile;
+        const int64_t nbig = a.tile2 > 0 ? a.nbig : 0;
+        yg_len = 2 * nbig * a.tile + 2 * (a.npairs - nbig) * t2 + wc + 64;
     } else {
         yg_len = (cols + 127) / 128 * 128 + wc + 64;
     }
@@ -277,10 +379,12 @@ int plot_common(Path path, wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uin
     hipStream_t stream = (hipStream_t)stream_;
 
     wlcs::PlotArgs a = make_args(rows, cols, w, out, ld, bitmap, ld_words, threshold, indel, ld_indel);
-    a.tile = path == Path::Seaweed ? choose_tile(ctx, rows, cols, w) : 64;
-    a.npairs = (int32_t)(((cols + a.tile - 1) / a.tile + 1) / 2);
+    if (path == Path::Seaweed)
+        choose_tiles(ctx, a, rows, cols, w);
+    else
+        uniform_tiles(a, cols, 64);
     int64_t xf_len, yg_len;
-    needed_lengths(path, rows, cols, w, a.tile, xf_len, yg_len);
+    needed_lengths(path, rows, cols, w, a, xf_len, yg_len);
     Prepared p;
     st = upload(ctx, x, m, y, n, map, xf_len, yg_len, stream, p);
     if (st != WLCS_OK) {
@@ -328,10 +432,12 @@ int pair_plot_common(Path path, wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w,
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
     wlcs::PlotArgs a = make_args(rows, cols, w, out, ld, bitmap, ld_words, threshold, indel, ld_indel);
-    a.tile = path == Path::Seaweed ? choose_tile(ctx, rows, cols, w) : 64;
-    a.npairs = (int32_t)(((cols + a.tile - 1) / a.tile + 1) / 2);
+    if (path == Path::Seaweed)
+        choose_tiles(ctx, a, rows, cols, w);
+    else
+        uniform_tiles(a, cols, 64);
     int64_t xf_len, yg_len;
-    needed_lengths(path, rows, cols, w, a.tile, xf_len, yg_len);
+    needed_lengths(path, rows, cols, w, a, xf_len, yg_len);
     if (xf_len > pair->xf_cap || yg_len > pair->yg_cap) return WLCS_EINVAL;  // cannot happen for valid tiles
     a.xf = pair->xf;
     a.yg = pair->yg;
@@ -382,10 +488,12 @@ int strided_common(Path path, wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, i
     a.dot_count = (unsigned long long*)dot_count;
     // strips past the last window read a copy of the last one, so the x codes
     // read stay below m + the window class; y as for an unstrided plot
-    a.tile = path == Path::Seaweed ? choose_tile(ctx, rows, a.cols, w) : 64;
-    a.npairs = (int32_t)(((a.cols + a.tile - 1) / a.tile + 1) / 2);
+    if (path == Path::Seaweed)
+        choose_tiles(ctx, a, rows, a.cols, w);
+    else
+        uniform_tiles(a, a.cols, 64);
     int64_t xf_len, yg_len;
-    needed_lengths(path, 1, path == Path::Seaweed ? a.cols : cols_all, w, a.tile, xf_len, yg_len);
+    needed_lengths(path, 1, path == Path::Seaweed ? a.cols : cols_all, w, a, xf_len, yg_len);
     if (pair->m + wlcs::w_class(w) > pair->xf_cap || yg_len > pair->yg_cap) return WLCS_EINVAL;
     a.xf = pair->xf;
     a.yg = pair->yg;
@@ -466,15 +574,13 @@ int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& pl
         a.dot_cap = j.dots ? j.dot_cap : 0;
         a.dot_count = (unsigned long long*)j.dot_count;
         if (j.w > wlcs::kBatchMaxW) {
-            a.tile = choose_tile(ctx, rows, cols, j.w);
-            a.npairs = (int32_t)(((cols + a.tile - 1) / a.tile + 1) / 2);
+            choose_tiles(ctx, a, rows, cols, j.w);
             plan.singles.push_back(a);
             continue;
         }
-        a.tile = batch_tile(ctx, cols, j.w);
-        a.npairs = (int32_t)(((cols + a.tile - 1) / a.tile + 1) / 2);
+        uniform_tiles(a, cols, batch_tile(ctx, cols, j.w));
         int64_t xf_len, yg_len;
-        needed_lengths(Path::Seaweed, rows, cols, j.w, a.tile, xf_len, yg_len);
+        needed_lengths(Path::Seaweed, rows, cols, j.w, a, xf_len, yg_len);
         if (xf_len > j.pair->xf_cap || yg_len > j.pair->yg_cap) return WLCS_EINVAL;
         Item it;
         it.d.xf = a.xf;
@@ -592,7 +698,16 @@ int wlcs_ctx_set_tile(wlcs_ctx* ctx, int32_t w_lo, int32_t w_hi, int32_t tile_wi
         return WLCS_OK;
     }
     if (tile_windows < 64 || tile_windows > 32768 || tile_windows % 64) return WLCS_EINVAL;
-    return add_rule(ctx->rules, ctx->nrules, TileRule{w_lo, w_hi, tile_windows});
+    return add_rule(ctx->rules, ctx->nrules, TileRule{w_lo, w_hi, tile_windows, tile_windows, 0});
+}
+
+int wlcs_ctx_set_tiles(wlcs_ctx* ctx, int32_t w_lo, int32_t w_hi, int32_t long_tile, int32_t short_tile,
+                       int32_t long_pairs) {
+    if (!ctx || w_lo < 1 || w_hi < w_lo || w_hi > WLCS_MAX_W) return WLCS_EINVAL;
+    if (long_tile == 0) return wlcs_ctx_set_tile(ctx, w_lo, w_hi, 0);
+    auto bad = [](int32_t t) { return t < 64 || t > 32768 || t % 64 != 0; };
+    if (bad(long_tile) || bad(short_tile) || long_pairs < 0) return WLCS_EINVAL;
+    return add_rule(ctx->rules, ctx->nrules, TileRule{w_lo, w_hi, long_tile, short_tile, long_pairs});
 }
 
 int wlcs_plot(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, int32_t w,
@@ -649,10 +764,9 @@ int wlcs_score_plot(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y
     a.ws = 2;
     a.xstride = 2 * (int64_t)step;
     a.bias = w;
-    a.tile = choose_tile(ctx, rows, a.cols, w2, 2);
-    a.npairs = (int32_t)(((a.cols + a.tile - 1) / a.tile + 1) / 2);
+    choose_tiles(ctx, a, rows, a.cols, w2, 2);
     int64_t xf_len, yg_len;
-    needed_lengths(Path::Seaweed, rows, a.cols, w2, a.tile, xf_len, yg_len);
+    needed_lengths(Path::Seaweed, rows, a.cols, w2, a, xf_len, yg_len);
     xf_len = (rows + 63) / 64 * 64 * a.xstride + wlcs::w_class(w2) + 64;
     Prepared p;
     st = upload(ctx, x, m, y, n, map, xf_len, yg_len, stream, p, sigma);

@@ -47,8 +47,10 @@ struct PlotArgs {
     int64_t rows;            // x-windows (strips)
     int64_t cols;            // y-windows
     int32_t w;
-    int32_t tile;            // y-windows per tile, multiple of 64
+    int32_t tile;            // y-windows per tile, multiple of 64 (the long tiles)
     int32_t npairs;          // tile pairs per block of 64 strips
+    int32_t tile2 = 0;       // y-windows per tile after the first nbig pairs (0: tile)
+    int32_t nbig = 0;        // leading tile pairs of `tile` windows
     int32_t threshold;
     uint8_t* wlcs;           // may be null
     int64_t ld;
@@ -65,21 +67,28 @@ struct Geom {
     int64_t ocols;     // output columns (cols / ws: only every ws-th combed window is stored)
     int64_t xstride;   // x codes between consecutive strips (1: every x-window)
     int32_t w, tile, npairs, threshold;
+    int32_t tile2, nbig;  // pairs from nbig on have tiles of tile2 windows
     int32_t wmode;     // plot stores: 2 = 16-byte rows, 1 = 4-byte rows, 0 = bytes
     int32_t bias;      // subtracted from every stored value (0..127)
     int64_t hy;        // strided plots: output column c is the window c * hy
     int64_t dot_cap;   // dot records the sparse output holds
 };
 
-// Windows per tile in tile pair pr of a row of cols windows: the full tile,
-// except in the last pair, whose remaining windows are split evenly (in whole
-// blocks of 64) between its two tiles, so that both halves of every register
-// carry work there too.  Tile A of the pair starts at 2 * pr * tile, tile B
-// right after it.
-__host__ __device__ inline int64_t pair_tile(int64_t cols, int64_t tile, int64_t pr) {
-    const int64_t rest = cols - 2 * pr * tile;
+// Tile pairs along a row of cols windows: the first nbig pairs have tiles of
+// `tile` windows, the later ones tiles of tile2 (one length if tile2 ==
+// tile); the last pair's remaining windows are split evenly (in whole blocks
+// of 64) between its two tiles, so that both halves of every register carry
+// work there too.  Returns the windows per tile of pair pr; tile A of the pair
+// starts at *start, tile B right after it.
+__host__ __device__ inline int64_t pair_tile(int64_t cols, int64_t tile, int64_t tile2, int64_t nbig, int64_t pr,
+                                             int64_t* start) {
+    const bool big = pr < nbig;
+    const int64_t t = big ? tile : tile2;
+    const int64_t a = big ? 2 * pr * tile : 2 * nbig * tile + 2 * (pr - nbig) * tile2;
+    *start = a;
+    const int64_t rest = cols - a;
     const int64_t half = ((rest + 1) / 2 + 63) / 64 * 64;
-    return half < tile ? half : tile;
+    return half < t ? half : t;
 }
 
 inline Geom geom_of(const PlotArgs& a) {
@@ -92,6 +101,8 @@ inline Geom geom_of(const PlotArgs& a) {
     g.w = a.w;
     g.tile = a.tile;
     g.npairs = a.npairs;
+    g.tile2 = a.tile2 > 0 ? a.tile2 : a.tile;
+    g.nbig = a.tile2 > 0 ? a.nbig : 0;
     g.threshold = a.threshold;
     g.ocols = a.ws == 2 ? a.cols / 2 : a.cols;
     g.xstride = a.xstride;

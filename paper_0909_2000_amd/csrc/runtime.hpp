@@ -16,10 +16,20 @@ struct Slot {
     bool pending = false;
 };
 
-// y-windows per tile for windows w in [lo, hi]
+// y-windows per tile for windows w in [lo, hi]: the first nbig tile pairs of
+// every strip block have tiles of `tile` windows, the later ones of tile2
+// (tile2 == tile: one length)
 struct TileRule {
-    int32_t lo, hi, tile;
+    int32_t lo, hi, tile, tile2 = 0, nbig = 0;
 };
+
+// A tiling chosen for one plot shape (rows, cols, window, stored-window step)
+struct TileChoice {
+    int64_t rows = -1, cols = -1;
+    int32_t w = 0, ws = 0;
+    int32_t tile = 0, tile2 = 0, nbig = 0, npairs = 0;
+};
+constexpr int kTileCache = 16;
 
 }  // namespace wlcs_rt
 
@@ -34,4 +44,6 @@ struct wlcs_ctx {
     wlcs_rt::TileRule batch_rules[16];
     int nbatch_rules = 0;
     int batch_waves_per_cu = 0;  // 0: kBatchWavesPerCu
+    wlcs_rt::TileChoice tile_cache[wlcs_rt::kTileCache];  // recent built-in tilings
+    int tile_cache_next = 0;
 };

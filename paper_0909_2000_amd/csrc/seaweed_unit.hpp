@@ -137,8 +137,8 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     constexpr int FO = FL / WS;  // outputs per flushed block
     const int lane = threadIdx.x & 63;
     const int64_t s0 = sb * 64;
-    const int64_t tlen = pair_tile(g.cols, g.tile, pr);  // windows per tile of this pair
-    const int64_t tA = (int64_t)(2 * pr) * g.tile;
+    int64_t tA;  // first window of tile A
+    const int64_t tlen = pair_tile(g.cols, g.tile, g.tile2, g.nbig, pr, &tA);  // windows per tile of this pair
     const int64_t tB = tA + tlen;
     const int w = EXACT ? WC : g.w;
 

@@ -89,6 +89,7 @@ def test_pair_and_ctx_argument_checks(lib):
     assert lib.wlcs_pair_destroy(None) == 0
     assert lib.wlcs_ctx_destroy(None) == 0
     assert lib.wlcs_ctx_set_tile(None, 1, 16, 64) == EINVAL
+    assert lib.wlcs_ctx_set_tiles(None, 1, 16, 1024, 64, 2) == EINVAL
     assert lib.wlcs_ctx_create(0, None) == EINVAL
 
 

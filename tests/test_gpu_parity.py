@@ -84,6 +84,62 @@ def test_tiles_and_relabelling(ctx, oracle_mod, tile):
         np.testing.assert_array_equal(got, want)
 
 
+@pytest.mark.parametrize("long_tile,short_tile,long_pairs", [
+    (1024, 64, 1), (512, 128, 2), (576, 192, 3), (2048, 64, 1), (256, 1024, 4), (640, 64, 99)])
+def test_two_tile_lengths(ctx, oracle_mod, long_tile, short_tile, long_pairs):
+    """Long tiles for the first tile pairs of every strip block, short ones
+    after them (the short region ending in the evenly split last pair; a
+    count of long pairs beyond the row is cut to what fits): whole plots
+    against the oracle, and equal to the plot with one tile length."""
+    _say(f"two tile lengths {long_tile}/{short_tile} x {long_pairs}")
+    g = workloads.rng(2100 + long_tile + short_tile + long_pairs)
+    for w in (16, 37, 64, 128):
+        x, y = workloads.iid(g, 100 + w, workloads.DNA), workloads.iid(g, 4700 + w, workloads.DNA)
+        want = oracle_mod.wlcs(x, y, w)
+        ctx.set_tiles(1, 255, long_tile, short_tile, long_pairs)
+        try:
+            got = {k: _cpu(v) for k, v in ctx.plot(x, y, w, threshold=(3 * w) // 4, indel=True).items()}
+        finally:
+            ctx.set_tile(1, 255, 0)
+        np.testing.assert_array_equal(got["wlcs"], want)
+        np.testing.assert_array_equal(got["indel"].view(np.uint16), oracle_mod.indel(want, w))
+        np.testing.assert_array_equal(got["bitmap"].view("<u8"), oracle_mod.dot_bitmap(want, (3 * w) // 4))
+
+
+def test_two_tile_lengths_strided_and_score(ctx, oracle_mod):
+    """The same tilings through the strided/sparse and the score-plot paths."""
+    g = workloads.rng(2150)
+    x, y = workloads.iid(g, 400, workloads.DNA), workloads.iid(g, 5200, workloads.DNA)
+    w, hx, hy = 48, 3, 2
+    want = oracle_mod.wlcs_strided(x, y, w, hx, hy)
+    thr = int(np.quantile(want, 0.99))
+    ctx.set_tiles(1, 255, 1024, 128, 2)
+    try:
+        pair = ctx.pair(x, y)
+        res = pair.plot_strided(w, hx, hy, threshold=thr, dot_cap=want.size + 1)
+        got = _cpu(res["wlcs"])
+        import paper_0909_2000_amd as wl
+        dots, count = wl.dot_records(res)
+        score = _cpu(ctx.score_plot(x, y, 30, step=4)["score"])
+    finally:
+        ctx.set_tile(1, 255, 0)
+    np.testing.assert_array_equal(got, want)
+    ref = oracle_mod.dot_list(want, w, thr, hx, hy)
+    assert count == ref.size
+    np.testing.assert_array_equal(dots.view(np.uint8), ref.view(np.uint8))
+    np.testing.assert_array_equal(score, oracle_mod.score_plot(x, y, 30, step=4))
+
+
+def test_tile_settings_rejected(ctx):
+    import paper_0909_2000_amd as wl
+    for args in [(1, 255, 100, 64, 1), (1, 255, 1024, 65, 1), (1, 255, 1024, 64, -1), (1, 255, 1 << 16, 64, 1),
+                 (0, 255, 1024, 64, 1), (9, 8, 1024, 64, 1)]:
+        with pytest.raises(wl.WlcsError) as e:
+            ctx.set_tiles(*args)
+        assert e.value.status == -1
+    ctx.set_tiles(1, 255, 0, 0, 0)  # drops the rules
+
+
 def test_config1_full(ctx, oracle_mod):
     p = workloads.config(1)
     _say("config 1 full")
