@@ -56,6 +56,23 @@ def _plot(lib, x=b"ACGTACGT", y=b"ACGTACGTAC", w=3, alpha=b"ACGT", sigma=None, o
                             ctypes.c_void_p(indel) if indel else None, ld_indel, flags, None)
 
 
+@pytest.mark.parametrize("fn", ["wlcs_plot", "wlcs_plot_dp", "wlcs_plot_blcs"])
+def test_lengths_beyond_the_maximum(lib, fn):
+    """A string longer than WLCS_MAX_LEN is rejected with ERANGE before any of
+    its bytes are read (the buffers here are short on purpose), as are negative
+    lengths."""
+    max_len = 100_000_000
+    x = y = b"ACGTACGT"
+
+    def call(m, n):
+        return getattr(lib, fn)(None, x, m, y, n, 3, b"ACGT", 4, ctypes.c_void_p(1), 1 << 30, None, 0, 0, None,
+                                0, 0, None)
+    assert call(max_len + 1, 8) == ERANGE
+    assert call(8, max_len + 1) == ERANGE
+    assert call(-1, 8) == ERANGE
+    assert call(8, -5) == ERANGE
+
+
 @pytest.mark.parametrize("fn", ["wlcs_plot", "wlcs_plot_dp"])
 def test_argument_checks_before_any_device_work(lib, fn):
     # ranges
