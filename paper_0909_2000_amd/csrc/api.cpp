@@ -59,13 +59,17 @@ int64_t n_windows(int64_t len, int32_t w, bool full) {
     return k > 0 ? k : 0;
 }
 
-// Resident waves per SIMD of the single-plot kernel of a window class (the
-// register budget; LDS allows 4 more at 8.7 KB per wave for the 32-window
-// flush and 3 at 12.8 KB for the 64-window one).
-int waves_per_simd(int wc, int ws) {
+// Units (64 strips, one tile pair) resident per SIMD for the single-plot
+// kernel of a window class, as the tile model counts them: its waves per SIMD
+// (the register budget; LDS allows 4 more at 8.7 KB per wave for the
+// 32-window flush and 3 at 12.8 KB for the 64-window one).  A score-plot
+// class that splits a strip over two waves counts one unit per SIMD: its
+// waves fit 2 or 3 per SIMD, but the tilings measured fastest on the GPU are
+// the ones the model picks with one.
+double units_per_simd(int wc, int ws) {
     if (ws == 2) {  // score plots: the separator schedule, classes of 8 rows
         const int dc = (wc + 7) / 8 * 8;
-        return dc <= 64 ? 3 : dc <= 128 ? 2 : 1;
+        return wlcs::dl_split(dc) ? 1.0 : (double)wlcs::min_waves_per_simd_dl(dc);
     }
     const int regs = wc <= 32 ? 4 : wc == 64 ? 3 : wc == 128 ? 2 : 1;
     const int lds = wc >= 64 ? 3 : 4;
@@ -141,7 +145,7 @@ int64_t tiling_makespan(const wlcs::PlotArgs& a, int64_t nblocks, int64_t cols, 
 // launch's tail short.  So the pairs of every strip block may start with long
 // tiles and end with short ones.  Every candidate (one length, or two with a
 // few counts of long pairs) is scored by the finishing time of a greedy list
-// schedule of its units over SIMDs x resident waves equal slots; the fastest
+// schedule of its units over SIMDs x resident units equal slots; the fastest
 // wins (the longer tiles on ties).  A context rule (wlcs_ctx_set_tile or
 // wlcs_ctx_set_tiles) overrides the choice.
 // The choice for a shape is kept in a small cache of the context.
@@ -164,7 +168,7 @@ void choose_tiles(wlcs_ctx* ctx, wlcs::PlotArgs& a, int64_t rows, int64_t cols, 
     }
     static const int32_t cand[] = {64, 128, 192, 256, 384, 512, 768, 1024, 1280, 1536, 2048, 2560, 3072, 4096, 6144, 8192, 12288, 16384};
     const int64_t nblocks = (rows + 63) / 64;
-    const int64_t slots = 4 * (int64_t)ctx->cus * waves_per_simd(ws == 2 ? w : wlcs::w_class(w), ws);
+    const int64_t slots = (int64_t)(4.0 * ctx->cus * units_per_simd(ws == 2 ? w : wlcs::w_class(w), ws));
     const int64_t cap = std::max<int64_t>(64, (cols + 63) / 64 * 64);
     int64_t best_t = INT64_MAX;
     wlcs::PlotArgs best = a;

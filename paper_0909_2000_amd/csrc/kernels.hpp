@@ -129,6 +129,28 @@ struct JobDesc {
     int32_t pad;
 };
 
+// Score-plot classes (the separator schedule of the seaweed kernel).  Waves
+// per SIMD a class of wc rows is compiled for when one wave holds the whole
+// strip: its wc labels and the codes of its wc / 2 letter rows (wc / 4
+// registers) must fit.
+constexpr int min_waves_per_simd_dl(int wc) { return wc <= 64 ? 3 : wc <= 128 ? 2 : 1; }
+// Score-plot classes come in steps of this many pair slots (2 rows each), so a
+// window leaves fewer than kDlSlots slots of its class unused.
+constexpr int kDlSlots = 4;
+// Score-plot classes above this many rows split every strip over two waves of
+// one workgroup (the upper and the lower pair slots), so that each wave's
+// labels and codes fit three (two above 208 rows) waves per SIMD instead of
+// one.
+constexpr int kDlSplitRows = 128;
+constexpr bool dl_split(int wc) { return wc > kDlSplitRows; }
+// Pair slots of the upper wave: a little over half, since the lower wave also
+// counts and stores (a multiple of kDlSlots, so unused slots stay in it).
+constexpr int dl_upper_slots(int wc) { return (wc / 4 + 2 + kDlSlots - 1) / kDlSlots * kDlSlots; }
+constexpr int min_waves_per_simd_dl_split(int wc) { return wc <= 208 ? 3 : 2; }
+// LDS of the hand-over between the two waves: two buffers of four labels
+// per lane
+constexpr int kDlHandDwords = 2 * 4 * 64;
+
 // Window capacity class of a window length: 16, 32, 64, 128 or 256.
 inline int w_class(int w) { return w <= 16 ? 16 : w <= 32 ? 32 : w <= 64 ? 64 : w <= 128 ? 128 : 256; }
 

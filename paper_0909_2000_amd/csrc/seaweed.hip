@@ -78,6 +78,28 @@ __global__ __launch_bounds__(64, DL ? min_waves_per_simd_dl(WC) : min_waves_per_
     comb_unit<WC, EXACT, WS, SP, DL>(xf, yg32, out, bm32, indel, dots, dot_count, g, sb, pr, ring, stage);
 }
 
+// Score plots of more than kDlSplitRows rows: two waves per strip (the upper
+// and the lower pair slots, see comb_unit), one unit per workgroup of 128.
+template <int WC>
+__global__ __launch_bounds__(128, min_waves_per_simd_dl_split(WC)) void seaweed_kernel_split(
+    const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32, uint8_t* __restrict__ out,
+    uint32_t* __restrict__ bm32, uint16_t* __restrict__ indel, DotRec* __restrict__ dots,
+    unsigned long long* __restrict__ dot_count, Geom g) {
+    __shared__ uint32_t ring[ring_words(WC) * 64];
+    __shared__ uint32_t stage[stage_dwords(WC, 2)];
+    __shared__ uint32_t hand[kDlHandDwords];
+    const int64_t nblocks = (g.rows + 63) / 64;
+    const int64_t unit = blockIdx.x;
+    const int pr = (int)(unit / nblocks);
+    const int64_t sb = unit - (int64_t)pr * nblocks;
+    if (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0)
+        comb_unit<WC, false, 2, false, true, 1>(xf, yg32, out, bm32, indel, dots, dot_count, g, sb, pr, ring, stage,
+                                                 hand);
+    else
+        comb_unit<WC, false, 2, false, true, 2>(xf, yg32, out, bm32, indel, dots, dot_count, g, sb, pr, ring, stage,
+                                                 hand);
+}
+
 __global__ void zero_u64(unsigned long long* p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
 }
@@ -102,8 +124,12 @@ hipError_t launch_dl(const PlotArgs& a, hipStream_t stream) {
     if (units <= 0) return hipSuccess;
     if (units > 0x7FFFFFFFll) return hipErrorInvalidValue;
     const Geom g = geom_of(a);
-    hipLaunchKernelGGL((seaweed_kernel<WC, false, 2, false, true>), dim3((uint32_t)units), dim3(64), 0, stream,
-                       a.xf, (const uint32_t*)a.yg, a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+    if constexpr (dl_split(WC))
+        hipLaunchKernelGGL((seaweed_kernel_split<WC>), dim3((uint32_t)units), dim3(128), 0, stream, a.xf,
+                           (const uint32_t*)a.yg, a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+    else
+        hipLaunchKernelGGL((seaweed_kernel<WC, false, 2, false, true>), dim3((uint32_t)units), dim3(64), 0, stream,
+                           a.xf, (const uint32_t*)a.yg, a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
     return hipGetLastError();
 }
 

@@ -33,13 +33,6 @@ constexpr int stage_dwords(int wc, int ws = 1) { return 2 * 64 * stage_pitch(wc,
 // Occupancy each window class is compiled for (waves per SIMD): the w labels
 // and w/2 code registers per lane plus the flush temporaries must fit.
 constexpr int min_waves_per_simd(int wc) { return wc <= 32 ? 4 : wc <= 64 ? 3 : wc <= 128 ? 2 : 1; }
-// The same for the score-plot schedule (DL), whose strip of wc rows keeps
-// codes for its wc / 2 letter rows only (wc / 4 registers).
-constexpr int min_waves_per_simd_dl(int wc) { return wc <= 64 ? 3 : wc <= 128 ? 2 : 1; }
-// Score-plot classes come in steps of this many pair slots (2 rows each), so a
-// window leaves fewer than kDlSlots slots of its class unused.
-constexpr int kDlSlots = 4;
-
 // Stores of a strided or sparse plot for one flushed block: window j0 + b of
 // strip s0 + r sits in byte b of row r of the staged block (stride pitch
 // dwords).  Output column c holds the window c * hy; the lanes of the wave
@@ -123,14 +116,25 @@ __device__ __forceinline__ void strided_flush(uint8_t* __restrict__ out, uint16_
 // slot apart, so that two independent chains share the instruction stream.
 // The strip has WC / 2 pair slots; a window of w / 2 < WC / 2 pairs leaves the
 // top WC / 2 - w / 2 (< kDlSlots) slots unused.
-template <int WC, bool EXACT, int WS = 1, bool SP = false, bool DL = false>
+//
+// PART (DL only): 0 combs the whole strip in one wave.  With two waves per
+// strip, PART 1 (the upper wave) combs the upper pair slots and hands the
+// four labels leaving its last slot in each pair of passes to PART 2 (the
+// lower wave) through `hand` in LDS; PART 2 combs the lower slots one pair of
+// passes behind, counts and stores.  Both waves meet at one workgroup barrier
+// per pair of passes (the upper after writing, the lower before reading), and
+// the same sequence of pairs of passes in both makes the barriers match.
+template <int WC, bool EXACT, int WS = 1, bool SP = false, bool DL = false, int PART = 0>
 __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32,
                                           uint8_t* __restrict__ out, uint32_t* __restrict__ bm32,
                                           uint16_t* __restrict__ indel, DotRec* __restrict__ dots,
                                           unsigned long long* __restrict__ dot_count, const Geom& g, int64_t sb,
-                                          int pr, uint32_t* __restrict__ ring, uint32_t* __restrict__ stage) {
+                                          int pr, uint32_t* __restrict__ ring, uint32_t* __restrict__ stage,
+                                          uint32_t* __restrict__ hand = nullptr) {
     static_assert(!SP || WS == 1, "strided and sparse plots store single windows");
     static_assert(!DL || (WS == 2 && !EXACT && WC % (2 * kDlSlots) == 0), "the score-plot schedule");
+    static_assert(PART == 0 || (DL && dl_split(WC)), "two waves per strip: score plots above kDlSplitRows rows");
+    constexpr bool UPPER = PART == 1;  // combs only: no count, no stores
     constexpr int RW = ring_words(WC);
     constexpr int FL = flush_windows(WC, WS);
     constexpr int PITCH = stage_pitch(WC, WS);
@@ -153,10 +157,15 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     const int wpad = (EXACT || DL) ? WC : w + pad;
     constexpr int NP = WC / 2;                 // DL: pair slots
     const int ppad = DL ? NP - w / 2 : 0;      // DL: unused slots at the top (< kDlSlots)
+    // DL: this wave's pair slots, S0 .. S0 + NS - 1 of the strip
+    constexpr int S0 = PART == 2 ? dl_upper_slots(WC) : 0;
+    constexpr int NS = PART == 0 ? NP : PART == 1 ? dl_upper_slots(WC) : NP - dl_upper_slots(WC);
+    static_assert(NS % 2 == 0 && S0 >= (PART == 2 ? kDlSlots : 0), "slot split");
+    constexpr int HN = DL ? 2 * NS : WC;       // labels held by this wave
     // x letters of this lane's strip, two rows per register (lanes past the
     // last strip comb a copy of the last one; their results are never stored);
-    // DL: the letters of the letter rows only, two slots per register
-    constexpr int NXC = DL ? WC / 4 : WC / 2;
+    // DL: the letters of this wave's letter rows only, two slots per register
+    constexpr int NXC = DL ? NS / 2 : WC / 2;
     uint32_t xc[NXC];
     {
         const int64_t sx = s0 + lane < g.rows ? s0 + lane : g.rows - 1;
@@ -166,7 +175,7 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         for (int j = 0; j < NXC; ++j) {
             uint32_t lo, hi;
             if (DL) {  // slot r holds letter r - ppad, at row 2 (r - ppad) + 1 of the strip
-                const int i0 = 2 * j - ppad, i1 = 2 * j + 1 - ppad;
+                const int i0 = S0 + 2 * j - ppad, i1 = S0 + 2 * j + 1 - ppad;
                 lo = i0 >= 0 ? (uint32_t)xp[2 * i0 + 1] : PADF;
                 hi = i1 >= 0 ? (uint32_t)xp[2 * i1 + 1] : PADF;
             } else {
@@ -177,11 +186,13 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
             xc[j] = lo | (hi << 16);
         }
     }
-    uint32_t h[WC];
+    uint32_t h[HN];
 #pragma unroll
-    for (int k = 0; k < WC; ++k) h[k] = 0;
+    for (int k = 0; k < HN; ++k) h[k] = 0;
+    if constexpr (!UPPER) {
 #pragma unroll
-    for (int q = 0; q < RW; ++q) ring[q * 64 + lane] = 0;
+        for (int q = 0; q < RW; ++q) ring[q * 64 + lane] = 0;
+    }
 
     const int64_t restA = g.cols - tA;  // > 0: every launched unit has a non-empty tile A
     const int64_t nA = (restA + 63) / 64 * 64;
@@ -259,6 +270,7 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         yq0 = yload(1);
         yq1 = yload(3);
     }
+    int hand_buf = 0;  // DL split: pairs of passes so far (picks the hand-over buffer)
     struct Counts { uint32_t c0, c1, c2; };
     auto passes = [&](int c, auto two_t) -> Counts {
         constexpr bool TWO = decltype(two_t)::value;
@@ -272,6 +284,15 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         }
         uint32_t pcar = pk_rep(c - org), pt = pk_rep(c + 1 - org);
         uint32_t qcar = pk_rep(c + 2 - org), qt = pk_rep(c + 3 - org);
+        uint32_t* const hb = hand + (hand_buf & 1) * 256 + lane;  // DL split: this pair of passes' hand-over
+        if constexpr (PART == 2) {
+            // the labels leaving the upper wave's last slot in these passes
+            __syncthreads();
+            pcar = hb[0];
+            pt = hb[64];
+            qcar = hb[128];
+            qt = hb[192];
+        }
         // The unused top slots (their letter is the pad code, which matches
         // nothing) run the same steps: the letter column's label, the largest
         // of all, passes through them unchanged, and after each of them the
@@ -279,28 +300,37 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         // than every label the slot holds), so that both columns enter the
         // first used slot with their top labels.
         const uint32_t sP = pcar, sQ = qcar;
-        // step k: pass P at slot k, pass Q at slot k - 1
+        // step k: pass P at slot k, pass Q at slot k - 1 (this wave's slots)
         auto step = [&](int k, bool q_on) {
-            const int kp = k < NP ? k : NP - 1, kq = k >= 1 ? k - 1 : 0;
-            if (k < NP && q_on) {
+            const int kp = k < NS ? k : NS - 1, kq = k >= 1 ? k - 1 : 0;
+            if (k < NS && q_on) {
                 if (k & 1)
                     fused_slot2<1>(h[2 * kp], h[2 * kp + 1], pt, pcar, xc[kp >> 1], YP, h[2 * kq], h[2 * kq + 1],
                                    qt, qcar, xc[kq >> 1], YQ);
                 else
                     fused_slot2<0>(h[2 * kp], h[2 * kp + 1], pt, pcar, xc[kp >> 1], YP, h[2 * kq], h[2 * kq + 1],
                                    qt, qcar, xc[kq >> 1], YQ);
-            } else if (k < NP) {
+            } else if (k < NS) {
                 pcar = (k & 1) ? fused_slot<1>(h[2 * kp], h[2 * kp + 1], pt, pcar, xc[kp >> 1], YP)
                                : fused_slot<0>(h[2 * kp], h[2 * kp + 1], pt, pcar, xc[kp >> 1], YP);
             } else if (q_on) {
                 qcar = (kq & 1) ? fused_slot<1>(h[2 * kq], h[2 * kq + 1], qt, qcar, xc[kq >> 1], YQ)
                                 : fused_slot<0>(h[2 * kq], h[2 * kq + 1], qt, qcar, xc[kq >> 1], YQ);
             }
-            if (k < kDlSlots && k < NP) pcar = pk_max(pcar, k < ppad ? sP : 0u);
-            if (q_on && kq < kDlSlots) qcar = pk_max(qcar, kq < ppad ? sQ : 0u);
+            if (S0 + k < kDlSlots && k < NS) pcar = pk_max(pcar, k < ppad ? sP : 0u);
+            if (q_on && S0 + kq < kDlSlots) qcar = pk_max(qcar, kq < ppad ? sQ : 0u);
         };
 #pragma unroll
-        for (int k = 0; k <= NP; ++k) step(k, TWO && k >= 1);
+        for (int k = 0; k <= NS; ++k) step(k, TWO && k >= 1);
+        ++hand_buf;
+        if constexpr (UPPER) {
+            hb[0] = pcar;
+            hb[64] = pt;
+            hb[128] = qcar;
+            hb[192] = qt;
+            __syncthreads();
+            return Counts{0u, 0u, 0u};
+        }
         (void)count(c - 1, pcar);
         Counts r;
         r.c0 = count(c, pt);
@@ -326,6 +356,17 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         for (int l = 0; l < w - 1; ++l) (void)column(l);
     }
 
+    // The staging block is this wave's alone: with two waves per strip the
+    // lower wave orders its LDS accesses without a workgroup barrier (the
+    // upper wave does not store).
+    auto stage_sync = [&]() {
+        if constexpr (PART == 0) {
+            __syncthreads();
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+    };
     const uint32_t bm_words = (uint32_t)(((g.ocols + 63) >> 6) * 2);
     for (int jb = 0; jb < nproc; jb += FL) {
 #pragma unroll 1
@@ -335,7 +376,7 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                 const int32_t norg = jj - 1;  // (column jj + w - 1) - w
                 const uint32_t d2 = pk_rep(norg - org);
 #pragma unroll
-                for (int k = 0; k < WC; ++k) h[k] = pk_sub_sat(h[k], d2);
+                for (int k = 0; k < HN; ++k) h[k] = pk_sub_sat(h[k], d2);
                 org = norg;
             }
             const int l = jj + w - 1;  // DL: odd (w even, jj a multiple of 4)
@@ -353,17 +394,20 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                 r2 = column(l + 2);
                 r3 = column(l + 3);
             }
-            // bytes 0 (tile A) and 2 (tile B) of the four results, gathered
-            // into one dword per tile: r0.b0 r0.b2 r1.b0 r1.b2, then the same
-            // for r2, r3, then the even and the odd bytes of the two
-            const uint32_t t01 = __builtin_amdgcn_perm(r1, r0, 0x06040200u);
-            const uint32_t t23 = __builtin_amdgcn_perm(r3, r2, 0x06040200u);
-            const uint32_t wa = __builtin_amdgcn_perm(t23, t01, 0x06040200u);
-            const uint32_t wb = __builtin_amdgcn_perm(t23, t01, 0x07050301u);
-            stage[lane * PITCH + gi] = wa;
-            stage[64 * PITCH + lane * PITCH + gi] = wb;
+            if constexpr (!UPPER) {
+                // bytes 0 (tile A) and 2 (tile B) of the four results, gathered
+                // into one dword per tile: r0.b0 r0.b2 r1.b0 r1.b2, then the
+                // same for r2, r3, then the even and the odd bytes of the two
+                const uint32_t t01 = __builtin_amdgcn_perm(r1, r0, 0x06040200u);
+                const uint32_t t23 = __builtin_amdgcn_perm(r3, r2, 0x06040200u);
+                const uint32_t wa = __builtin_amdgcn_perm(t23, t01, 0x06040200u);
+                const uint32_t wb = __builtin_amdgcn_perm(t23, t01, 0x07050301u);
+                stage[lane * PITCH + gi] = wa;
+                stage[64 * PITCH + lane * PITCH + gi] = wb;
+            }
         }
-        __syncthreads();
+        if constexpr (UPPER) continue;  // the lower wave stores
+        stage_sync();
         const int64_t s = s0 + lane;  // this lane's strip
 #pragma unroll 1
         for (int half = 0; half < 2; ++half) {
@@ -447,7 +491,7 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                 }
             }
         }
-        __syncthreads();
+        stage_sync();
     }
 }
 

@@ -385,6 +385,49 @@ def comb_blown_up_fused(letters, yl, cap, interleave):
     return exits
 
 
+def fused_slots(h, code, pad, lo, hi, top, carry, out, yl_c):
+    """Slots lo .. hi - 1 of one fused pass (see fused_pass), entered with the
+    separator column's carry and the letter column's label; returns both as
+    they leave slot hi - 1."""
+    for r in range(lo, hi):
+        a, b = h[2 * r], h[2 * r + 1]
+        mx, b = max(a, b), min(a, b)
+        h[2 * r], d = min(carry, out), max(carry, out)
+        if code[r] == yl_c:
+            h[2 * r + 1], out = d, b
+        else:
+            h[2 * r + 1], out = min(b, d), max(b, d)
+        carry = max(mx, top) if r < pad else mx
+    return carry, out
+
+
+@pytest.mark.parametrize("cap,upper", [(16, 8), (32, 20), (32, 4)])
+def test_split_blown_up_schedule_equals_combing(cap, upper):
+    """The strip split over two waves: the upper slots 0 .. upper - 1 of every
+    pass, then (here all at the end, the extreme case of the lower wave's lag)
+    the lower slots entered with the labels the upper slots handed over.  The
+    lower slots read nothing else from the upper ones, so the exits equal plain
+    combing whatever the lag."""
+    g = workloads.rng(950 + cap + upper)
+    for trial in range(40):
+        npairs = int(g.integers(cap - 3, cap + 1))
+        letters = bytes(workloads.iid(g, npairs, workloads.DNA))
+        yl = bytes(workloads.iid(g, int(g.integers(1, 14)), workloads.DNA))
+        pad = cap - npairs
+        code = [None] * pad + list(letters)
+        h = [LEFT] * (2 * cap)
+        handed = []
+        for c in range(1, 2 * len(yl), 2):  # upper wave: every pass
+            handed.append((c, fused_slots(h, code, pad, 0, upper, c - 1, c - 1, c, yl[c // 2])))
+        exits = []
+        for c, (carry, out) in handed:     # lower wave: every pass, afterwards
+            exits += list(fused_slots(h, code, pad, upper, cap, c - 1, carry, out, yl[c // 2]))
+        xb = b"".join(b"$" + bytes([ch]) for ch in letters)
+        yb = b"".join(b"$" + bytes([ch]) for ch in yl)
+        plain, _ = comb(xb, yb)
+        assert exits == plain
+
+
 @pytest.mark.parametrize("interleave", [False, True])
 @pytest.mark.parametrize("cap", [16, 32])
 def test_fused_blown_up_schedule_equals_combing(cap, interleave):
