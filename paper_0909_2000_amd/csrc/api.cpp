@@ -76,6 +76,15 @@ double units_per_simd(int wc, int ws) {
     return std::min(regs, lds);
 }
 
+// Units (workgroups) that fit on one CU at once.
+int units_per_cu(int wc, int ws) {
+    if (ws == 2) {
+        const int dc = (wc + 7) / 8 * 8;
+        return wlcs::dl_split(dc) ? 4 * wlcs::min_waves_per_simd_dl_split(dc) / 2 : 4 * wlcs::min_waves_per_simd_dl(dc);
+    }
+    return 4 * (int)units_per_simd(wc, ws);
+}
+
 // Tile pairs of a row of cols windows with long tiles of `tile` windows for
 // at most nbig_max leading pairs (never past the row's end) and tiles of tile2
 // after them.
@@ -168,7 +177,13 @@ void choose_tiles(wlcs_ctx* ctx, wlcs::PlotArgs& a, int64_t rows, int64_t cols, 
     }
     static const int32_t cand[] = {64, 128, 192, 256, 384, 512, 768, 1024, 1280, 1536, 2048, 2560, 3072, 4096, 6144, 8192, 12288, 16384};
     const int64_t nblocks = (rows + 63) / 64;
-    const int64_t slots = (int64_t)(4.0 * ctx->cus * units_per_simd(ws == 2 ? w : wlcs::w_class(w), ws));
+    const int wcl = ws == 2 ? w : wlcs::w_class(w);
+    const int64_t slots = (int64_t)(4.0 * ctx->cus * units_per_simd(wcl, ws));
+    // long tiles only with at least as many long units as fit on the GPU at
+    // once: then every CU starts full of long units, whichever CUs the units
+    // land on (with fewer, some CUs can end up with several long units and
+    // others with none, and the launch waits for the former)
+    const int64_t resident = (int64_t)ctx->cus * units_per_cu(wcl, ws);
     const int64_t cap = std::max<int64_t>(64, (cols + 63) / 64 * 64);
     int64_t best_t = INT64_MAX;
     wlcs::PlotArgs best = a;
@@ -187,7 +202,8 @@ void choose_tiles(wlcs_ctx* ctx, wlcs::PlotArgs& a, int64_t rows, int64_t cols, 
         const int64_t nb_max = cols / (2 * (int64_t)t);
         for (int32_t t2 : cand) {
             if (t2 >= t) break;
-            for (int64_t nb = std::max<int64_t>(1, nb_max - 7); nb <= nb_max; ++nb) consider(t, t2, nb);
+            for (int64_t nb = std::max<int64_t>(1, nb_max - 7); nb <= nb_max; ++nb)
+                if (nb * nblocks >= resident) consider(t, t2, nb);
         }
     }
     a.tile = best.tile;
