@@ -419,7 +419,7 @@ def bench_paper_shapes(ctx, torch, workloads):
         res = ctx.score_plot(x, y, w, step=step)  # allocates and warms up
         S = res["score"]
         ms = float(np.median([_timed_once(torch, lambda: ctx.score_plot(x, y, w, step=step, out=S))
-                              for _ in range(3)]))
+                              for _ in range(7)]))
         cells = float(S.shape[0]) * (2 * n) * (2 * w)
         out[name] = {"m": m, "n": n, "w": w, "step": step, "rows": S.shape[0], "cols": S.shape[1],
                      "ms": ms, "blown_up_cells_per_s": cells / (ms / 1e3),
