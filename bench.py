@@ -38,6 +38,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), or an empty string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
 def measured_traffic(workload: str, cells: float = 0.0):
     """HBM bytes per launch of the timed kernel, from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs, each scaled by what the same counter read for
@@ -176,9 +188,22 @@ def main():
     achieved = cells * OPS_PER_CELL / (avg_kernel_ms / 1e3)
     traffic, traffic_detail = measured_traffic(p.name, cells)
     algo_bytes = float(m + n) * 2 + float(rows) * cols + (float(rows) * ((cols + 63) // 64) * 8 if thr else 0)
+    # the device's sustained packed-16-bit rate, measured by the library's
+    # probe of independent v_pk_max_u16 chains, beside the published peak
+    # (about 28 ms a run: shorter runs read low while the clock ramps up)
+    measured_peak = max(ctx.measure_valu_peak(8000) for _ in range(2))
+    log(f"measured packed-u16 VALU peak: {measured_peak / 1e12:.1f} TOP/s "
+        f"(published {PEAK_U16_OPS / 1e12:.1f})")
+    launch_s = avg_kernel_ms / 1e3
+    if traffic_detail is not None and "write_bytes" in traffic_detail:
+        traffic_detail["write_TB_per_s"] = traffic_detail["write_bytes"] / launch_s / 1e12
+        traffic_detail["read_TB_per_s"] = traffic_detail["read_bytes"] / launch_s / 1e12
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_U16_OPS / 1e12,
                 "unit": "TOP/s", "frac": achieved / PEAK_U16_OPS, "traffic": traffic,
                 "traffic_detail": traffic_detail, "algorithmic_bytes": algo_bytes,
+                "algorithmic_output_TB_per_s": algo_bytes / launch_s / 1e12,
+                "measured_peak": measured_peak / 1e12, "frac_of_measured_peak": achieved / measured_peak,
+                "peak_probe": "wlcs_measure_valu_peak: independent v_pk_max_u16 chains on every SIMD",
                 "ops_per_cell": OPS_PER_CELL, "cells_per_launch": cells,
                 "avg_launch_ms": avg_kernel_ms}
 
@@ -206,7 +231,8 @@ def main():
         cpu = {"value": nrows * float(n) * w / cpu_s, "unit": "window-cells/s", "cores": threads,
                "kind": "oracle",
                "sample": f"{nrows} of {rows} plot rows (x-windows spread evenly), each against all "
-                         f"{cols} y-windows, plain per-window DP, {cpu_s:.1f} s"}
+                         f"{cols} y-windows, plain per-window DP, {cpu_s:.1f} s",
+               "one_core_value": float(n) * w / one_row, "cpu_model": cpu_model()}
         log(f"CPU oracle: {cpu['value']:.3e} window-cells/s on {threads} threads; "
             f"timed plot equals it on those {nrows} rows: {parity}")
 
@@ -467,11 +493,18 @@ def bench_serving(ctx, torch, workloads, args):
     at = run(rate)
     # the same stream with dot lists (window starts, WLCS, indel distance of
     # every pair at or above the threshold) in place of the dense outputs
+    # latency across the load: the same stream at other fractions of capacity
+    sweep = {}
+    for load in (0.25, 0.5, 0.9):
+        r = run(load * capacity)
+        sweep[str(load)] = {"rate_jobs_per_s": load * capacity, "p50_s": r["p50_s"], "p99_s": r["p99_s"],
+                            "jobs_per_s": r["jobs_per_s"]}
+        log(f"serving at {load:.2f} x capacity: p50 {r['p50_s'] * 1e3:.1f} ms, p99 {r['p99_s'] * 1e3:.1f} ms")
     sat_s = run(1.0, all_at_once=True, dots=True)
     rate_s = args.serving_load * sat_s["jobs_per_s"]
     at_s = run(rate_s, dots=True)
     return {"jobs": len(jobs), "capacity_jobs_per_s": capacity, "saturated": sat,
-            "load": args.serving_load, "rate_jobs_per_s": rate, "at_load": at,
+            "load": args.serving_load, "rate_jobs_per_s": rate, "at_load": at, "load_sweep": sweep,
             "budget_gib": args.budget_gib,
             "workload": "Poisson arrivals; DNA/protein 1:1; m,n log-uniform [500,50000]; "
                         "w ~ {16,32,64,128}; outputs bitmap (T=ceil(3w/4)) + uint16 indel",

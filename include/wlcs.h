@@ -71,6 +71,18 @@ int wlcs_ctx_destroy(wlcs_ctx *ctx);
 /* Last HIP error code (hipError_t as int) seen by the context, 0 if none. */
 int wlcs_ctx_last_hip_error(const wlcs_ctx *ctx);
 
+/* Measurement helper, not part of the method: the sustained rate of packed
+ * 16-bit VALU operations on the context's device, against which the seaweed
+ * kernels' rates are reported.  A kernel of independent v_pk_max_u16 chains
+ * (two 16-bit operations per lane and instruction, no instruction waiting for
+ * the one before it) runs on every SIMD of every CU, once to warm up and once
+ * timed with HIP events.  iters (1..10^6) sets the length of the timed run
+ * (about 0.34 ms per 100 on an MI355X; runs under about 10 ms read low while
+ * the clock ramps up).  Synchronous: it allocates, runs on a
+ * stream of its own, waits and frees.  *ops_per_s receives 16-bit element
+ * operations per second. */
+int wlcs_measure_valu_peak(wlcs_ctx *ctx, int32_t iters, double *ops_per_s);
+
 /* Human-readable text for a status code (static storage). */
 const char *wlcs_status_str(int status);
 

@@ -83,6 +83,7 @@ def _load():
     lib.wlcs_status_str.restype = ctypes.c_char_p
     lib.wlcs_ctx_set_tile.argtypes = [vp, i32, i32, i32]
     lib.wlcs_ctx_set_tiles.argtypes = [vp, i32, i32, i32, i32, i32]
+    lib.wlcs_measure_valu_peak.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
     plot_args = [vp, u8p, i64, u8p, i64, i32, u8p, i32, vp, i64, vp, i64, i32, vp, i64, u32, vp]
     lib.wlcs_plot.argtypes = plot_args
     lib.wlcs_plot_dp.argtypes = plot_args
@@ -108,6 +109,7 @@ def _load():
     lib.wlcs_pair_plot_strided.argtypes = strided_args
     lib.wlcs_pair_plot_dp_strided.argtypes = strided_args
     for f in ("wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_ctx_set_tile", "wlcs_ctx_set_tiles",
+              "wlcs_measure_valu_peak",
               "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot",
               "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
               "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
@@ -122,9 +124,9 @@ def _load():
 def exported_symbols() -> list:
     """Names of the C ABI entry points the binding uses."""
     return ["wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_status_str",
-            "wlcs_ctx_set_tile", "wlcs_ctx_set_tiles", "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create",
-            "wlcs_pair_destroy", "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
-            "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
+            "wlcs_ctx_set_tile", "wlcs_ctx_set_tiles", "wlcs_measure_valu_peak", "wlcs_plot", "wlcs_plot_dp",
+            "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch",
+            "wlcs_batch_graph", "wlcs_graph_launch", "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
             "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
             "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs", "wlcs_pair_plot_blcs"]
 
@@ -196,6 +198,15 @@ class Context:
         st = _load().wlcs_ctx_set_tile(self._h, w_lo, w_hi, tile)
         if st != 0:
             raise WlcsError(st, "wlcs_ctx_set_tile")
+
+    def measure_valu_peak(self, iters: int = 2000) -> float:
+        """wlcs_measure_valu_peak: sustained packed 16-bit VALU element
+        operations per second on this device (a measurement helper)."""
+        v = ctypes.c_double(0.0)
+        st = _load().wlcs_measure_valu_peak(self._h, int(iters), ctypes.byref(v))
+        if st != 0:
+            raise WlcsError(st, "wlcs_measure_valu_peak", _load().wlcs_ctx_last_hip_error(self._h))
+        return v.value
 
     def set_tiles(self, w_lo: int, w_hi: int, long_tile: int, short_tile: int, long_pairs: int):
         """wlcs_ctx_set_tiles: long tiles for the first long_pairs tile pairs

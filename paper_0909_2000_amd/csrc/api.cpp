@@ -17,6 +17,11 @@
 
 #include "runtime.hpp"
 
+namespace wlcs {
+// probe.hip: blocks x 256 threads of independent packed 16-bit VALU chains
+hipError_t launch_valu_peak(uint32_t* out, int32_t blocks, int32_t iters, hipStream_t stream);
+}  // namespace wlcs
+
 using wlcs_rt::kSlots;
 using wlcs_rt::Slot;
 using wlcs_rt::TileRule;
@@ -696,6 +701,35 @@ int wlcs_ctx_destroy(wlcs_ctx* ctx) {
 }
 
 int wlcs_ctx_last_hip_error(const wlcs_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+
+int wlcs_measure_valu_peak(wlcs_ctx* ctx, int32_t iters, double* ops_per_s) {
+    if (!ctx || !ops_per_s || iters < 1 || iters > 1000000) return WLCS_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
+    const int32_t blocks = 32 * ctx->cus;  // 128 waves per CU, 32 per SIMD
+    uint32_t* out = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipMalloc((void**)&out, (size_t)blocks * 256 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e == hipSuccess) e = wlcs::launch_valu_peak(out, blocks, iters < 100 ? iters : 100, stream);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
+    if (e == hipSuccess) e = wlcs::launch_valu_peak(out, blocks, iters, stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (e == hipSuccess && ms > 0.0f)
+        *ops_per_s = (double)blocks * 256.0 * (double)iters * 64.0 * 2.0 / (ms * 1e-3);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (stream) (void)hipStreamDestroy(stream);
+    if (out) (void)hipFree(out);
+    if (e != hipSuccess) return fail(ctx, e);
+    return ms > 0.0f ? WLCS_OK : WLCS_EHIP;
+}
 
 const char* wlcs_status_str(int status) {
     switch (status) {

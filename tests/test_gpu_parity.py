@@ -140,6 +140,21 @@ def test_tile_settings_rejected(ctx):
     ctx.set_tiles(1, 255, 0, 0, 0)  # drops the rules
 
 
+def test_valu_peak_probe(lib, ctx):
+    """The measurement helper the roofline is reported against: packed 16-bit
+    element operations per second within a plausible band around the
+    published 78.6 T (256 CUs x 64 lanes x 2 x 2.4 GHz), and its argument
+    checks."""
+    import ctypes
+    peak = ctx.measure_valu_peak(500)
+    _say(f"measured packed-u16 VALU peak: {peak / 1e12:.1f} T ops/s")
+    assert 40e12 < peak < 90e12
+    v = ctypes.c_double(0.0)
+    for iters in (0, -3, 2_000_000):
+        assert lib._load().wlcs_measure_valu_peak(ctx.handle, iters, ctypes.byref(v)) == -1
+    assert lib._load().wlcs_measure_valu_peak(ctx.handle, 10, None) == -1
+
+
 def test_config1_full(ctx, oracle_mod):
     p = workloads.config(1)
     _say("config 1 full")
