@@ -474,12 +474,12 @@ def bench_serving(ctx, torch, workloads, args):
     jobs = workloads.serving_jobs(rate=1.0, njobs=args.serving_jobs)
     budget = int(args.budget_gib * (1 << 30))
 
-    def run(rate_scale, all_at_once=False, dots=False):
+    def run(rate_scale, all_at_once=False, dots=False, d2h=False):
         reqs = serve.requests_from_workload(jobs, rate_scale=rate_scale, dots=dots)
         if all_at_once:
             for r in reqs:
                 r.arrival = 0.0
-        ex = serve.GpuExecutor(0, streams=3)  # its own context, latency tiles
+        ex = serve.GpuExecutor(0, streams=3, d2h_bitmaps=d2h)  # its own context, latency tiles
         srv = serve.Server(ex, budget_bytes=budget, max_jobs=256, max_batch=64, keep_results=False)
         rep = srv.run(reqs)
         torch.cuda.synchronize()
@@ -491,6 +491,9 @@ def bench_serving(ctx, torch, workloads, args):
     rate = args.serving_load * capacity
     # arrivals were drawn at 1 job/s: compress them to `rate`
     at = run(rate)
+    # the same, each job's latency running until its bitmap is in host memory
+    at_d2h = run(rate, d2h=True)
+    log(f"serving with bitmap D2H: p50 {at_d2h['p50_s'] * 1e3:.1f} ms, p99 {at_d2h['p99_s'] * 1e3:.1f} ms")
     # the same stream with dot lists (window starts, WLCS, indel distance of
     # every pair at or above the threshold) in place of the dense outputs
     # latency across the load: the same stream at other fractions of capacity
@@ -505,6 +508,7 @@ def bench_serving(ctx, torch, workloads, args):
     at_s = run(rate_s, dots=True)
     return {"jobs": len(jobs), "capacity_jobs_per_s": capacity, "saturated": sat,
             "load": args.serving_load, "rate_jobs_per_s": rate, "at_load": at, "load_sweep": sweep,
+            "at_load_with_bitmap_d2h": at_d2h,
             "budget_gib": args.budget_gib,
             "workload": "Poisson arrivals; DNA/protein 1:1; m,n log-uniform [500,50000]; "
                         "w ~ {16,32,64,128}; outputs bitmap (T=ceil(3w/4)) + uint16 indel",

@@ -90,9 +90,12 @@ LATENCY_GRID = 16
 
 class GpuExecutor:
     """Runs batches on one GPU through libwlcs, one stream per concurrent batch.
-    Without a context of its own it makes one with the latency tiles."""
+    Without a context of its own it makes one with the latency tiles.  With
+    d2h_bitmaps each job's bitmap is also copied to pinned host memory on the
+    batch's stream before its completion event (result "bitmap_host"), so that
+    a job's latency runs until its result is on the host."""
 
-    def __init__(self, device: int = 0, streams: int = 3, ctx=None):
+    def __init__(self, device: int = 0, streams: int = 3, ctx=None, d2h_bitmaps: bool = False):
         import torch
 
         import paper_0909_2000_amd as wl
@@ -104,6 +107,7 @@ class GpuExecutor:
                 ctx.set_batch_tile(lo, hi, t)
             ctx.set_batch_grid(LATENCY_GRID)
         self.ctx = ctx
+        self.d2h = d2h_bitmaps
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
         self.busy = [None] * streams  # per stream: (event, batch_id) or None
         self.t0 = time.perf_counter()
@@ -131,6 +135,12 @@ class GpuExecutor:
             specs.append(sp)
         with self.torch.cuda.stream(s):
             results = self.ctx.batch(specs, stream=s)
+            if self.d2h:
+                for res in results:
+                    if "bitmap" in res:
+                        host = self.torch.empty(res["bitmap"].shape, dtype=res["bitmap"].dtype, pin_memory=True)
+                        host.copy_(res["bitmap"], non_blocking=True)
+                        res["bitmap_host"] = host
             ev = self.torch.cuda.Event()
             ev.record(s)
         for js, res, sp in zip(jobs, results, specs):

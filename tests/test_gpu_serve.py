@@ -54,6 +54,39 @@ def test_serving_results_equal_alone(oracle_mod):
                                       oracle_mod.indel(want, r.w))
 
 
+def test_serving_bitmaps_copied_to_host():
+    """With d2h_bitmaps the executor also copies every job's bitmap to pinned
+    host memory on the batch's stream before the completion event: once a job
+    is done its host copy equals the device bitmap, and equals the job plotted
+    alone."""
+    import torch
+    import paper_0909_2000_amd as wl
+    from paper_0909_2000_amd import serve
+
+    g = workloads.rng(37)
+    reqs = []
+    t = 0.0
+    for k in range(24):
+        t += float(g.exponential(1.0 / 3000.0))
+        w = int((16, 32, 64, 128)[k % 4])
+        m, n = int(g.integers(200, 3000)) + w, int(g.integers(200, 3000)) + w
+        x, y = workloads.iid(g, m, workloads.DNA), workloads.iid(g, n, workloads.DNA)
+        reqs.append(serve.Request(k, x, y, w, workloads.DNA, threshold=(3 * w + 3) // 4, indel=False,
+                                  want_plot=False, arrival=t))
+    ctx = wl.Context(0)
+    ex = serve.GpuExecutor(0, streams=3, ctx=ctx, d2h_bitmaps=True)
+    srv = serve.Server(ex, budget_bytes=1 << 34, max_jobs=12, max_batch=4, keep_results=True)
+    rep = srv.run(reqs)
+    print("serving report with bitmap D2H", rep, flush=True)
+    assert rep["rejected"] == 0 and rep["batches"] > 1
+    for r in reqs:
+        res = srv.result(r.jid)
+        host = res["bitmap_host"]
+        assert not host.is_cuda and host.is_pinned()
+        alone = ctx.plot(r.x, r.y, r.w, threshold=r.threshold, want_plot=False)["bitmap"]
+        assert torch.equal(host, alone.cpu()), r.jid
+
+
 def test_sparse_serving_results_equal_alone(oracle_mod):
     """Serving with step sizes and dot lists instead of dense outputs: every
     job's dot list equals the job's own wlcs_pair_plot_strided list (sorted;
