@@ -150,6 +150,13 @@ constexpr int min_waves_per_simd_dl_split(int wc) { return wc <= 208 ? 3 : 2; }
 // LDS of the hand-over between the two waves: two buffers of four labels
 // per lane
 constexpr int kDlHandDwords = 2 * 4 * 64;
+// Plots in the 128-row class split every strip over two waves as well (the
+// upper and the lower half of the rows): one wave holding 128 rows needs all
+// 256 registers (two waves per SIMD), a half fits three.  (Halves of the
+// 256-row class spill inside the column loop at two waves per SIMD and ran
+// slower than one wave holding the whole strip.)
+constexpr bool general_split(int wc) { return wc == 128; }
+constexpr int min_waves_per_simd_split(int wc) { return wc <= 128 ? 3 : 2; }
 
 // Window capacity class of a window length: 16, 32, 64, 128 or 256.
 inline int w_class(int w) { return w <= 16 ? 16 : w <= 32 ? 32 : w <= 64 ? 64 : w <= 128 ? 128 : 256; }

@@ -100,6 +100,28 @@ __global__ __launch_bounds__(128, min_waves_per_simd_dl_split(WC)) void seaweed_
                                                  hand);
 }
 
+// Plots in the 128-row class: two waves per strip (the upper and the lower
+// half of the rows, see comb_unit), one unit per workgroup of 128.
+template <int WC, bool EXACT, bool SP>
+__global__ __launch_bounds__(128, min_waves_per_simd_split(WC)) void seaweed_kernel_rsplit(
+    const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32, uint8_t* __restrict__ out,
+    uint32_t* __restrict__ bm32, uint16_t* __restrict__ indel, DotRec* __restrict__ dots,
+    unsigned long long* __restrict__ dot_count, Geom g) {
+    __shared__ uint32_t ring[ring_words(WC) * 64];
+    __shared__ uint32_t stage[stage_dwords(WC, 1)];
+    __shared__ uint32_t hand[kDlHandDwords];
+    const int64_t nblocks = (g.rows + 63) / 64;
+    const int64_t unit = blockIdx.x;
+    const int pr = (int)(unit / nblocks);
+    const int64_t sb = unit - (int64_t)pr * nblocks;
+    if (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0)
+        comb_unit<WC, EXACT, 1, SP, false, 1>(xf, yg32, out, bm32, indel, dots, dot_count, g, sb, pr, ring, stage,
+                                               hand);
+    else
+        comb_unit<WC, EXACT, 1, SP, false, 2>(xf, yg32, out, bm32, indel, dots, dot_count, g, sb, pr, ring, stage,
+                                               hand);
+}
+
 __global__ void zero_u64(unsigned long long* p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
 }
@@ -107,12 +129,21 @@ __global__ void zero_u64(unsigned long long* p) {
 template <int WC, int WS, bool SP>
 void launch_ws(const PlotArgs& a, const Geom& g, uint32_t units, hipStream_t stream) {
     const uint32_t* yg32 = (const uint32_t*)a.yg;
-    if (a.w == WC)
-        hipLaunchKernelGGL((seaweed_kernel<WC, true, WS, SP>), dim3(units), dim3(64), 0, stream, a.xf, yg32, a.wlcs,
-                           a.bitmap32, a.indel, a.dots, a.dot_count, g);
-    else
-        hipLaunchKernelGGL((seaweed_kernel<WC, false, WS, SP>), dim3(units), dim3(64), 0, stream, a.xf, yg32, a.wlcs,
-                           a.bitmap32, a.indel, a.dots, a.dot_count, g);
+    if constexpr (WS == 1 && general_split(WC)) {
+        if (a.w == WC)
+            hipLaunchKernelGGL((seaweed_kernel_rsplit<WC, true, SP>), dim3(units), dim3(128), 0, stream, a.xf, yg32,
+                               a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+        else
+            hipLaunchKernelGGL((seaweed_kernel_rsplit<WC, false, SP>), dim3(units), dim3(128), 0, stream, a.xf, yg32,
+                               a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+    } else {
+        if (a.w == WC)
+            hipLaunchKernelGGL((seaweed_kernel<WC, true, WS, SP>), dim3(units), dim3(64), 0, stream, a.xf, yg32,
+                               a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+        else
+            hipLaunchKernelGGL((seaweed_kernel<WC, false, WS, SP>), dim3(units), dim3(64), 0, stream, a.xf, yg32,
+                               a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+    }
 }
 
 // score plots: the separator schedule in the class of the window rounded up

@@ -117,13 +117,13 @@ __device__ __forceinline__ void strided_flush(uint8_t* __restrict__ out, uint16_
 // The strip has WC / 2 pair slots; a window of w / 2 < WC / 2 pairs leaves the
 // top WC / 2 - w / 2 (< kDlSlots) slots unused.
 //
-// PART (DL only): 0 combs the whole strip in one wave.  With two waves per
-// strip, PART 1 (the upper wave) combs the upper pair slots and hands the
-// four labels leaving its last slot in each pair of passes to PART 2 (the
-// lower wave) through `hand` in LDS; PART 2 combs the lower slots one pair of
-// passes behind, counts and stores.  Both waves meet at one workgroup barrier
-// per pair of passes (the upper after writing, the lower before reading), and
-// the same sequence of pairs of passes in both makes the barriers match.
+// PART: 0 combs the whole strip in one wave.  With two waves per strip, PART
+// 1 (the upper wave) combs the upper rows (DL: pair slots) and hands the
+// labels leaving its last row to PART 2 (the lower wave) through `hand` in
+// LDS, four per group of columns (DL: per pair of passes); PART 2 combs the
+// lower rows one group behind, counts and stores.  Both waves meet at one
+// workgroup barrier per group (the upper after writing, the lower before
+// reading), and the same sequence of groups in both makes the barriers match.
 template <int WC, bool EXACT, int WS = 1, bool SP = false, bool DL = false, int PART = 0>
 __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32,
                                           uint8_t* __restrict__ out, uint32_t* __restrict__ bm32,
@@ -133,7 +133,8 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                                           uint32_t* __restrict__ hand = nullptr) {
     static_assert(!SP || WS == 1, "strided and sparse plots store single windows");
     static_assert(!DL || (WS == 2 && !EXACT && WC % (2 * kDlSlots) == 0), "the score-plot schedule");
-    static_assert(PART == 0 || (DL && dl_split(WC)), "two waves per strip: score plots above kDlSplitRows rows");
+    static_assert(PART == 0 || (DL ? dl_split(WC) : (WS == 1 && general_split(WC))),
+                  "two waves per strip: score plots above kDlSplitRows rows, other plots of 128 rows");
     constexpr bool UPPER = PART == 1;  // combs only: no count, no stores
     constexpr int RW = ring_words(WC);
     constexpr int FL = flush_windows(WC, WS);
@@ -161,11 +162,14 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     constexpr int S0 = PART == 2 ? dl_upper_slots(WC) : 0;
     constexpr int NS = PART == 0 ? NP : PART == 1 ? dl_upper_slots(WC) : NP - dl_upper_slots(WC);
     static_assert(NS % 2 == 0 && S0 >= (PART == 2 ? kDlSlots : 0), "slot split");
-    constexpr int HN = DL ? 2 * NS : WC;       // labels held by this wave
+    // general: this wave's rows, R0 .. R0 + NR - 1 of the strip
+    constexpr int R0 = (!DL && PART == 2) ? WC / 2 : 0;
+    constexpr int NR = (DL || PART == 0) ? WC : WC / 2;
+    constexpr int HN = DL ? 2 * NS : NR;       // labels held by this wave
     // x letters of this lane's strip, two rows per register (lanes past the
     // last strip comb a copy of the last one; their results are never stored);
     // DL: the letters of this wave's letter rows only, two slots per register
-    constexpr int NXC = DL ? NS / 2 : WC / 2;
+    constexpr int NXC = DL ? NS / 2 : NR / 2;
     uint32_t xc[NXC];
     {
         const int64_t sx = s0 + lane < g.rows ? s0 + lane : g.rows - 1;
@@ -179,9 +183,9 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                 lo = i0 >= 0 ? (uint32_t)xp[2 * i0 + 1] : PADF;
                 hi = i1 >= 0 ? (uint32_t)xp[2 * i1 + 1] : PADF;
             } else {
-                const int i0 = 2 * j - pad, i1 = 2 * j + 1 - pad;
-                lo = (EXACT || i0 >= 0) ? (uint32_t)xp[EXACT ? 2 * j : i0] : PADF;
-                hi = (EXACT || i1 >= 0) ? (uint32_t)xp[EXACT ? 2 * j + 1 : i1] : PADF;
+                const int i0 = R0 + 2 * j - pad, i1 = R0 + 2 * j + 1 - pad;
+                lo = (EXACT || i0 >= 0) ? (uint32_t)xp[EXACT ? R0 + 2 * j : i0] : PADF;
+                hi = (EXACT || i1 >= 0) ? (uint32_t)xp[EXACT ? R0 + 2 * j + 1 : i1] : PADF;
             }
             xc[j] = lo | (hi << 16);
         }
@@ -245,18 +249,51 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         return rem2;
     };
 
-    // Comb column l (tile-relative) through the w rows; returns the count
-    // (general schedule).
-    auto column = [&](int l) -> uint32_t {
+    // Comb column l (tile-relative) through this wave's rows (general
+    // schedule); returns the label leaving the last of them.  The upper rows
+    // start from the column's top label, the lower ones from t_in (the label
+    // the upper wave handed over).
+    auto comb_rows = [&](int l, uint32_t t_in) -> uint32_t {
         const uint32_t Y = ynext;
         ynext = yload(l + 1);
-        uint32_t t = seaweed_cell_top(h[0], pk_rep(l - org + 1), xc[0], Y);
+        uint32_t t = t_in;
+        if constexpr (R0 == 0) t = seaweed_cell_top(h[0], pk_rep(l - org + 1), xc[0], Y);
 #pragma unroll
-        for (int k = 1; k < WC; ++k) {
-            if (!EXACT && (k & 15) == 0 && k >= wpad) break;  // uniform, once per 16 rows
+        for (int k = R0 == 0 ? 1 : 0; k < NR; ++k) {
+            if (!EXACT && ((R0 + k) & 15) == 0 && R0 + k >= wpad) break;  // uniform, once per 16 rows
             t = (k & 1) ? seaweed_cell<1>(h[k], t, xc[k >> 1], Y) : seaweed_cell<0>(h[k], t, xc[k >> 1], Y);
         }
-        return count(l, t);
+        return t;
+    };
+    // One column through the whole strip; returns the count.
+    auto column = [&](int l) -> uint32_t { return count(l, comb_rows(l, 0u)); };
+    // Columns l0 .. l0 + n - 1 (n <= 4, uniform); returns the counts (of the
+    // columns there are) in r[].  With two waves per strip the upper wave hands
+    // the four exits over and returns nothing.
+    int hand_buf_g = 0;
+    auto group = [&](int l0, int n, uint32_t (&r)[4]) {
+        if constexpr (PART == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < n) r[i] = column(l0 + i);
+        } else {
+            uint32_t* const hb = hand + (hand_buf_g & 1) * 256 + lane;
+            ++hand_buf_g;
+            if constexpr (UPPER) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (i < n) hb[i * 64] = comb_rows(l0 + i, 0u);
+                __syncthreads();
+            } else {
+                __syncthreads();
+                uint32_t t_in[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) t_in[i] = hb[i * 64];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (i < n) r[i] = count(l0 + i, comb_rows(l0 + i, t_in[i]));
+            }
+        }
     };
 
     // DL: a pass down the pair slots combs the separator column c - 1 and
@@ -353,7 +390,8 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         for (; c + 2 <= w - 3; c += 4) (void)passes(c, P1{});
         if (c <= w - 3) (void)passes(c, P0{});
     } else {
-        for (int l = 0; l < w - 1; ++l) (void)column(l);
+        uint32_t r[4];
+        for (int l = 0; l < w - 1; l += 4) group(l, w - 1 - l < 4 ? w - 1 - l : 4, r);
     }
 
     // The staging block is this wave's alone: with two waves per strip the
@@ -389,10 +427,12 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                 r1 = r.c1;
                 r2 = r3 = r.c2;
             } else {
-                r0 = column(l);
-                r1 = column(l + 1);
-                r2 = column(l + 2);
-                r3 = column(l + 3);
+                uint32_t r[4] = {0u, 0u, 0u, 0u};
+                group(l, 4, r);
+                r0 = r[0];
+                r1 = r[1];
+                r2 = r[2];
+                r3 = r[3];
             }
             if constexpr (!UPPER) {
                 // bytes 0 (tile A) and 2 (tile B) of the four results, gathered
