@@ -159,9 +159,9 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     constexpr int NP = WC / 2;                 // DL: pair slots
     const int ppad = DL ? NP - w / 2 : 0;      // DL: unused slots at the top (< kDlSlots)
     // DL: this wave's pair slots, S0 .. S0 + NS - 1 of the strip
-    constexpr int S0 = PART == 2 ? dl_upper_slots(WC) : 0;
-    constexpr int NS = PART == 0 ? NP : PART == 1 ? dl_upper_slots(WC) : NP - dl_upper_slots(WC);
-    static_assert(NS % 2 == 0 && S0 >= (PART == 2 ? kDlSlots : 0), "slot split");
+    constexpr int S0 = (DL && PART == 2) ? dl_upper_slots(WC) : 0;
+    constexpr int NS = (!DL || PART == 0) ? NP : PART == 1 ? dl_upper_slots(WC) : NP - dl_upper_slots(WC);
+    static_assert(!DL || (NS % 2 == 0 && S0 >= (PART == 2 ? kDlSlots : 0)), "slot split");
     // general: this wave's rows, R0 .. R0 + NR - 1 of the strip
     constexpr int R0 = (!DL && PART == 2) ? WC / 2 : 0;
     constexpr int NR = (DL || PART == 0) ? WC : WC / 2;
