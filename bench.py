@@ -325,7 +325,7 @@ def main():
 
 
 def bench_batch(ctx, torch, workloads, reps=3):
-    """256 DNA pairs of uneven m, n and w in one persistent launch (eager and
+    """256 DNA pairs of uneven m, n and w in persistent launches (eager and
     graph-replayed), outputs preallocated, pairs resident."""
     import numpy as np
     pairs = workloads.batch_config()

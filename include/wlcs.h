@@ -245,10 +245,12 @@ int wlcs_pair_plot_dp_strided(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, i
                               int64_t dot_cap, uint64_t *dot_count, uint32_t flags, void *stream);
 
 /* ---- batched plots ------------------------------------------------------
- * Many plots of uneven m, n and w in one persistent, work-stealing launch: the
- * plots' units (64 x-windows against two y-tiles) go into one device-wide
- * queue that resident wavefronts drain (windows w <= 128; longer windows run
- * as separate launches on the same stream).  Each plot's outputs are exactly
+ * Many plots of uneven m, n and w in persistent, work-stealing launches: the
+ * plots' units (64 x-windows against two y-tiles) go into device-wide queues
+ * that resident wavefronts drain, one queue and launch per group of window
+ * classes (w <= 32, w <= 64, w <= 128: each group's kernel holds only its own
+ * classes' code and runs at that group's occupancy; longer windows run as
+ * separate launches on the same stream).  Each plot's outputs are exactly
  * those of wlcs_pair_plot with the same arguments. */
 typedef struct {
     const wlcs_pair *pair; /* resident strings (wlcs_pair_create on the same device) */
@@ -286,8 +288,10 @@ int wlcs_graph_destroy(wlcs_graph *graph); /* waits for the graph's device memor
 
 /* Batch tuning: y-windows per tile for batched plots of windows w_lo..w_hi
  * (multiple of 64, 64..32768; 0 restores the built-in choice, which aims at
- * equal work per unit: about 131072 / w windows), and the persistent grid
- * (workgroups per compute unit, 1..16; 0 restores the default 8). */
+ * equal work per unit: about 131072 / w windows), and the persistent grids
+ * (waves per compute unit, 1..16, for every group, the 128-row group in
+ * workgroups of two waves; 0 restores the default: each group's resident
+ * capacity, 16 waves per CU for w <= 32, 12 above). */
 int wlcs_ctx_set_batch_tile(wlcs_ctx *ctx, int32_t w_lo, int32_t w_hi, int32_t tile_windows);
 int wlcs_ctx_set_batch_grid(wlcs_ctx *ctx, int32_t waves_per_cu);
 
@@ -302,7 +306,7 @@ int wlcs_ctx_get_batch_grid(const wlcs_ctx *ctx, int32_t *waves_per_cu);
  * m, n in 1,000..16,000, 32 per class) on the context's device, and applied
  * to ctx with wlcs_ctx_set_batch_tile / wlcs_ctx_set_batch_grid.  The search
  * starts from the built-in choices and changes one knob at a time (each
- * class's tile in turn: 256..4096; then the grid: 4..16 workgroups per CU),
+ * class's tile in turn: 256..4096; then the grid: 4..16 waves per CU),
  * keeping a candidate only if the whole batch runs faster with it, so the
  * result never times slower than the built-in choices.  A knob left at its
  * built-in choice is stored as 0.

@@ -349,7 +349,7 @@ class Context:
         return arr, results
 
     def batch(self, specs, stream=None) -> list:
-        """All plots of specs in one persistent launch (wlcs_batch)."""
+        """All plots of specs in persistent work-stealing launches (wlcs_batch)."""
         lib = _load()
         arr, results = self._jobs(specs)
         stream = self._stream(stream)

@@ -4,7 +4,9 @@
 """
 from __future__ import annotations
 
+import json
 import os
+import re
 import subprocess
 import sys
 
@@ -23,19 +25,46 @@ FLAGS = [
 ]
 
 
+# the compiler's per-kernel resource report (registers, scratch, occupancy)
+REPORT = os.path.join(HERE, "kernel_resources.json")
+_REMARK = re.compile(r"remark: +(Function Name|VGPRs|AGPRs|SGPRs|ScratchSize \[bytes/lane\]|"
+                     r"Occupancy \[waves/SIMD\]|LDS Size \[bytes/block\]): (\S+)")
+_KEYS = {"VGPRs": "vgprs", "AGPRs": "agprs", "SGPRs": "sgprs", "ScratchSize [bytes/lane]": "scratch_bytes",
+         "Occupancy [waves/SIMD]": "waves_per_simd", "LDS Size [bytes/block]": "lds_bytes"}
+
+
+def parse_resources(text: str) -> dict:
+    """Kernel (mangled name) -> its resource figures, from the compiler's
+    kernel-resource-usage remarks."""
+    kernels, cur = {}, None
+    for m in _REMARK.finditer(text):
+        key, val = m.group(1), m.group(2)
+        if key == "Function Name":
+            cur = kernels.setdefault(val, {})
+        elif cur is not None:
+            cur[_KEYS[key]] = int(val)
+    return kernels
+
+
 def build(verbose: bool = False, extra: list | None = None, out: str = LIB) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = out + ".tmp"
-    cmd = [HIPCC, *FLAGS, *(extra or []), *srcs, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, "-Rpass-analysis=kernel-resource-usage", *(extra or []), *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libwlcs.so")
-    if verbose and r.stderr.strip():
-        sys.stderr.write(r.stderr)
+    other = "\n".join(ln for ln in r.stderr.splitlines()
+                      if "kernel-resource-usage" not in ln and ln.strip())
+    if verbose and other:
+        sys.stderr.write(other + "\n")
     os.replace(tmp, out)
+    if out == LIB:
+        with open(REPORT + ".tmp", "w") as f:
+            json.dump(parse_resources(r.stderr), f, indent=1, sort_keys=True)
+        os.replace(REPORT + ".tmp", REPORT)
     return out
 
 

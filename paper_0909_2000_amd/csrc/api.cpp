@@ -556,11 +556,14 @@ int32_t batch_tile(const wlcs_ctx* ctx, int64_t cols, int32_t w) {
 }
 
 struct BatchPlan {
-    std::vector<wlcs::JobDesc> table;  // jobs with w <= kBatchMaxW, by decreasing unit cost
-    std::vector<wlcs::PlotArgs> singles;  // longer windows: single-plot launches
-    std::vector<unsigned long long*> counts;  // every job's dot counter, zeroed first
-    int64_t total_units = 0;
-    bool sparse = false;  // some batched job is strided or lists dots
+    // jobs with w <= kBatchMaxW, by kernel group, then by decreasing unit cost
+    // within a group; a group's unit0 values count from its own first unit
+    std::vector<wlcs::JobDesc> table;
+    int32_t first[wlcs::kBatchGroups + 1] = {};  // table index of each group's first job
+    int64_t units[wlcs::kBatchGroups] = {};      // units of each group
+    bool sparse[wlcs::kBatchGroups] = {};        // some job of the group is strided or lists dots
+    std::vector<wlcs::PlotArgs> singles;         // longer windows: single-plot launches
+    std::vector<unsigned long long*> counts;     // every job's dot counter, zeroed first
 };
 
 int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& plan) {
@@ -618,38 +621,53 @@ int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& pl
         it.d.dots = a.dots;
         it.d.dot_count = a.dot_count;
         it.d.g = wlcs::geom_of(a);
-        if (hy > 1 || a.dot_count) plan.sparse = true;
         it.d.unit0 = (rows + 63) / 64 * a.npairs;  // unit count for now
         it.d.variant = wlcs::batch_variant(j.w);
         it.d.pad = 0;
         it.cost = 2.0 * (double)(a.tile + j.w - 1) * (double)j.w;
+        const int grp = wlcs::batch_group(it.d.variant);
+        if (hy > 1 || a.dot_count) plan.sparse[grp] = true;
         items.push_back(it);
     }
-    std::stable_sort(items.begin(), items.end(), [](const Item& p, const Item& q) { return p.cost > q.cost; });
-    int64_t u0 = 0;
-    for (Item& it : items) {
-        const int64_t units = it.d.unit0;
-        it.d.unit0 = u0;
-        u0 += units;
-        plan.table.push_back(it.d);
+    std::stable_sort(items.begin(), items.end(), [](const Item& p, const Item& q) {
+        const int gp = wlcs::batch_group(p.d.variant), gq = wlcs::batch_group(q.d.variant);
+        return gp != gq ? gp < gq : p.cost > q.cost;
+    });
+    for (const Item& it : items) {
+        const int grp = wlcs::batch_group(it.d.variant);
+        wlcs::JobDesc d = it.d;
+        const int64_t units = d.unit0;
+        d.unit0 = plan.units[grp];
+        plan.units[grp] += units;
+        plan.table.push_back(d);
+        plan.first[grp + 1] = (int32_t)plan.table.size();
     }
-    plan.total_units = u0;
+    for (int grp = 1; grp <= wlcs::kBatchGroups; ++grp)  // groups without jobs start where the last one ended
+        plan.first[grp] = std::max(plan.first[grp], plan.first[grp - 1]);
     return WLCS_OK;
 }
 
-int batch_grid(const wlcs_ctx* ctx, int64_t total_units) {
-    const int64_t per_cu = ctx->batch_waves_per_cu > 0 ? ctx->batch_waves_per_cu : wlcs::kBatchWavesPerCu;
-    return (int)std::min<int64_t>(total_units, (int64_t)ctx->cus * per_cu);
+// Workgroups of a group's persistent grid: the waves per CU set by
+// wlcs_ctx_set_batch_grid (else the group's resident capacity), two waves per
+// workgroup in the 128-row group.
+int batch_grid(const wlcs_ctx* ctx, int group, int64_t units) {
+    const int64_t waves = ctx->batch_waves_per_cu > 0 ? ctx->batch_waves_per_cu : wlcs::batch_waves_per_cu(group);
+    const int64_t per_cu = group == 2 ? std::max<int64_t>(1, waves / 2) : waves;
+    return (int)std::min<int64_t>(units, (int64_t)ctx->cus * per_cu);
 }
 
 // Enqueue a planned batch whose job table already sits at table_dev and the
-// list of its dot counters at counts_dev.
+// list of its dot counters at counts_dev; counters holds the groups' work
+// counters, 64 bytes apart.  The costliest group (128-row windows) runs first.
 hipError_t enqueue_batch(const wlcs_ctx* ctx, const BatchPlan& plan, const wlcs::JobDesc* table_dev,
-                         unsigned long long* counter, unsigned long long* const* counts_dev, hipStream_t stream) {
+                         unsigned long long* counters, unsigned long long* const* counts_dev, hipStream_t stream) {
     hipError_t e = wlcs::launch_zero_each(counts_dev, (int32_t)plan.counts.size(), stream);
-    if (e == hipSuccess && !plan.table.empty())
-        e = wlcs::launch_batch(table_dev, (int32_t)plan.table.size(), plan.total_units, counter,
-                               batch_grid(ctx, plan.total_units), plan.sparse, stream);
+    for (int grp = wlcs::kBatchGroups - 1; grp >= 0 && e == hipSuccess; --grp) {
+        const int32_t n = plan.first[grp + 1] - plan.first[grp];
+        if (n > 0)
+            e = wlcs::launch_batch(grp, table_dev + plan.first[grp], n, plan.units[grp], counters + 8 * grp,
+                                   batch_grid(ctx, grp, plan.units[grp]), plan.sparse[grp], stream);
+    }
     for (size_t k = 0; e == hipSuccess && k < plan.singles.size(); ++k) e = wlcs::launch_seaweed(plan.singles[k], stream);
     return e;
 }

@@ -1,15 +1,23 @@
-// Batched alignment plots: many pairs of uneven m, n and w in one persistent
-// launch.
+// Batched alignment plots: many pairs of uneven m, n and w in a few
+// persistent launches.
 //
 // The host builds a job table (one entry per plot: code arrays, geometry,
-// outputs, and the index of the job's first unit in one global unit list).  A
-// grid sized to the resident capacity of the device loops: each wave takes the
-// next unit index from a device-wide atomic counter (work stealing), finds its
-// job by binary search over the jobs' first-unit indices, and combs that unit
-// (64 strips x 2 y-tiles) with the same per-unit code as the single-plot
-// kernel.  Jobs are ordered by decreasing unit cost so the tail of the queue
-// holds the cheapest units.  Windows up to 128 run here; longer windows run
-// as separate single-plot launches on the same stream.
+// outputs, and the index of the job's first unit in its group's unit list).
+// Jobs fall into three groups by window class (up to 32 rows, 64 rows, 128
+// rows), and each group runs as one persistent launch of a kernel that holds
+// only its classes' unit code, so each runs at the occupancy of its own
+// largest class: four waves per SIMD up to 32 rows, three at 64 rows, and
+// the 128-row class with every strip split over two waves of a workgroup
+// (three waves per SIMD, as in the single-plot kernel) instead of two waves
+// per SIMD for a kernel that holds every class.  A grid sized to the
+// resident capacity of the device loops: each wave (split: workgroup) takes
+// the next unit index from a device-wide atomic counter (work stealing),
+// finds its job by binary search over the jobs' first-unit indices, and
+// combs that unit (64 strips x 2 y-tiles) with the same per-unit code as the
+// single-plot kernel.  Within a group, jobs are ordered by decreasing unit
+// cost so the tail of the queue holds the cheapest units.  Windows up to 128
+// run here; longer windows run as separate single-plot launches on the same
+// stream.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -18,48 +26,94 @@
 namespace wlcs {
 namespace {
 
-template <int WC, bool EXACT, bool SP>
-__device__ __forceinline__ void run_unit(const JobDesc& jd, int64_t local, uint32_t* ring, uint32_t* stage) {
+template <int WC, bool EXACT, bool SP, int PART = 0>
+__device__ __forceinline__ void run_unit(const JobDesc& jd, int64_t local, uint32_t* ring, uint32_t* stage,
+                                         uint32_t* hand = nullptr) {
     // pair-major within a job, as in the single-plot kernel
     const int64_t nblocks = (jd.g.rows + 63) / 64;
     const int pr = (int)(local / nblocks);
     const int64_t sb = local - (int64_t)pr * nblocks;
-    comb_unit<WC, EXACT, 1, SP>(jd.xf, jd.yg32, jd.out, jd.bm32, jd.indel, SP ? jd.dots : nullptr,
-                                SP ? jd.dot_count : nullptr, jd.g, sb, pr, ring, stage);
+    comb_unit<WC, EXACT, 1, SP, false, PART>(jd.xf, jd.yg32, jd.out, jd.bm32, jd.indel, SP ? jd.dots : nullptr,
+                                             SP ? jd.dot_count : nullptr, jd.g, sb, pr, ring, stage, hand);
 }
 
-template <bool SP>
-__global__ __launch_bounds__(64, 2) void batch_kernel(const JobDesc* __restrict__ jobs, int32_t njobs,
-                                                      int64_t total_units, unsigned long long* __restrict__ counter) {
-    __shared__ uint32_t ring[ring_words(128) * 64];
-    __shared__ uint32_t stage[stage_dwords(128)];
+// the job whose unit range holds u (jobs[k].unit0 ascending, jobs[0].unit0 == 0)
+__device__ __forceinline__ int find_job(const JobDesc* __restrict__ jobs, int32_t njobs, int64_t u) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].unit0 <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t uniform_u64(unsigned long long v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (int64_t)(((unsigned long long)hi << 32) | lo);
+}
+
+constexpr int group_waves_per_simd(int grp) { return grp == 0 ? min_waves_per_simd(32) : min_waves_per_simd(64); }
+constexpr int group_class(int grp) { return grp == 0 ? 32 : 64; }
+
+// Groups 0 (classes 16 and 32) and 1 (class 64): one wave per unit.
+template <int GRP, bool SP>
+__global__ __launch_bounds__(64, group_waves_per_simd(GRP)) void batch_kernel(const JobDesc* __restrict__ jobs,
+                                                                             int32_t njobs, int64_t total_units,
+                                                                             unsigned long long* __restrict__ counter) {
+    __shared__ uint32_t ring[ring_words(group_class(GRP)) * 64];
+    __shared__ uint32_t stage[stage_dwords(group_class(GRP))];
     const int lane = threadIdx.x;
     for (;;) {
-        uint32_t ulo = 0, uhi = 0;
-        if (lane == 0) {
-            const unsigned long long v = atomicAdd(counter, 1ull);
-            ulo = (uint32_t)v;
-            uhi = (uint32_t)(v >> 32);
+        unsigned long long v = 0;
+        if (lane == 0) v = atomicAdd(counter, 1ull);
+        const int64_t u = uniform_u64(v);  // lane 0 holds the ticket
+        if (u >= total_units) break;       // queue drained: every wave leaves
+        const JobDesc jd = jobs[find_job(jobs, njobs, u)];
+        const int64_t local = u - jd.unit0;
+        if constexpr (GRP == 0) {
+            switch (jd.variant) {
+                case kBatch16: run_unit<16, true, SP>(jd, local, ring, stage); break;
+                case kBatch16Short: run_unit<16, false, SP>(jd, local, ring, stage); break;
+                case kBatch32: run_unit<32, true, SP>(jd, local, ring, stage); break;
+                default: run_unit<32, false, SP>(jd, local, ring, stage); break;
+            }
+        } else {
+            if (jd.variant == kBatch64) run_unit<64, true, SP>(jd, local, ring, stage);
+            else run_unit<64, false, SP>(jd, local, ring, stage);
         }
-        // lane 0 holds the ticket; make it wave-uniform (scalar registers)
-        const unsigned long long u = ((unsigned long long)__builtin_amdgcn_readfirstlane(uhi) << 32) |
-                                     __builtin_amdgcn_readfirstlane(ulo);
-        if ((int64_t)u >= total_units) break;  // queue drained: every wave leaves
-        // job whose unit range holds u (jobs[k].unit0 ascending)
-        int lo = 0, hi = njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (jobs[mid].unit0 <= (int64_t)u) lo = mid;
-            else hi = mid - 1;
-        }
-        const JobDesc jd = jobs[lo];
-        const int64_t local = (int64_t)u - jd.unit0;
-        switch (jd.variant) {
-            case 0: run_unit<16, true, SP>(jd, local, ring, stage); break;
-            case 1: run_unit<32, true, SP>(jd, local, ring, stage); break;
-            case 2: run_unit<64, true, SP>(jd, local, ring, stage); break;
-            case 3: run_unit<128, true, SP>(jd, local, ring, stage); break;
-            default: run_unit<128, false, SP>(jd, local, ring, stage); break;
+    }
+}
+
+// Group 2 (class 128): every unit on the two waves of a workgroup, the upper
+// rows on wave 0 and the lower rows on wave 1.  Wave 0 takes the ticket and
+// passes it on through LDS.  The barrier after each ticket is written also
+// keeps the units apart: wave 0 starts a unit only once wave 1 has left the
+// previous one (its flushes and LDS ring included).  The ticket slot
+// alternates, so a ticket is never overwritten before wave 1 has read it.
+template <bool SP>
+__global__ __launch_bounds__(128, min_waves_per_simd_split(128)) void batch_kernel_split(
+    const JobDesc* __restrict__ jobs, int32_t njobs, int64_t total_units, unsigned long long* __restrict__ counter) {
+    __shared__ uint32_t ring[ring_words(128) * 64];
+    __shared__ uint32_t stage[stage_dwords(128, 1)];
+    __shared__ uint32_t hand[kDlHandDwords];
+    __shared__ unsigned long long ticket[2];
+    const bool upper = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0;
+    for (int slot = 0;; slot ^= 1) {
+        if (threadIdx.x == 0) ticket[slot] = atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t u = uniform_u64(ticket[slot]);
+        if (u >= total_units) break;  // the same ticket in both waves: both leave
+        const JobDesc jd = jobs[find_job(jobs, njobs, u)];
+        const int64_t local = u - jd.unit0;
+        const bool exact = jd.variant == kBatch128;
+        if (upper) {
+            if (exact) run_unit<128, true, SP, 1>(jd, local, ring, stage, hand);
+            else run_unit<128, false, SP, 1>(jd, local, ring, stage, hand);
+        } else {
+            if (exact) run_unit<128, true, SP, 2>(jd, local, ring, stage, hand);
+            else run_unit<128, false, SP, 2>(jd, local, ring, stage, hand);
         }
     }
 }
@@ -72,30 +126,56 @@ __global__ void zero_each(unsigned long long* const* __restrict__ ptrs, int32_t 
     for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) *ptrs[k] = 0ull;
 }
 
-}  // namespace
-
-int batch_variant(int w) {
-    switch (w) {
-        case 16: return 0;
-        case 32: return 1;
-        case 64: return 2;
-        case 128: return 3;
-        default: return 4;  // any other w <= 128
+template <int GRP>
+void launch_group(const JobDesc* jobs_dev, int32_t njobs, int64_t total_units, unsigned long long* counter,
+                  int32_t grid, bool sparse, hipStream_t stream) {
+    if constexpr (GRP == 2) {
+        if (sparse)
+            hipLaunchKernelGGL(batch_kernel_split<true>, dim3((uint32_t)grid), dim3(128), 0, stream, jobs_dev, njobs,
+                               total_units, counter);
+        else
+            hipLaunchKernelGGL(batch_kernel_split<false>, dim3((uint32_t)grid), dim3(128), 0, stream, jobs_dev, njobs,
+                               total_units, counter);
+    } else {
+        if (sparse)
+            hipLaunchKernelGGL((batch_kernel<GRP, true>), dim3((uint32_t)grid), dim3(64), 0, stream, jobs_dev, njobs,
+                               total_units, counter);
+        else
+            hipLaunchKernelGGL((batch_kernel<GRP, false>), dim3((uint32_t)grid), dim3(64), 0, stream, jobs_dev, njobs,
+                               total_units, counter);
     }
 }
 
-hipError_t launch_batch(const JobDesc* jobs_dev, int32_t njobs, int64_t total_units, unsigned long long* counter,
-                        int32_t grid, bool sparse, hipStream_t stream) {
+}  // namespace
+
+int batch_variant(int w) {
+    switch (w_class(w)) {
+        case 16: return w == 16 ? kBatch16 : kBatch16Short;
+        case 32: return w == 32 ? kBatch32 : kBatch32Short;
+        case 64: return w == 64 ? kBatch64 : kBatch64Short;
+        default: return w == 128 ? kBatch128 : kBatch128Short;  // w <= kBatchMaxW
+    }
+}
+
+int batch_waves_per_cu(int group) {
+    const int per_simd = group == 0   ? group_waves_per_simd(0)
+                         : group == 1 ? group_waves_per_simd(1)
+                                      : min_waves_per_simd_split(128);
+    return 4 * per_simd;  // four SIMDs per CU
+}
+
+hipError_t launch_batch(int group, const JobDesc* jobs_dev, int32_t njobs, int64_t total_units,
+                        unsigned long long* counter, int32_t grid, bool sparse, hipStream_t stream) {
     if (total_units <= 0 || njobs <= 0) return hipSuccess;
+    if (group < 0 || group >= kBatchGroups || grid <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(zero_counter, dim3(1), dim3(64), 0, stream, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (sparse)
-        hipLaunchKernelGGL(batch_kernel<true>, dim3((uint32_t)grid), dim3(64), 0, stream, jobs_dev, njobs,
-                           total_units, counter);
-    else
-        hipLaunchKernelGGL(batch_kernel<false>, dim3((uint32_t)grid), dim3(64), 0, stream, jobs_dev, njobs,
-                           total_units, counter);
+    switch (group) {
+        case 0: launch_group<0>(jobs_dev, njobs, total_units, counter, grid, sparse, stream); break;
+        case 1: launch_group<1>(jobs_dev, njobs, total_units, counter, grid, sparse, stream); break;
+        default: launch_group<2>(jobs_dev, njobs, total_units, counter, grid, sparse, stream); break;
+    }
     return hipGetLastError();
 }
 

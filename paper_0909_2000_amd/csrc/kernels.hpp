@@ -169,12 +169,24 @@ hipError_t launch_dp(const PlotArgs& a, hipStream_t stream);
 hipError_t launch_blcs(const PlotArgs& a, hipStream_t stream);
 // bitmap, indel and dot list of a finished plot (at wout, row stride ldo)
 hipError_t launch_epilogue(const PlotArgs& a, const uint8_t* wout, int64_t ldo, hipStream_t stream);
+// Per-unit code paths of the batched kernels: a window class, and whether
+// the window fills it (exact) or is shorter (padded strip).
+enum BatchVariant {
+    kBatch16, kBatch16Short, kBatch32, kBatch32Short,  // group 0
+    kBatch64, kBatch64Short,                           // group 1
+    kBatch128, kBatch128Short,                         // group 2 (two waves per strip)
+};
+constexpr int kBatchGroups = 3;
+constexpr int batch_group(int variant) { return variant <= kBatch32Short ? 0 : variant <= kBatch64Short ? 1 : 2; }
 int batch_variant(int w);
-constexpr int kBatchMaxW = 128;            // longer windows leave the batched kernel
-constexpr int kBatchWavesPerCu = 8;        // resident waves per CU of batch_kernel
+// resident waves per CU of a group's kernel (the default persistent grid)
+int batch_waves_per_cu(int group);
+constexpr int kBatchMaxW = 128;            // longer windows leave the batched kernels
+// One group's persistent launch over its njobs table entries (unit0 counted
+// from the group's first unit), grid workgroups (group 2: two waves each).
 // sparse: some job stores strided windows or lists dots (the kernel variant
-// with those flushes)
-hipError_t launch_batch(const JobDesc* jobs_dev, int32_t njobs, int64_t total_units,
+// with those flushes).  The counter is zeroed first by a kernel of its own.
+hipError_t launch_batch(int group, const JobDesc* jobs_dev, int32_t njobs, int64_t total_units,
                         unsigned long long* counter, int32_t grid, bool sparse, hipStream_t stream);
 // *ptrs[k] = 0 for k < n
 hipError_t launch_zero_each(unsigned long long* const* ptrs, int32_t n, hipStream_t stream);

@@ -43,7 +43,7 @@ struct wlcs_ctx {
     int nrules = 0;
     wlcs_rt::TileRule batch_rules[16];
     int nbatch_rules = 0;
-    int batch_waves_per_cu = 0;  // 0: kBatchWavesPerCu
+    int batch_waves_per_cu = 0;  // 0: each batched kernel's resident capacity
     wlcs_rt::TileChoice tile_cache[wlcs_rt::kTileCache];  // recent built-in tilings
     int tile_cache_next = 0;
 };

@@ -137,12 +137,15 @@ void launch_ws(const PlotArgs& a, const Geom& g, uint32_t units, hipStream_t str
             hipLaunchKernelGGL((seaweed_kernel_rsplit<WC, false, SP>), dim3(units), dim3(128), 0, stream, a.xf, yg32,
                                a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
     } else {
-        if (a.w == WC)
-            hipLaunchKernelGGL((seaweed_kernel<WC, true, WS, SP>), dim3(units), dim3(64), 0, stream, a.xf, yg32,
-                               a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
-        else
-            hipLaunchKernelGGL((seaweed_kernel<WC, false, WS, SP>), dim3(units), dim3(64), 0, stream, a.xf, yg32,
-                               a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+        if constexpr (WC < 256) {  // windows are at most 255 long: none fills the 256-row class
+            if (a.w == WC) {
+                hipLaunchKernelGGL((seaweed_kernel<WC, true, WS, SP>), dim3(units), dim3(64), 0, stream, a.xf, yg32,
+                                   a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((seaweed_kernel<WC, false, WS, SP>), dim3(units), dim3(64), 0, stream, a.xf, yg32,
+                           a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
     }
 }
 

@@ -267,16 +267,15 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     };
     // One column through the whole strip; returns the count.
     auto column = [&](int l) -> uint32_t { return count(l, comb_rows(l, 0u)); };
-    // Columns l0 .. l0 + n - 1 (n <= 4, uniform); returns the counts (of the
-    // columns there are) in r[].  With two waves per strip the upper wave hands
-    // the four exits over and returns nothing.
+    // Two waves per strip: columns l0 .. l0 + n - 1 (n <= 4, uniform).  The
+    // upper wave hands the four exits over and returns nothing; the lower
+    // wave returns the counts (of the columns there are) in r[].  (One wave
+    // per strip combs column by column: grouping its columns would inline four
+    // copies of a whole strip per call site, which at 256 rows no longer
+    // unrolls and puts the label arrays in scratch memory.)
     int hand_buf_g = 0;
     auto group = [&](int l0, int n, uint32_t (&r)[4]) {
-        if constexpr (PART == 0) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (i < n) r[i] = column(l0 + i);
-        } else {
+        if constexpr (PART != 0) {
             uint32_t* const hb = hand + (hand_buf_g & 1) * 256 + lane;
             ++hand_buf_g;
             if constexpr (UPPER) {
@@ -389,6 +388,8 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         int c = 1;
         for (; c + 2 <= w - 3; c += 4) (void)passes(c, P1{});
         if (c <= w - 3) (void)passes(c, P0{});
+    } else if constexpr (PART == 0) {
+        for (int l = 0; l < w - 1; ++l) (void)column(l);
     } else {
         uint32_t r[4];
         for (int l = 0; l < w - 1; l += 4) group(l, w - 1 - l < 4 ? w - 1 - l : 4, r);
@@ -426,6 +427,11 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                 r0 = r.c0;
                 r1 = r.c1;
                 r2 = r3 = r.c2;
+            } else if constexpr (PART == 0) {
+                r0 = column(l);
+                r1 = column(l + 1);
+                r2 = column(l + 2);
+                r3 = column(l + 3);
             } else {
                 uint32_t r[4] = {0u, 0u, 0u, 0u};
                 group(l, 4, r);

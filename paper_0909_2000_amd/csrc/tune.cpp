@@ -1,11 +1,11 @@
 // Tuner of the batched launch (wlcs_tune in include/wlcs.h).
 //
-// Two knobs decide how the persistent batched kernel cuts its work: the
+// Two knobs decide how the persistent batched kernels cut their work: the
 // y-windows per tile of each window class (a wave combs 64 x-windows against
 // two tiles, so longer tiles spend less of their columns on the w - 1 warm-up
 // columns that every tile restart costs, while shorter tiles give more units
-// and balance the queue better), and the resident workgroups per compute unit
-// of the persistent grid.  The tuner times real batched launches on the
+// and balance the queue better), and the waves per compute unit of the
+// persistent grids.  The tuner times real batched launches on the
 // context's device for every candidate, keeps the fastest, applies the result
 // to the context and stores it in a JSON cache keyed by device, which later
 // calls load instead of timing again:
@@ -293,7 +293,7 @@ bool write_file(const char* path, const std::string& text) {
 
 // candidates; 0 stands for the built-in choice, where the search starts
 constexpr int32_t kTiles[] = {0, 256, 512, 1024, 2048, 4096};
-constexpr int32_t kGrids[] = {0, 4, 6, 12, 16};
+constexpr int32_t kGrids[] = {0, 4, 6, 8, 16};
 constexpr int32_t kClasses[4][2] = {{1, 16}, {17, 32}, {33, 64}, {65, 128}};
 constexpr int kPairs = 128;  // 32 per window class
 constexpr int64_t kMinLen = 1000, kMaxLen = 16000;
@@ -403,9 +403,9 @@ int run_tuning(wlcs_ctx* ctx, JVal& entry) {
         if (st == WLCS_OK) st = wlcs_ctx_set_batch_grid(ctx, 0);
         double default_ms = 0.0;
         if (st == WLCS_OK) st = time_batch(ctx, wl.jobs, stream, a, b, default_ms);
-        // coordinate descent on the time of the whole batch (the classes
-        // share one queue, so a class's tile is judged by what it does to
-        // all of it): each class's tile in turn, then the grid; a candidate
+        // coordinate descent on the time of the whole batch (a class's tile
+        // is judged by what it does to all of it, its group's queue tail
+        // included): each class's tile in turn, then the grid; a candidate
         // is kept only if it beats the best so far, so the result is never
         // slower than the built-in choices on this batch
         double tuned_ms = default_ms;

@@ -7,7 +7,7 @@ dense bitmap, the list of dots at or above the threshold, which holds far
 fewer bytes than the dense outputs of a large plot).  The server keeps a FIFO of waiting jobs
 and admits the head while its device footprint (resident letter codes plus
 its outputs) fits the memory budget and a job slot is free.  Admitted jobs
-are launched together as one batch (one persistent work-stealing launch,
+are launched together as one batch (persistent work-stealing launches,
 ``wlcs_batch``) on one of several streams, so jobs that arrive while earlier
 batches run start on a free stream and overlap them on the device; a batch's
 completion frees its footprint and slots, which admits more jobs.  Latency is

@@ -14,7 +14,7 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 TILES = {0, 256, 512, 1024, 2048, 4096}  # 0: the built-in choice
-GRIDS = {0, 4, 6, 12, 16}
+GRIDS = {0, 4, 6, 8, 16}
 CLASSES = ("1-16", "17-32", "33-64", "65-128")
 
 
