@@ -570,7 +570,8 @@ int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& pl
     if (!ctx || njobs < 0 || (njobs > 0 && !jobs)) return WLCS_EINVAL;
     struct Item {
         wlcs::JobDesc d;
-        double cost;
+        double cost;  // of one unit
+        bool last;    // the job's last tile pair
     };
     std::vector<Item> items;
     for (int32_t k = 0; k < njobs; ++k) {
@@ -621,18 +622,33 @@ int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& pl
         it.d.dots = a.dots;
         it.d.dot_count = a.dot_count;
         it.d.g = wlcs::geom_of(a);
-        it.d.unit0 = (rows + 63) / 64 * a.npairs;  // unit count for now
         it.d.variant = wlcs::batch_variant(j.w);
-        it.d.pad = 0;
-        it.cost = 2.0 * (double)(a.tile + j.w - 1) * (double)j.w;
         const int grp = wlcs::batch_group(it.d.variant);
         if (hy > 1 || a.dot_count) plan.sparse[grp] = true;
+        const int64_t nblocks = (rows + 63) / 64;
+        // the pairs before the last one (full tiles), then the last pair
+        if (a.npairs > 1) {
+            it.d.unit0 = nblocks * (a.npairs - 1);  // unit count for now
+            it.d.pr0 = 0;
+            it.last = false;
+            it.cost = 2.0 * (double)(a.tile + j.w - 1) * (double)j.w;
+            items.push_back(it);
+        }
+        int64_t start;
+        const int64_t tlast = wlcs::pair_tile(cols, a.tile, a.tile, 0, a.npairs - 1, &start);
+        it.d.unit0 = nblocks;
+        it.d.pr0 = a.npairs - 1;
+        it.last = true;
+        it.cost = 2.0 * (double)(tlast + j.w - 1) * (double)j.w;
         items.push_back(it);
     }
     std::stable_sort(items.begin(), items.end(), [](const Item& p, const Item& q) {
         const int gp = wlcs::batch_group(p.d.variant), gq = wlcs::batch_group(q.d.variant);
-        return gp != gq ? gp < gq : p.cost > q.cost;
+        if (gp != gq) return gp < gq;
+        if (p.last != q.last) return q.last;
+        return p.cost > q.cost;
     });
+    if (items.size() > 0x7FFFFFFF) return WLCS_ERANGE;  // table entries are counted in int32
     for (const Item& it : items) {
         const int grp = wlcs::batch_group(it.d.variant);
         wlcs::JobDesc d = it.d;

@@ -14,8 +14,10 @@
 // the next unit index from a device-wide atomic counter (work stealing),
 // finds its job by binary search over the jobs' first-unit indices, and
 // combs that unit (64 strips x 2 y-tiles) with the same per-unit code as the
-// single-plot kernel.  Within a group, jobs are ordered by decreasing unit
-// cost so the tail of the queue holds the cheapest units.  Windows up to 128
+// single-plot kernel.  Within a group, every job's tile pairs but the last
+// come first, by decreasing unit cost, then the jobs' last pairs (each split
+// evenly over its two tiles, so usually shorter), again by decreasing cost:
+// the tail of the queue holds the cheapest units.  Windows up to 128
 // run here; longer windows run as separate single-plot launches on the same
 // stream.
 #include <algorithm>
@@ -29,10 +31,12 @@ namespace {
 template <int WC, bool EXACT, bool SP, int PART = 0>
 __device__ __forceinline__ void run_unit(const JobDesc& jd, int64_t local, uint32_t* ring, uint32_t* stage,
                                          uint32_t* hand = nullptr) {
-    // pair-major within a job, as in the single-plot kernel
+    // pair-major within an entry, as in the single-plot kernel: unit local
+    // is strip block local % nblocks of the entry's pair local / nblocks
     const int64_t nblocks = (jd.g.rows + 63) / 64;
-    const int pr = (int)(local / nblocks);
-    const int64_t sb = local - (int64_t)pr * nblocks;
+    const int64_t q = local / nblocks;
+    const int64_t sb = local - q * nblocks;
+    const int pr = jd.pr0 + (int)q;
     comb_unit<WC, EXACT, 1, SP, false, PART>(jd.xf, jd.yg32, jd.out, jd.bm32, jd.indel, SP ? jd.dots : nullptr,
                                              SP ? jd.dot_count : nullptr, jd.g, sb, pr, ring, stage, hand);
 }

@@ -124,9 +124,9 @@ struct JobDesc {
     DotRec* dots;
     unsigned long long* dot_count;
     Geom g;
-    int64_t unit0;    // index of the job's first unit in the global unit list
+    int64_t unit0;    // index of the entry's first unit in its group's unit list
     int32_t variant;  // per-unit code path (batch_variant)
-    int32_t pad;
+    int32_t pr0;      // the entry's first tile pair (a job's last pair is an entry of its own)
 };
 
 // Score-plot classes (the separator schedule of the seaweed kernel).  Waves

@@ -236,3 +236,48 @@ def test_strided_and_sparse_jobs_equal_alone(oracle_mod):
             c.fill_(999)
         torch.cuda.synchronize()
     graph.close()
+
+
+@pytest.mark.parametrize("ws", [(16, 9), (32, 20), (64, 40), (128, 100), (16, 128), (64, 200), (255,)])
+def test_batch_group_subsets_vs_oracle(ctx, oracle_mod, ws):
+    """Jobs in only some of the three kernel groups (windows up to 32, up to
+    64, up to 128; 200 and 255 run alone): the groups without jobs launch
+    nothing and the others still see only their own jobs."""
+    specs, inputs = _mixed_specs(ctx, 60 + sum(ws), 2 * len(ws) + 1, 20, 300, ws)
+    _say(f"batch of windows {ws}")
+    results = ctx.batch(specs)
+    for res, spec, (x, y, w) in zip(results, specs, inputs):
+        _check_vs_oracle(oracle_mod, res, spec, x, y, w)
+
+
+def test_sparse_job_in_one_group_only(oracle_mod):
+    """A dot-listing strided job among plain jobs of the other groups: only its
+    group runs the strided/sparse kernel variant; every job equals the oracle."""
+    import torch
+    import paper_0909_2000_amd as wl
+    g = workloads.rng(61)
+    ctx = wl.Context(0)
+    for sparse_w in (16, 64, 100):
+        specs, inputs = [], []
+        for w in (16, 30, 64, 50, 128, 90):
+            m, n = int(g.integers(300, 900)) + w, int(g.integers(300, 900)) + w
+            x, y = workloads.iid(g, m, workloads.DNA), workloads.iid(g, n, workloads.DNA)
+            specs.append({"pair": ctx.pair(x, y), "w": w})
+            inputs.append((x, y, w))
+        m, n = 1200 + sparse_w, 1100 + sparse_w
+        x, y = workloads.iid(g, m, workloads.DNA), workloads.iid(g, n, workloads.DNA)
+        y[200:200 + 2 * sparse_w] = x[100:100 + 2 * sparse_w]  # a homology, so the list is not empty
+        thr = (3 * sparse_w + 3) // 4
+        specs.append({"pair": ctx.pair(x, y), "w": sparse_w, "hx": 3, "hy": 2, "threshold": thr,
+                      "dot_cap": 50000})
+        _say(f"sparse job w={sparse_w} among plain jobs")
+        res = ctx.batch(specs)
+        torch.cuda.synchronize()
+        for r, (xx, yy, w) in zip(res[:-1], inputs):
+            np.testing.assert_array_equal(_np(r["wlcs"]), oracle_mod.wlcs(xx, yy, w))
+        want = oracle_mod.wlcs_strided(x, y, sparse_w, 3, 2)
+        np.testing.assert_array_equal(_np(res[-1]["wlcs"]), want)
+        dots, count = wl.dot_records(res[-1])
+        ref = oracle_mod.dot_list(want, sparse_w, thr, 3, 2)
+        assert count == ref.size > 0
+        np.testing.assert_array_equal(dots.view(np.uint8), ref.view(np.uint8))
