@@ -332,6 +332,44 @@ int wlcs_ctx_get_batch_grid(const wlcs_ctx *ctx, int32_t *waves_per_cu);
 #define WLCS_TUNE_FORCE 1u
 int wlcs_tune(wlcs_ctx *ctx, const char *cache_path, uint32_t flags);
 
+/* Tiling tuner of one plot shape: times the seaweed kernel on `pair` (window
+ * w, every hx-th x-window, every y-window; flags 0 or WLCS_FULL_RANGE, as in
+ * wlcs_pair_plot_strided) under a coarse grid of tilings (long tiles of
+ * 256..6144 windows for a count of leading pairs, short tiles of 128..1024
+ * after them, or one length), then around the fastest of them, then times
+ * the three fastest and the built-in choice again with more launches and
+ * keeps the fastest.  The result is recorded in ctx for the shape (rows,
+ * cols, w) and then applies to every plot of that shape made through ctx
+ * (wlcs_pair_plot, wlcs_plot, their strided forms; not score plots), ahead
+ * of the built-in tile model and behind tile rules (wlcs_ctx_set_tile(s)).
+ * The built-in tile model scores tilings by a schedule of equal slots; this
+ * measures them on the device instead.
+ *
+ *   cache_path  the JSON cache of wlcs_tune (NULL: tune, apply, write
+ *               nothing).  The device's entry holds "plots": {"RxCxW":
+ *               [long_tile, short_tile, long_pairs]} (0, 0, 0: the built-in
+ *               choice was the fastest) and the times in "plots_ms".  If it
+ *               holds this shape, that tiling is applied and nothing is timed;
+ *               otherwise the result is added (the entry's other members are
+ *               kept; wlcs_tune completes an entry that has no batch knobs yet
+ *               and keeps its plot tilings).
+ *   tune_flags  0, or WLCS_TUNE_FORCE to time even when the cache has the
+ *               shape (its record is then replaced).
+ *
+ * Synchronous: returns when the timed plots have completed (a few seconds for
+ * a 50,000 x 50,000 plot); rows x cols bytes of device memory are taken and
+ * released.  Errors as for wlcs_tune, plus WLCS_ERANGE for w outside
+ * 1..WLCS_MAX_W or hx < 1.  An empty plot returns WLCS_OK at once.  Tiling
+ * does not change any result (Theorem 3.1 holds for every tile). */
+int wlcs_tune_plot(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, int32_t hx, uint32_t flags,
+                   const char *cache_path, uint32_t tune_flags);
+
+/* The measured tiling that applies to plots of rows x cols windows of length
+ * w (rows counted after the x-step), from wlcs_tune_plot or a loaded cache;
+ * all three 0 if none (the built-in choice applies). */
+int wlcs_ctx_get_plot_tiling(const wlcs_ctx *ctx, int64_t rows, int64_t cols, int32_t w, int32_t *long_tile,
+                             int32_t *short_tile, int32_t *long_pairs);
+
 #ifdef __cplusplus
 }
 #endif

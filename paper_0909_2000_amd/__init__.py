@@ -105,6 +105,9 @@ def _load():
     lib.wlcs_ctx_get_batch_tile.argtypes = [vp, i32, ctypes.POINTER(i32)]
     lib.wlcs_ctx_get_batch_grid.argtypes = [vp, ctypes.POINTER(i32)]
     lib.wlcs_tune.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint32]
+    lib.wlcs_tune_plot.argtypes = [vp, vp, i32, i32, ctypes.c_uint32, ctypes.c_char_p, ctypes.c_uint32]
+    lib.wlcs_ctx_get_plot_tiling.argtypes = [vp, i64, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                             ctypes.POINTER(i32)]
     strided_args = [vp, vp, i32, i32, i32, vp, i64, vp, i64, i32, vp, i64, vp, i64, vp, ctypes.c_uint32, vp]
     lib.wlcs_pair_plot_strided.argtypes = strided_args
     lib.wlcs_pair_plot_dp_strided.argtypes = strided_args
@@ -115,7 +118,7 @@ def _load():
               "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
               "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
               "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs",
-              "wlcs_pair_plot_blcs"):
+              "wlcs_pair_plot_blcs", "wlcs_tune_plot", "wlcs_ctx_get_plot_tiling"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -128,7 +131,8 @@ def exported_symbols() -> list:
             "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch",
             "wlcs_batch_graph", "wlcs_graph_launch", "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
             "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
-            "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs", "wlcs_pair_plot_blcs"]
+            "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs", "wlcs_pair_plot_blcs",
+            "wlcs_tune_plot", "wlcs_ctx_get_plot_tiling"]
 
 
 # the wlcs_dot record
@@ -302,6 +306,27 @@ class Context:
         st = lib.wlcs_tune(self._h, path, WLCS_TUNE_FORCE if force else 0)
         if st != 0:
             raise WlcsError(st, "wlcs_tune", lib.wlcs_ctx_last_hip_error(self._h))
+
+    def tune_plot(self, pair, w: int, hx: int = 1, full_range: bool = False, cache_path: str | None = None,
+                  force: bool = False):
+        """wlcs_tune_plot: measure the fastest tiling of this plot shape on the
+        device (or apply the one recorded in the cache) for the plots of that
+        shape made through this context."""
+        lib = _load()
+        path = os.fsencode(cache_path) if cache_path is not None else None
+        st = lib.wlcs_tune_plot(self._h, pair._h, w, hx, WLCS_FULL_RANGE if full_range else 0, path,
+                                WLCS_TUNE_FORCE if force else 0)
+        if st != 0:
+            raise WlcsError(st, "wlcs_tune_plot", lib.wlcs_ctx_last_hip_error(self._h))
+
+    def plot_tiling(self, rows: int, cols: int, w: int) -> tuple:
+        """The measured tiling (long tile, short tile, long pairs) that applies
+        to plots of rows x cols windows of length w; (0, 0, 0) if none."""
+        vals = [ctypes.c_int32(0) for _ in range(3)]
+        st = _load().wlcs_ctx_get_plot_tiling(self._h, rows, cols, w, *[ctypes.byref(v) for v in vals])
+        if st != 0:
+            raise WlcsError(st, "wlcs_ctx_get_plot_tiling")
+        return tuple(v.value for v in vals)
 
     def _jobs(self, specs):
         """specs: dicts with pair, w and optional threshold, indel, full_range,

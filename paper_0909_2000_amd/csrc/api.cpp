@@ -161,7 +161,8 @@ int64_t tiling_makespan(const wlcs::PlotArgs& a, int64_t nblocks, int64_t cols, 
 // few counts of long pairs) is scored by the finishing time of a greedy list
 // schedule of its units over SIMDs x resident units equal slots; the fastest
 // wins (the longer tiles on ties).  A context rule (wlcs_ctx_set_tile or
-// wlcs_ctx_set_tiles) overrides the choice.
+// wlcs_ctx_set_tiles) overrides the choice, and a tiling measured for the
+// shape (wlcs_tune_plot) overrides the model.
 // The choice for a shape is kept in a small cache of the context.
 void choose_tiles(wlcs_ctx* ctx, wlcs::PlotArgs& a, int64_t rows, int64_t cols, int32_t w, int ws = 1) {
     for (int r = ctx->nrules - 1; r >= 0; --r) {
@@ -170,6 +171,10 @@ void choose_tiles(wlcs_ctx* ctx, wlcs::PlotArgs& a, int64_t rows, int64_t cols, 
             set_tiles(a, cols, R.tile, R.tile2 > 0 ? R.tile2 : R.tile, R.nbig);
             return;
         }
+    }
+    if (const wlcs_rt::TileChoice* c = wlcs_rt::find_tuned(ctx, rows, cols, w, ws)) {
+        set_tiles(a, cols, c->tile, c->tile2 > 0 ? c->tile2 : c->tile, c->nbig);
+        return;
     }
     for (const wlcs_rt::TileChoice& c : ctx->tile_cache) {
         if (c.rows == rows && c.cols == cols && c.w == w && c.ws == ws) {
@@ -430,16 +435,6 @@ int plot_common(Path path, wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uin
 }  // namespace
 
 // A device-resident, encoded pair of strings.
-struct wlcs_pair {
-    int device = 0;
-    hipStream_t stream = nullptr;  // creation stream: the codes are allocated and freed in its order
-    int64_t m = 0, n = 0;
-    int32_t sigma = 0;  // letters of the pair's alphabet
-    uint16_t* xf = nullptr;  // capacity xf_cap
-    uint16_t* yg = nullptr;  // capacity yg_cap
-    int64_t xf_cap = 0, yg_cap = 0;
-};
-
 namespace {
 
 constexpr int32_t kMaxTile = 32768;

@@ -30,8 +30,22 @@ struct TileChoice {
     int32_t tile = 0, tile2 = 0, nbig = 0, npairs = 0;
 };
 constexpr int kTileCache = 16;
+// Tilings measured fastest for one plot shape each (wlcs_tune_plot, or
+// loaded from a tuning cache by wlcs_tune / wlcs_tune_plot)
+constexpr int kTuned = 32;
 
 }  // namespace wlcs_rt
+
+// Resident letter codes of one pair (wlcs_pair_create).
+struct wlcs_pair {
+    int device = 0;
+    hipStream_t stream = nullptr;  // creation stream: the codes are allocated and freed in its order
+    int64_t m = 0, n = 0;
+    int32_t sigma = 0;  // letters of the pair's alphabet
+    uint16_t* xf = nullptr;  // capacity xf_cap
+    uint16_t* yg = nullptr;  // capacity yg_cap
+    int64_t xf_cap = 0, yg_cap = 0;
+};
 
 struct wlcs_ctx {
     int device = 0;
@@ -46,4 +60,43 @@ struct wlcs_ctx {
     int batch_waves_per_cu = 0;  // 0: each batched kernel's resident capacity
     wlcs_rt::TileChoice tile_cache[wlcs_rt::kTileCache];  // recent built-in tilings
     int tile_cache_next = 0;
+    wlcs_rt::TileChoice tuned[wlcs_rt::kTuned];  // measured tilings by shape (general plots, ws = 1)
+    int ntuned = 0, tuned_next = 0;
 };
+
+namespace wlcs_rt {
+
+// Record (or replace) the measured tiling of one shape; tile == 0 removes it
+// (the built-in choice was the fastest).
+inline void set_tuned(wlcs_ctx* ctx, const TileChoice& c) {
+    for (int k = 0; k < ctx->ntuned; ++k) {
+        TileChoice& e = ctx->tuned[k];
+        if (e.rows == c.rows && e.cols == c.cols && e.w == c.w && e.ws == c.ws) {
+            if (c.tile > 0) {
+                e = c;
+            } else {  // drop it: move the last entry here
+                e = ctx->tuned[ctx->ntuned - 1];
+                --ctx->ntuned;
+                if (ctx->tuned_next > ctx->ntuned) ctx->tuned_next = 0;
+            }
+            return;
+        }
+    }
+    if (c.tile <= 0) return;
+    if (ctx->ntuned < kTuned) {
+        ctx->tuned[ctx->ntuned++] = c;
+    } else {  // full: replace the oldest
+        ctx->tuned[ctx->tuned_next] = c;
+        ctx->tuned_next = (ctx->tuned_next + 1) % kTuned;
+    }
+}
+
+inline const TileChoice* find_tuned(const wlcs_ctx* ctx, int64_t rows, int64_t cols, int32_t w, int32_t ws) {
+    for (int k = 0; k < ctx->ntuned; ++k) {
+        const TileChoice& e = ctx->tuned[k];
+        if (e.rows == rows && e.cols == cols && e.w == w && e.ws == ws) return &e;
+    }
+    return nullptr;
+}
+
+}  // namespace wlcs_rt

@@ -65,6 +65,11 @@ struct JVal {
         v.num = x;
         return v;
     }
+    static JVal array() {
+        JVal v;
+        v.kind = Arr;
+        return v;
+    }
     static JVal object() {
         JVal v;
         v.kind = Obj;
@@ -462,30 +467,227 @@ int run_tuning(wlcs_ctx* ctx, JVal& entry) {
     return st;
 }
 
-// Apply a cache entry; WLCS_EINVAL if it does not have the expected shape
-// (nothing is applied then).
-int apply_entry(wlcs_ctx* ctx, JVal& entry) {
-    JVal* tiles = entry.get("batch_tiles");
-    JVal* grid = entry.get("batch_grid");
-    if (!tiles || tiles->kind != JVal::Obj || (grid && grid->kind != JVal::Num)) return WLCS_EINVAL;
-    std::vector<wlcs_rt::TileRule> rules;
-    for (auto& kv : tiles->obj) {
-        int lo = 0, hi = 0;
-        if (sscanf(kv.first.c_str(), "%d-%d", &lo, &hi) != 2 || kv.second.kind != JVal::Num) return WLCS_EINVAL;
-        const double t = kv.second.num;
-        // 0: the built-in choice
-        if (lo < 1 || hi < lo || hi > WLCS_MAX_W || t < 0 || t > 32768 || (t > 0 && t < 64) ||
-            t != (int32_t)t || (int32_t)t % 64)
-            return WLCS_EINVAL;
-        rules.push_back({lo, hi, (int32_t)t});
+// The measured tilings of single plots in an entry ("plots": {"RxCxW":
+// [tile, tile2, nbig]}, tile 0 for the built-in choice); false if malformed.
+bool parse_plots(JVal& entry, std::vector<wlcs_rt::TileChoice>& out) {
+    JVal* plots = entry.get("plots");
+    if (!plots) return true;
+    if (plots->kind != JVal::Obj) return false;
+    for (auto& kv : plots->obj) {
+        long long r = 0, c = 0;
+        int w = 0;
+        char tail = 0;
+        if (sscanf(kv.first.c_str(), "%lldx%lldx%d%c", &r, &c, &w, &tail) != 3 || r < 1 || c < 1 || w < 1 ||
+            w > WLCS_MAX_W)
+            return false;
+        const JVal& v = kv.second;
+        if (v.kind != JVal::Arr || v.arr.size() != 3) return false;
+        double t[3];
+        for (int k = 0; k < 3; ++k) {
+            if (v.arr[k].kind != JVal::Num) return false;
+            t[k] = v.arr[k].num;
+            if (t[k] < 0 || t[k] > 32768 || t[k] != (int32_t)t[k]) return false;
+        }
+        const bool builtin = t[0] == 0;
+        if (!builtin && ((int32_t)t[0] < 64 || (int32_t)t[0] % 64 || (int32_t)t[1] < 64 || (int32_t)t[1] % 64 ||
+                         t[1] > t[0]))
+            return false;
+        wlcs_rt::TileChoice ch;
+        ch.rows = r;
+        ch.cols = c;
+        ch.w = w;
+        ch.ws = 1;
+        ch.tile = (int32_t)t[0];
+        ch.tile2 = (int32_t)t[1];
+        ch.nbig = (int32_t)t[2];
+        out.push_back(ch);
     }
-    const double g = grid ? grid->num : 0.0;
-    if (g < 0 || g > 16 || g != (int32_t)g) return WLCS_EINVAL;
-    for (const auto& r : rules) {
-        const int st = wlcs_ctx_set_batch_tile(ctx, r.lo, r.hi, r.tile);
+    return true;
+}
+
+// Apply a cache entry; WLCS_EINVAL if it does not have the expected shape
+// (nothing is applied then).  batch: the entry must hold the batch knobs.
+int apply_entry(wlcs_ctx* ctx, JVal& entry, bool batch = true) {
+    std::vector<wlcs_rt::TileChoice> plots;
+    if (!parse_plots(entry, plots)) return WLCS_EINVAL;
+    if (batch) {
+        JVal* tiles = entry.get("batch_tiles");
+        JVal* grid = entry.get("batch_grid");
+        if (!tiles || tiles->kind != JVal::Obj || (grid && grid->kind != JVal::Num)) return WLCS_EINVAL;
+        std::vector<wlcs_rt::TileRule> rules;
+        for (auto& kv : tiles->obj) {
+            int lo = 0, hi = 0;
+            if (sscanf(kv.first.c_str(), "%d-%d", &lo, &hi) != 2 || kv.second.kind != JVal::Num) return WLCS_EINVAL;
+            const double t = kv.second.num;
+            // 0: the built-in choice
+            if (lo < 1 || hi < lo || hi > WLCS_MAX_W || t < 0 || t > 32768 || (t > 0 && t < 64) ||
+                t != (int32_t)t || (int32_t)t % 64)
+                return WLCS_EINVAL;
+            rules.push_back({lo, hi, (int32_t)t});
+        }
+        const double g = grid ? grid->num : 0.0;
+        if (g < 0 || g > 16 || g != (int32_t)g) return WLCS_EINVAL;
+        for (const auto& r : rules) {
+            const int st = wlcs_ctx_set_batch_tile(ctx, r.lo, r.hi, r.tile);
+            if (st != WLCS_OK) return st;
+        }
+        const int st = wlcs_ctx_set_batch_grid(ctx, (int32_t)g);
         if (st != WLCS_OK) return st;
     }
-    return wlcs_ctx_set_batch_grid(ctx, (int32_t)g);
+    for (const auto& p : plots) wlcs_rt::set_tuned(ctx, p);
+    return WLCS_OK;
+}
+
+std::string plot_key(int64_t rows, int64_t cols, int32_t w) {
+    return std::to_string(rows) + "x" + std::to_string(cols) + "x" + std::to_string(w);
+}
+
+// ---- tiling search for one plot shape ---------------------------------------
+
+struct PlotTiming {
+    wlcs_ctx* ctx;
+    const wlcs_pair* pair;
+    int32_t w, hx;
+    uint32_t flags;
+    uint8_t* out;
+    int64_t ld;
+    hipStream_t stream;
+    hipEvent_t a, b;
+    wlcs_rt::TileRule saved[16];
+    int nsaved;
+
+    // median of reps timed plots after one untimed one, under tiling
+    // (tile, tile2, nbig) (tile 0: the built-in choice)
+    int time(int32_t tile, int32_t tile2, int32_t nbig, int reps, double& ms) {
+        for (int r = 0; r < nsaved; ++r) ctx->rules[r] = saved[r];
+        ctx->nrules = nsaved;
+        if (tile > 0) {  // a rule for exactly this window, looked at first
+            const int slot = nsaved < 16 ? nsaved : 15;
+            ctx->rules[slot] = wlcs_rt::TileRule{w, w, tile, tile2, nbig};
+            ctx->nrules = slot + 1;
+        }
+        std::vector<float> t((size_t)reps);
+        int st = WLCS_OK;
+        for (int k = -1; k < reps && st == WLCS_OK; ++k) {
+            hipError_t e = k >= 0 ? hipEventRecord(a, stream) : hipSuccess;
+            if (e == hipSuccess)
+                st = wlcs_pair_plot_strided(ctx, pair, w, hx, 1, out, ld, nullptr, 0, 0, nullptr, 0, nullptr, 0,
+                                            nullptr, flags, stream);
+            if (st != WLCS_OK) break;
+            if (k < 0) continue;
+            if (e == hipSuccess) e = hipEventRecord(b, stream);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t[(size_t)k], a, b);
+            if (e != hipSuccess) {
+                ctx->last_hip = (int)e;
+                st = WLCS_EHIP;
+            }
+        }
+        for (int r = 0; r < nsaved; ++r) ctx->rules[r] = saved[r];
+        ctx->nrules = nsaved;
+        if (st != WLCS_OK) return st;
+        std::sort(t.begin(), t.end());
+        ms = t[(size_t)reps / 2];
+        return WLCS_OK;
+    }
+};
+
+struct Tried {
+    int32_t tile, tile2, nbig;
+    double ms;
+};
+
+// Coarse grid of two-length tilings (and one-length ones), then the
+// neighbourhood of the fastest, then the three fastest and the built-in
+// choice timed again with more launches; the fastest of those wins.
+int search_tiling(PlotTiming& pt, int64_t cols, int32_t& tile, int32_t& tile2, int32_t& nbig, double& tuned_ms,
+                  double& builtin_ms) {
+    const int64_t cap = std::max<int64_t>(64, (cols + 63) / 64 * 64);
+    std::vector<Tried> tried;
+    int st = WLCS_OK;
+    auto norm = [&](int32_t t, int32_t t2, int64_t nb) -> Tried {
+        const int64_t nbm = cols / (2 * (int64_t)t);
+        if (t2 >= t || nbm < 1) return Tried{t, t, 0, 0.0};  // one length
+        return Tried{t, t2, (int32_t)std::max<int64_t>(1, std::min<int64_t>(nb, nbm)), 0.0};
+    };
+    auto attempt = [&](Tried c) {
+        if (st != WLCS_OK || c.tile < 64 || c.tile > cap || c.tile % 64 || c.tile2 < 64 || c.tile2 % 64) return;
+        for (const Tried& d : tried)
+            if (d.tile == c.tile && d.tile2 == c.tile2 && d.nbig == c.nbig) return;
+        st = pt.time(c.tile, c.tile2, c.nbig, 3, c.ms);
+        if (st == WLCS_OK) tried.push_back(c);
+    };
+    static const int32_t kLong[] = {256, 512, 1024, 1536, 2048, 3072, 4096, 6144};
+    static const int32_t kShort[] = {128, 256, 512, 1024};
+    for (int32_t t : kLong) {
+        if (t > cap) break;
+        attempt(norm(t, t, 0));
+        const int64_t nbm = cols / (2 * (int64_t)t);
+        for (int32_t t2 : kShort) {
+            if (t2 >= t || nbm < 1) continue;
+            const int64_t nbs[4] = {nbm / 4, nbm / 2, 3 * nbm / 4, nbm};
+            for (int64_t nb : nbs) attempt(norm(t, t2, nb));
+        }
+    }
+    if (st != WLCS_OK) return st;
+    if (tried.empty()) {  // no candidate fits the row: the built-in choice stays
+        tile = tile2 = nbig = 0;
+        st = pt.time(0, 0, 0, 5, builtin_ms);
+        tuned_ms = builtin_ms;
+        return st;
+    }
+    auto fastest = [&]() {
+        return *std::min_element(tried.begin(), tried.end(), [](const Tried& p, const Tried& q) { return p.ms < q.ms; });
+    };
+    const Tried b1 = fastest();
+    auto r64 = [](double v) { return (int32_t)std::max<int64_t>(64, (int64_t)(v / 64.0 + 0.5) * 64); };
+    const double tf[5] = {0.75, 0.875, 1.0, 1.125, 1.25}, sf[3] = {0.75, 1.0, 1.5};
+    for (double f : tf) {
+        const int32_t t = r64(b1.tile * f);
+        if (b1.tile2 == b1.tile) {
+            attempt(norm(t, t, 0));
+            continue;
+        }
+        for (double g : sf)
+            for (int d = -2; d <= 2; ++d) attempt(norm(t, r64(b1.tile2 * g), (int64_t)b1.nbig + d));
+    }
+    if (st != WLCS_OK) return st;
+    // the three fastest and the built-in choice, timed again
+    std::sort(tried.begin(), tried.end(), [](const Tried& p, const Tried& q) { return p.ms < q.ms; });
+    if (tried.size() > 3) tried.resize(3);
+    st = pt.time(0, 0, 0, 9, builtin_ms);
+    Tried best{0, 0, 0, builtin_ms};
+    for (Tried& c : tried) {
+        if (st == WLCS_OK) st = pt.time(c.tile, c.tile2, c.nbig, 9, c.ms);
+        if (st == WLCS_OK && c.ms < best.ms) best = c;
+    }
+    if (st != WLCS_OK) return st;
+    tile = best.tile;
+    tile2 = best.tile2;
+    nbig = best.nbig;
+    tuned_ms = best.ms;
+    return WLCS_OK;
+}
+
+// Read the cache file into cache (an empty object if path is NULL or the
+// file does not exist); WLCS_EINVAL if it is not a JSON object.
+int read_cache(const char* path, JVal& cache) {
+    cache = JVal::object();
+    std::string text;
+    if (!path || !read_file(path, text)) return WLCS_OK;
+    Parser ps{text.data(), text.data() + text.size()};
+    JVal parsed = ps.value();
+    ps.ws();
+    if (!ps.ok || ps.p != ps.end || parsed.kind != JVal::Obj) return WLCS_EINVAL;  // reported, not overwritten
+    cache = std::move(parsed);
+    return WLCS_OK;
+}
+
+int write_cache(const char* path, const JVal& cache) {
+    std::string out;
+    dump(cache, out, 0);
+    out += "\n";
+    return write_file(path, out) ? WLCS_OK : WLCS_EIO;
 }
 
 }  // namespace
@@ -499,33 +701,143 @@ int wlcs_tune(wlcs_ctx* ctx, const char* cache_path, uint32_t flags) {
     if (prev != ctx->device && hipSetDevice(ctx->device) != hipSuccess) return WLCS_EHIP;
     std::string key;
     int st = device_key(ctx->device, key) ? WLCS_OK : WLCS_EHIP;
-    JVal cache = JVal::object();
-    std::string text;
-    if (st == WLCS_OK && cache_path && read_file(cache_path, text)) {
-        Parser ps{text.data(), text.data() + text.size()};
-        JVal parsed = ps.value();
-        ps.ws();
-        if (!ps.ok || ps.p != ps.end || parsed.kind != JVal::Obj)
-            st = WLCS_EINVAL;  // an unreadable cache is reported, not overwritten
-        else
-            cache = std::move(parsed);
-    }
+    JVal cache;
+    if (st == WLCS_OK) st = read_cache(cache_path, cache);
     JVal* have = st == WLCS_OK ? cache.get(key) : nullptr;
-    if (st == WLCS_OK && have && !(flags & WLCS_TUNE_FORCE)) {
+    if (have && have->kind != JVal::Obj) st = WLCS_EINVAL;
+    // batch knobs without their tiles: a malformed entry (an entry with only
+    // measured plot tilings is completed below)
+    if (have && !have->get("batch_tiles") && (have->get("batch_grid") || have->get("batch_ms"))) st = WLCS_EINVAL;
+    if (st == WLCS_OK && have && have->get("batch_tiles") && !(flags & WLCS_TUNE_FORCE)) {
         st = apply_entry(ctx, *have);
     } else if (st == WLCS_OK) {
+        // an entry without the batch knobs (only measured plot tilings) is
+        // completed; its plot tilings are kept and applied
+        std::vector<wlcs_rt::TileChoice> plots;
+        if (have && !parse_plots(*have, plots)) st = WLCS_EINVAL;
         JVal entry;
-        st = run_tuning(ctx, entry);
+        if (st == WLCS_OK) st = run_tuning(ctx, entry);
+        for (const char* m : {"plots", "plots_ms"})
+            if (st == WLCS_OK && have && have->get(m)) entry.set(m, *have->get(m));
+        if (st == WLCS_OK) st = apply_entry(ctx, entry);
         if (st == WLCS_OK && cache_path) {
             cache.set(key, std::move(entry));
-            std::string out;
-            dump(cache, out, 0);
-            out += "\n";
-            if (!write_file(cache_path, out)) st = WLCS_EIO;
+            st = write_cache(cache_path, cache);
         }
     }
     if (prev >= 0 && prev != ctx->device) (void)hipSetDevice(prev);
     return st;
+}
+
+int wlcs_tune_plot(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, int32_t hx, uint32_t flags,
+                   const char* cache_path, uint32_t tune_flags) {
+    if (!ctx || !pair || pair->device != ctx->device || (flags & ~WLCS_FULL_RANGE) ||
+        (tune_flags & ~WLCS_TUNE_FORCE))
+        return WLCS_EINVAL;
+    if (w < 1 || w > WLCS_MAX_W || hx < 1) return WLCS_ERANGE;
+    const bool full = (flags & WLCS_FULL_RANGE) != 0;
+    const int64_t rows_all = std::max<int64_t>(0, pair->m - w + (full ? 1 : 0));
+    const int64_t cols = std::max<int64_t>(0, pair->n - w + (full ? 1 : 0));
+    const int64_t rows = (rows_all + hx - 1) / hx;
+    if (rows == 0 || cols == 0) return WLCS_OK;  // an empty plot: nothing to tune
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != ctx->device && hipSetDevice(ctx->device) != hipSuccess) return WLCS_EHIP;
+    std::string dkey;
+    int st = device_key(ctx->device, dkey) ? WLCS_OK : WLCS_EHIP;
+    const std::string pkey = plot_key(rows, cols, w);
+    JVal cache;
+    if (st == WLCS_OK) st = read_cache(cache_path, cache);
+    JVal* have = st == WLCS_OK ? cache.get(dkey) : nullptr;
+    if (have && have->kind != JVal::Obj) st = WLCS_EINVAL;
+    JVal* plots = have ? have->get("plots") : nullptr;
+    if (plots && plots->kind != JVal::Obj) st = WLCS_EINVAL;
+    JVal* known = (st == WLCS_OK && plots) ? plots->get(pkey) : nullptr;
+    if (known && !(tune_flags & WLCS_TUNE_FORCE)) {
+        // apply the recorded tiling of this shape only
+        JVal one = JVal::object();
+        JVal p = JVal::object();
+        p.set(pkey, *known);
+        one.set("plots", std::move(p));
+        st = apply_entry(ctx, one, false);
+    } else if (st == WLCS_OK) {
+        // the pair's codes may still be in flight on its creation stream
+        hipError_t e = hipDeviceSynchronize();
+        PlotTiming pt{};
+        pt.ctx = ctx;
+        pt.pair = pair;
+        pt.w = w;
+        pt.hx = hx;
+        pt.flags = flags;
+        pt.ld = cols;
+        pt.nsaved = ctx->nrules;
+        for (int r = 0; r < ctx->nrules; ++r) pt.saved[r] = ctx->rules[r];
+        // a measured tiling of this shape must not steer the built-in timing
+        wlcs_rt::TileChoice drop;
+        drop.rows = rows;
+        drop.cols = cols;
+        drop.w = w;
+        drop.ws = 1;
+        drop.tile = 0;
+        wlcs_rt::set_tuned(ctx, drop);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&pt.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreate(&pt.a);
+        if (e == hipSuccess) e = hipEventCreate(&pt.b);
+        if (e == hipSuccess) e = hipMalloc((void**)&pt.out, (size_t)(rows * cols));
+        if (e != hipSuccess) {
+            ctx->last_hip = (int)e;
+            st = e == hipErrorOutOfMemory ? WLCS_ENOMEM : WLCS_EHIP;
+        }
+        int32_t tile = 0, tile2 = 0, nbig = 0;
+        double tuned_ms = 0.0, builtin_ms = 0.0;
+        if (st == WLCS_OK) st = search_tiling(pt, cols, tile, tile2, nbig, tuned_ms, builtin_ms);
+        if (pt.stream) (void)hipStreamSynchronize(pt.stream);
+        if (pt.out) (void)hipFree(pt.out);
+        if (pt.a) (void)hipEventDestroy(pt.a);
+        if (pt.b) (void)hipEventDestroy(pt.b);
+        if (pt.stream) (void)hipStreamDestroy(pt.stream);
+        if (st == WLCS_OK) {
+            wlcs_rt::TileChoice ch;
+            ch.rows = rows;
+            ch.cols = cols;
+            ch.w = w;
+            ch.ws = 1;
+            ch.tile = tile;
+            ch.tile2 = tile2;
+            ch.nbig = nbig;
+            wlcs_rt::set_tuned(ctx, ch);
+        }
+        if (st == WLCS_OK && cache_path) {
+            JVal rec = JVal::array();
+            rec.arr.push_back(JVal::number(tile));
+            rec.arr.push_back(JVal::number(tile2));
+            rec.arr.push_back(JVal::number(nbig));
+            if (!have) {
+                cache.set(dkey, JVal::object());
+                have = cache.get(dkey);
+            }
+            if (!have->get("plots")) have->set("plots", JVal::object());
+            have->get("plots")->set(pkey, std::move(rec));
+            JVal ms = JVal::object();
+            ms.set("builtin", JVal::number(builtin_ms));
+            ms.set("tuned", JVal::number(tuned_ms));
+            if (!have->get("plots_ms")) have->set("plots_ms", JVal::object());
+            have->get("plots_ms")->set(pkey, std::move(ms));
+            st = write_cache(cache_path, cache);
+        }
+    }
+    if (prev >= 0 && prev != ctx->device) (void)hipSetDevice(prev);
+    return st;
+}
+
+int wlcs_ctx_get_plot_tiling(const wlcs_ctx* ctx, int64_t rows, int64_t cols, int32_t w, int32_t* tile,
+                             int32_t* tile2, int32_t* nbig) {
+    if (!ctx || !tile || !tile2 || !nbig || rows < 0 || cols < 0 || w < 1 || w > WLCS_MAX_W) return WLCS_EINVAL;
+    const wlcs_rt::TileChoice* c = wlcs_rt::find_tuned(ctx, rows, cols, w, 1);
+    *tile = c ? c->tile : 0;
+    *tile2 = c ? c->tile2 : 0;
+    *nbig = c ? c->nbig : 0;
+    return WLCS_OK;
 }
 
 int wlcs_ctx_get_batch_tile(const wlcs_ctx* ctx, int32_t w, int32_t* tile_windows) {

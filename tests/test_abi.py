@@ -110,6 +110,10 @@ def test_pair_and_ctx_argument_checks(lib):
     v = ctypes.c_double(-1.0)
     assert lib.wlcs_measure_valu_peak(None, 100, ctypes.byref(v)) == EINVAL and v.value == -1.0
     assert lib.wlcs_ctx_create(0, None) == EINVAL
+    assert lib.wlcs_tune_plot(None, None, 64, 1, 0, None, 0) == EINVAL
+    t = [ctypes.c_int32(7) for _ in range(3)]
+    assert lib.wlcs_ctx_get_plot_tiling(None, 10, 10, 8, *[ctypes.byref(x) for x in t]) == EINVAL
+    assert [x.value for x in t] == [7, 7, 7]
 
 
 def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):

@@ -7,6 +7,8 @@ import json
 import os
 import time
 
+import numpy as np
+
 import pytest
 
 import workloads
@@ -131,3 +133,102 @@ def test_cache_entry_is_applied_as_written(tmp_path):
     ctx.tune(str(path))
     assert ctx.batch_grid() == 6
     assert [ctx.batch_tile(w) for w in (16, 17, 64, 65, 128)] == [256, 768, 0, 2048, 2048]
+
+
+def _plot_pair(wl, ctx, seed=70, m=4000, n=5000):
+    g = workloads.rng(seed)
+    x, y = workloads.iid(g, m, workloads.DNA), workloads.iid(g, n, workloads.DNA)
+    return x, y, ctx.pair(x, y)
+
+
+def test_tune_plot_records_applies_and_keeps_other_entries(tmp_path, oracle_mod):
+    """wlcs_tune_plot times tilings of one shape, records the fastest in the
+    context and the cache (the device's batch knobs and other devices'
+    entries stay), a second context loads the record without timing, and
+    wlcs_tune keeps the plot records when it completes the device entry.
+    The plots are the same whichever tiling applies."""
+    import torch
+    import paper_0909_2000_amd as wl
+    path = tmp_path / "cache.json"
+    other = {"gfx000-1cu": {"batch_grid": 4, "batch_tiles": {"1-16": 64}}}
+    path.write_text(json.dumps(other))
+    ctx = wl.Context(0)
+    x, y, pair = _plot_pair(wl, ctx)
+    w = 64
+    rows, cols = x.size - w, y.size - w
+    ref = pair.plot(w)["wlcs"].clone()  # the built-in tiling
+    t0 = time.time()
+    ctx.tune_plot(pair, w, cache_path=str(path))
+    print(f"tune_plot {rows}x{cols}x{w}: {time.time() - t0:.1f} s", flush=True)
+    data = json.loads(path.read_text())
+    assert data["gfx000-1cu"] == other["gfx000-1cu"]
+    entry = data[_key(torch)]
+    rec = entry["plots"][f"{rows}x{cols}x{w}"]
+    ms = entry["plots_ms"][f"{rows}x{cols}x{w}"]
+    assert ms["tuned"] <= ms["builtin"] and ms["tuned"] > 0
+    assert len(rec) == 3
+    assert ctx.plot_tiling(rows, cols, w) == (tuple(rec) if rec[0] else (0, 0, 0))
+    assert torch.equal(pair.plot(w)["wlcs"], ref)
+    sample = [0, rows // 2, rows - 1]
+    np_ref = ref[torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    np.testing.assert_array_equal(np_ref, oracle_mod.wlcs_rows(x, y, w, sample))
+    # a second context applies the record and times nothing
+    ctx2 = wl.Context(0)
+    pair2 = ctx2.pair(x, y)
+    t0 = time.time()
+    ctx2.tune_plot(pair2, w, cache_path=str(path))
+    assert time.time() - t0 < 1.0
+    assert ctx2.plot_tiling(rows, cols, w) == ctx.plot_tiling(rows, cols, w)
+    # wlcs_tune completes the entry with the batch knobs and keeps the record
+    ctx3 = wl.Context(0)
+    ctx3.tune(str(path))
+    entry3 = json.loads(path.read_text())[_key(torch)]
+    assert "batch_tiles" in entry3 and entry3["plots"] == entry["plots"]
+    assert ctx3.plot_tiling(rows, cols, w) == ctx.plot_tiling(rows, cols, w)
+
+
+def test_recorded_plot_tiling_is_applied(tmp_path, oracle_mod):
+    """A cache record with a deliberate tiling (long tiles of 1024 windows for
+    one leading pair, then 256) is applied to plots of that shape only; the
+    strided shape (every 3rd x-window) has a record of its own."""
+    import torch
+    import paper_0909_2000_amd as wl
+    ctx = wl.Context(0)
+    x, y, pair = _plot_pair(wl, ctx, seed=71, m=3000, n=4100)
+    w = 100
+    rows, cols = x.size - w, y.size - w
+    srows = -(-rows // 3)
+    path = tmp_path / "cache.json"
+    path.write_text(json.dumps({_key(torch): {"plots": {f"{rows}x{cols}x{w}": [1024, 256, 1],
+                                                         f"{srows}x{cols}x{w}": [512, 128, 2]}}}))
+    ctx.tune_plot(pair, w, cache_path=str(path))
+    assert ctx.plot_tiling(rows, cols, w) == (1024, 256, 1)
+    assert ctx.plot_tiling(srows, cols, w) == (0, 0, 0)  # only the asked shape is applied
+    ctx.tune_plot(pair, w, hx=3, cache_path=str(path))
+    assert ctx.plot_tiling(srows, cols, w) == (512, 128, 2)
+    got = pair.plot(w)["wlcs"].cpu().numpy()
+    np.testing.assert_array_equal(got, oracle_mod.wlcs(x, y, w))
+    got = pair.plot_strided(w, 3, 1)["wlcs"].cpu().numpy()
+    np.testing.assert_array_equal(got, oracle_mod.wlcs_strided(x, y, w, 3, 1))
+    other = wl.Context(0)  # a context without the record: the same plots
+    assert other.plot_tiling(rows, cols, w) == (0, 0, 0)
+    np.testing.assert_array_equal(other.pair(x, y).plot(w)["wlcs"].cpu().numpy(), oracle_mod.wlcs(x, y, w))
+
+
+@pytest.mark.parametrize("plots", [
+    {"10x10x8": [100, 64, 1]},      # not a multiple of 64
+    {"10x10x8": [512, 1024, 1]},    # short tile longer than the long one
+    {"10x10": [512, 256, 1]},       # not rows x cols x w
+    {"10x10x8": [512, 256]},        # two numbers
+    [1, 2, 3],                      # not an object
+])
+def test_malformed_plot_records_apply_nothing(tmp_path, plots):
+    import torch
+    import paper_0909_2000_amd as wl
+    path = tmp_path / "cache.json"
+    path.write_text(json.dumps({_key(torch): {"batch_grid": 6, "batch_tiles": {"1-16": 256}, "plots": plots}}))
+    ctx = wl.Context(0)
+    with pytest.raises(wl.WlcsError) as e:
+        ctx.tune(str(path))
+    assert e.value.status == -1
+    assert ctx.batch_grid() == 0 and ctx.plot_tiling(10, 10, 8) == (0, 0, 0)
