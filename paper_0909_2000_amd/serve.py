@@ -88,6 +88,21 @@ LATENCY_TILES = {(1, 64): 512, (65, 128): 1024}
 LATENCY_GRID = 16
 
 
+# Streams of the executors, per device, shared by every executor of the
+# process: torch's caching allocator keeps freed blocks per stream, so
+# executors on new streams could not reuse the output memory their
+# predecessors cached and would map fresh device memory each time (until the
+# device is full and the allocator has to release everything at once).
+_STREAM_POOL: dict = {}
+
+
+def _streams(torch, dev, count: int) -> list:
+    pool = _STREAM_POOL.setdefault(dev.index, [])
+    while len(pool) < count:
+        pool.append(torch.cuda.Stream(device=dev))
+    return pool[:count]
+
+
 class GpuExecutor:
     """Runs batches on one GPU through libwlcs, one stream per concurrent batch.
     Without a context of its own it makes one with the latency tiles.  With
@@ -108,7 +123,7 @@ class GpuExecutor:
             ctx.set_batch_grid(LATENCY_GRID)
         self.ctx = ctx
         self.d2h = d2h_bitmaps
-        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
+        self.streams = _streams(torch, self.dev, streams)
         self.busy = [None] * streams  # per stream: (event, batch_id) or None
         self.t0 = time.perf_counter()
 
