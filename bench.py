@@ -23,6 +23,7 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 TUNING_CACHE = os.path.join(ROOT, "paper_0909_2000_amd", "tuning_gfx950.json")
+FIXED_RATE = 1100.0  # serving: jobs/s of the fixed-rate latency point
 sys.path.insert(0, ROOT)
 
 # HIP events over the timed region; per-cell operation count of the method
@@ -507,6 +508,9 @@ def bench_serving(ctx, torch, workloads, args):
     # the same stream with dot lists (window starts, WLCS, indel distance of
     # every pair at or above the threshold) in place of the dense outputs
     # latency across the load: the same stream at other fractions of capacity
+    # a fixed arrival rate, comparable whatever the capacity
+    fixed = run(FIXED_RATE)
+    log(f"serving at {FIXED_RATE:.0f} jobs/s: p50 {fixed['p50_s'] * 1e3:.1f} ms, p99 {fixed['p99_s'] * 1e3:.1f} ms")
     sweep = {}
     for load in (0.25, 0.5, 0.9):
         r = run(load * capacity)
@@ -520,6 +524,8 @@ def bench_serving(ctx, torch, workloads, args):
     return {"jobs": len(jobs), "capacity_jobs_per_s": capacity, "saturated": sat,
             "load": args.serving_load, "rate_jobs_per_s": rate, "at_load": at, "load_sweep": sweep,
             "at_load_with_bitmap_d2h": at_d2h,
+            "at_fixed_rate": {"rate_jobs_per_s": FIXED_RATE, "p50_s": fixed["p50_s"], "p99_s": fixed["p99_s"],
+                              "jobs_per_s": fixed["jobs_per_s"]},
             "budget_gib": args.budget_gib,
             "workload": "Poisson arrivals; DNA/protein 1:1; m,n log-uniform [500,50000]; "
                         "w ~ {16,32,64,128}; outputs bitmap (T=ceil(3w/4)) + uint16 indel",

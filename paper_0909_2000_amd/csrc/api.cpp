@@ -22,7 +22,7 @@ namespace wlcs {
 hipError_t launch_valu_peak(uint32_t* out, int32_t blocks, int32_t iters, hipStream_t stream);
 }  // namespace wlcs
 
-using wlcs_rt::kSlots;
+using wlcs_rt::kMaxSlots;
 using wlcs_rt::Slot;
 using wlcs_rt::TileRule;
 
@@ -239,7 +239,6 @@ void uniform_tiles(wlcs::PlotArgs& a, int64_t cols, int32_t tile) { set_tiles(a,
 
 struct Prepared {
     int64_t rows = 0, cols = 0;
-    uint8_t* raw = nullptr;  // device: x bytes then y bytes
     uint16_t* xf = nullptr;
     uint16_t* yg = nullptr;
 };
@@ -264,23 +263,74 @@ int validate(const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, int32_t w
 
 // Copy `bytes` host bytes to device memory dst on `stream` through one of the
 // context's pinned slots (the host buffer may be reused on return).
-int stage_copy(wlcs_ctx* ctx, const void* src, size_t bytes, void* dst, hipStream_t stream) {
-    if (bytes == 0) return WLCS_OK;
-    Slot& sl = ctx->slots[ctx->next_slot];
-    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
+// A pinned staging slot of at least `bytes` (with a device buffer as large
+// when `device`) whose last work has completed: the first idle one from the
+// rotation (a query, no wait), else a new one while fewer than kMaxSlots
+// exist, else the next one in turn after its work is done.  So work queued
+// behind other work on a busy stream does not hold the host back while slots
+// are to be had, and no device memory is allocated or freed per call
+// (a stream-ordered free costs the host about half a millisecond while the
+// stream has work queued).  Capacities grow in powers of two from 1 MiB
+// (each growth frees the old buffers, and freeing device memory waits for the
+// device).
+int acquire_slot(wlcs_ctx* ctx, size_t bytes, Slot*& out, bool device = false) {
+    out = nullptr;
+    Slot* pick = nullptr;
+    for (int k = 0; k < ctx->nslots && !pick; ++k) {
+        Slot& sl = ctx->slots[(ctx->next_slot + k) % ctx->nslots];
+        if (!sl.pending) {
+            pick = &sl;
+            break;
+        }
+        const hipError_t q = hipEventQuery(sl.done);
+        if (q == hipSuccess) {
+            sl.pending = false;
+            pick = &sl;
+        } else if (q != hipErrorNotReady) {
+            return fail(ctx, q);
+        }
+    }
     hipError_t e;
-    if (sl.pending) {
+    if (!pick && ctx->nslots < kMaxSlots) {
+        Slot& sl = ctx->slots[ctx->nslots];
+        if ((e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess) return fail(ctx, e);
+        ++ctx->nslots;
+        pick = &sl;
+    }
+    if (!pick) {
+        Slot& sl = ctx->slots[ctx->next_slot % ctx->nslots];
         if ((e = hipEventSynchronize(sl.done)) != hipSuccess) return fail(ctx, e);
         sl.pending = false;
+        pick = &sl;
     }
-    if (sl.cap < bytes) {
-        if (sl.buf) (void)hipHostFree(sl.buf);
-        sl.buf = nullptr;
-        sl.cap = 0;
-        const size_t cap = std::max<size_t>(bytes, 1 << 16);
-        if ((e = hipHostMalloc((void**)&sl.buf, cap, hipHostMallocDefault)) != hipSuccess) return fail(ctx, e);
-        sl.cap = cap;
+    ctx->next_slot = (int)(pick - ctx->slots + 1) % ctx->nslots;
+    size_t cap = 1 << 20;
+    while (cap < bytes) cap <<= 1;
+    if (pick->cap < bytes) {
+        if (pick->buf) (void)hipHostFree(pick->buf);
+        pick->buf = nullptr;
+        pick->cap = 0;
+        if ((e = hipHostMalloc((void**)&pick->buf, cap, hipHostMallocDefault)) != hipSuccess) return fail(ctx, e);
+        pick->cap = cap;
     }
+    if (device && pick->dcap < bytes) {
+        if (pick->dbuf) (void)hipFree(pick->dbuf);
+        pick->dbuf = nullptr;
+        pick->dcap = 0;
+        if ((e = hipMalloc((void**)&pick->dbuf, cap)) != hipSuccess) return fail(ctx, e);
+        pick->dcap = cap;
+    }
+    out = pick;
+    return WLCS_OK;
+}
+
+int stage_copy(wlcs_ctx* ctx, const void* src, size_t bytes, void* dst, hipStream_t stream) {
+    if (bytes == 0) return WLCS_OK;
+    Slot* slot = nullptr;
+    int st = acquire_slot(ctx, bytes, slot);
+    if (st != WLCS_OK) return st;
+    Slot& sl = *slot;
+    hipError_t e;
     memcpy(sl.buf, src, bytes);
     if ((e = hipMemcpyAsync(dst, sl.buf, bytes, hipMemcpyHostToDevice, stream)) != hipSuccess) return fail(ctx, e);
     if ((e = hipEventRecord(sl.done, stream)) != hipSuccess) return fail(ctx, e);
@@ -288,48 +338,49 @@ int stage_copy(wlcs_ctx* ctx, const void* src, size_t bytes, void* dst, hipStrea
     return WLCS_OK;
 }
 
-// Copy x and y into a pinned slot, then to device memory, and encode them into
-// the padded code arrays the kernels read.
+// Copy x and y into a pinned slot, then into the slot's device buffer, and
+// encode them into xf (xf_len codes) and yg (yg_len codes), device arrays of
+// the caller (either may be null); the slot is free again once the encode
+// kernels are done.
+int stage_encode(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, const uint8_t map[256],
+                 uint16_t* xf, int64_t xf_len, uint16_t* yg, int64_t yg_len, hipStream_t stream, int sep = -1) {
+    const size_t need = (size_t)(m + n);
+    const uint8_t* raw = nullptr;  // device copy of x then y (none when both are empty: padding only)
+    Slot* slot = nullptr;
+    hipError_t e;
+    if (need > 0) {
+        const int st = acquire_slot(ctx, need, slot, true);
+        if (st != WLCS_OK) return st;
+        memcpy(slot->buf, x, (size_t)m);
+        memcpy(slot->buf + m, y, (size_t)n);
+        if ((e = hipMemcpyAsync(slot->dbuf, slot->buf, need, hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return fail(ctx, e);
+        raw = slot->dbuf;
+    }
+    if (xf && (e = wlcs::launch_encode(raw, m, map, 1, xf, xf_len, stream, sep)) != hipSuccess) return fail(ctx, e);
+    if (yg && (e = wlcs::launch_encode(raw + m, n, map, 0, yg, yg_len, stream, sep)) != hipSuccess)
+        return fail(ctx, e);
+    if (slot) {
+        if ((e = hipEventRecord(slot->done, stream)) != hipSuccess) return fail(ctx, e);
+        slot->pending = true;
+    }
+    return WLCS_OK;
+}
+
+// Code arrays of one plot call (stream-ordered allocations, released after
+// the plot) holding x and y encoded.
 int upload(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* y, int64_t n, const uint8_t map[256],
            int64_t xf_len, int64_t yg_len, hipStream_t stream, Prepared& p, int sep = -1) {
-    const size_t need = (size_t)(m + n);
-    if (need == 0) return WLCS_OK;
-    Slot& sl = ctx->slots[ctx->next_slot];
-    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
+    if (m + n == 0) return WLCS_OK;
     hipError_t e;
-    if (sl.pending) {
-        if ((e = hipEventSynchronize(sl.done)) != hipSuccess) return fail(ctx, e);
-        sl.pending = false;
-    }
-    if (sl.cap < need) {
-        if (sl.buf) (void)hipHostFree(sl.buf);
-        sl.buf = nullptr;
-        sl.cap = 0;
-        if ((e = hipHostMalloc((void**)&sl.buf, std::max<size_t>(need, 1 << 16), hipHostMallocDefault)) !=
-            hipSuccess)
-            return fail(ctx, e);
-        sl.cap = std::max<size_t>(need, 1 << 16);
-    }
-    memcpy(sl.buf, x, (size_t)m);
-    memcpy(sl.buf + m, y, (size_t)n);
-    if ((e = hipMallocAsync((void**)&p.raw, need, stream)) != hipSuccess) return fail(ctx, e);
     if (xf_len > 0 && (e = hipMallocAsync((void**)&p.xf, (size_t)xf_len * 2, stream)) != hipSuccess)
         return fail(ctx, e);
     if (yg_len > 0 && (e = hipMallocAsync((void**)&p.yg, (size_t)yg_len * 2, stream)) != hipSuccess)
         return fail(ctx, e);
-    if ((e = hipMemcpyAsync(p.raw, sl.buf, need, hipMemcpyHostToDevice, stream)) != hipSuccess)
-        return fail(ctx, e);
-    if ((e = hipEventRecord(sl.done, stream)) != hipSuccess) return fail(ctx, e);
-    sl.pending = true;
-    if (xf_len > 0 && (e = wlcs::launch_encode(p.raw, m, map, 1, p.xf, xf_len, stream, sep)) != hipSuccess)
-        return fail(ctx, e);
-    if (yg_len > 0 && (e = wlcs::launch_encode(p.raw + m, n, map, 0, p.yg, yg_len, stream, sep)) != hipSuccess)
-        return fail(ctx, e);
-    return WLCS_OK;
+    return stage_encode(ctx, x, m, y, n, map, p.xf, xf_len, p.yg, yg_len, stream, sep);
 }
 
 void release(Prepared& p, hipStream_t stream) {
-    if (p.raw) (void)hipFreeAsync(p.raw, stream);
     if (p.xf) (void)hipFreeAsync(p.xf, stream);
     if (p.yg) (void)hipFreeAsync(p.yg, stream);
     p = Prepared();
@@ -703,14 +754,6 @@ int wlcs_ctx_create(int device, wlcs_ctx** out) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         ctx->cus = cus;
-    for (int i = 0; i < kSlots; ++i) {
-        hipError_t e = hipEventCreateWithFlags(&ctx->slots[i].done, hipEventDisableTiming);
-        if (e != hipSuccess) {
-            ctx->last_hip = (int)e;
-            wlcs_ctx_destroy(ctx);
-            return WLCS_EHIP;
-        }
-    }
     *out = ctx;
     return WLCS_OK;
 }
@@ -719,10 +762,11 @@ int wlcs_ctx_destroy(wlcs_ctx* ctx) {
     if (!ctx) return WLCS_OK;
     DeviceGuard guard(ctx->device);
     int st = WLCS_OK;
-    for (int i = 0; i < kSlots; ++i) {
+    for (int i = 0; i < ctx->nslots; ++i) {
         Slot& sl = ctx->slots[i];
         if (sl.pending && hipEventSynchronize(sl.done) != hipSuccess) st = WLCS_EHIP;
         if (sl.buf) (void)hipHostFree(sl.buf);
+        if (sl.dbuf) (void)hipFree(sl.dbuf);
         if (sl.done) (void)hipEventDestroy(sl.done);
     }
     delete ctx;
@@ -894,14 +938,7 @@ int wlcs_pair_create(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* 
         wlcs_pair_destroy(pr);
         return fail(ctx, e);
     }
-    Prepared p;
-    st = upload(ctx, x, m, y, n, map, 0, 0, stream, p);  // raw bytes only
-    if (st == WLCS_OK) {
-        e = wlcs::launch_encode(p.raw, m, map, 1, pr->xf, pr->xf_cap, stream);
-        if (e == hipSuccess) e = wlcs::launch_encode(p.raw + m, n, map, 0, pr->yg, pr->yg_cap, stream);
-        if (e != hipSuccess) st = fail(ctx, e);
-    }
-    release(p, stream);
+    st = stage_encode(ctx, x, m, y, n, map, pr->xf, pr->xf_cap, pr->yg, pr->yg_cap, stream);
     if (st != WLCS_OK) {
         (void)hipStreamSynchronize(stream);
         wlcs_pair_destroy(pr);

@@ -7,11 +7,19 @@
 
 namespace wlcs_rt {
 
-constexpr int kSlots = 4;  // pinned staging buffers per context
+// Staging slots per context (pinned and device buffers), made as needed: a
+// slot whose last work is still queued (behind other work on a busy stream) is
+// not waited for while fewer than this many exist.  A serving loop keeps about
+// one per job in flight (three batches of up to 64 jobs).
+constexpr int kMaxSlots = 256;
 
+// A pinned host buffer and (for strings to encode) a device buffer of the
+// same capacity; `done` marks the end of the last work that read them.
 struct Slot {
     uint8_t* buf = nullptr;
     size_t cap = 0;
+    uint8_t* dbuf = nullptr;
+    size_t dcap = 0;
     hipEvent_t done = nullptr;
     bool pending = false;
 };
@@ -51,7 +59,8 @@ struct wlcs_ctx {
     int device = 0;
     int cus = 256;
     int last_hip = 0;
-    wlcs_rt::Slot slots[wlcs_rt::kSlots];
+    wlcs_rt::Slot slots[wlcs_rt::kMaxSlots];
+    int nslots = 0;  // slots made so far (each with its event)
     int next_slot = 0;
     wlcs_rt::TileRule rules[16];
     int nrules = 0;
