@@ -61,10 +61,14 @@ extern "C" {
 typedef struct wlcs_ctx wlcs_ctx;
 
 /* Create a context on HIP device `device` (ordinal).  *out receives the handle.
- * The context owns device scratch, pinned staging buffers and tuning. */
+ * The context owns device scratch, staging slots and tuning.  A staging slot
+ * is a pinned host buffer and a device buffer of the same size (1 MiB, or
+ * the next power of two above a larger string pair); the context makes them
+ * as calls need them, up to 256 (about one per pair in flight), and reuses a
+ * slot once the work that read it is done. */
 int wlcs_ctx_create(int device, wlcs_ctx **out);
 
-/* Wait for the context's outstanding staging copies and free everything it
+/* Wait for the context's outstanding staging work and free everything it
  * owns.  NULL is accepted. */
 int wlcs_ctx_destroy(wlcs_ctx *ctx);
 
