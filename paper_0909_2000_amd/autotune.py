@@ -15,11 +15,12 @@ The tuner itself is native: ``Context.tune`` calls ``wlcs_tune``, which times
 real batched launches of a seeded synthetic batch for every candidate on the
 device, applies the fastest and keeps them in a JSON cache keyed by device
 name and compute-unit count (this module's command line rewrites the
-package's cache).  ``tune_batch`` and ``tune_plot`` below do the same search
-on a caller's own batch or plot shape, through the same context setters, and
-``load`` / ``apply`` read the cache format from Python.
+package's cache).  ``tune_batch`` below does that search on a caller's own
+batch through the same context setters; ``tune_plot`` measures the tiling of
+one plot shape (the native ``wlcs_tune_plot``); ``load`` / ``apply`` read the
+cache format from Python.
 
-    python -m paper_0909_2000_amd.autotune --out paper_0909_2000_amd/tuning_gfx950.json
+    python -m paper_0909_2000_amd.autotune --out paper_0909_2000_amd/tuning_gfx950.json [--plots]
 """
 from __future__ import annotations
 
@@ -86,23 +87,21 @@ def tune_batch(ctx, specs, log=print) -> dict:
             "batch_ms": {"default": None, "tuned": gtimes[grid]}}
 
 
-def tune_plot(ctx, pair, w, threshold=None, log=print) -> dict:
-    """Tile for single plots of this shape (applies to the w's class)."""
-    import torch
-    rows, cols = max(pair.m - w, 0), max(pair.n - w, 0)
-    out = torch.empty((rows, cols), dtype=torch.uint8, device="cuda")
-    times = {}
-    for t in (0,) + TILES:  # 0 = built-in choice
-        ctx.set_tile(1, 255, t) if t else ctx.set_tile(1, 255, 0)
-        times[t] = _time(torch, lambda: pair.plot(w, threshold=threshold, out=out))
-    ctx.set_tile(1, 255, 0)
-    tile = min(times, key=times.get)
-    log("  plot: " + ", ".join(f"{t or 'auto'}:{v:.2f}ms" for t, v in times.items()) + f" -> {tile or 'auto'}")
-    return {"tile": tile, "ms": times}
+def tune_plot(ctx, pair, w, hx=1, cache_path=None, force=False, log=print) -> tuple:
+    """Measured tiling of one plot shape (the native ``wlcs_tune_plot``): the
+    fastest of a grid of two-length tilings and its neighbourhood, recorded in
+    the context (and in the cache file when given).  Returns (long tile, short
+    tile, long pairs), (0, 0, 0) when the built-in choice was the fastest."""
+    ctx.tune_plot(pair, w, hx=hx, cache_path=cache_path, force=force)
+    rows, cols = -(-max(pair.m - w, 0) // hx), max(pair.n - w, 0)
+    tiling = ctx.plot_tiling(rows, cols, w)
+    log(f"  plot {rows}x{cols}x{w}: {tiling if any(tiling) else 'built-in'}")
+    return tiling
 
 
 def apply(ctx, cache: dict) -> None:
-    """Set a tuning cache's knobs on a context."""
+    """Set a tuning cache entry's batch knobs on a context (its measured plot
+    tilings are applied by ``Context.tune(path)``, which reads the file)."""
     for key, tile in cache.get("batch_tiles", {}).items():
         lo, hi = map(int, key.split("-"))
         ctx.set_batch_tile(lo, hi, int(tile))
@@ -125,6 +124,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   "tuning_gfx950.json"))
+    ap.add_argument("--plots", action="store_true",
+                    help="also record measured tilings of the benchmark's plot shapes (50,000^2 DNA at w = 64, "
+                         "every and every 5th x-window; 30,000^2 protein at w = 128)")
     args = ap.parse_args()
     import torch
 
@@ -134,6 +136,14 @@ def main():
 
     ctx = wl.Context(0)
     ctx.tune(args.out, force=True)
+    if args.plots:
+        import workloads
+        for k, hx in ((2, 1), (3, 1), (2, 5)):
+            p = workloads.config(k)
+            pair = ctx.pair(p.x, p.y, alphabet=p.alphabet)
+            tune_plot(ctx, pair, p.w, hx=hx, cache_path=args.out, force=True,
+                      log=lambda msg: print(msg, file=sys.stderr, flush=True))
+            pair.close()
     entry = load(args.out, torch)
     print(f"tuned on {_device_key(torch)}: {json.dumps(entry)}", file=sys.stderr, flush=True)
     print(json.dumps(entry))
