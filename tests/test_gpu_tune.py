@@ -232,3 +232,23 @@ def test_malformed_plot_records_apply_nothing(tmp_path, plots):
         ctx.tune(str(path))
     assert e.value.status == -1
     assert ctx.batch_grid() == 0 and ctx.plot_tiling(10, 10, 8) == (0, 0, 0)
+
+
+def test_tune_plot_narrow_and_empty_shapes(tmp_path, oracle_mod):
+    """A plot narrower than every candidate tile records the built-in choice
+    ([0, 0, 0]); an empty plot returns at once and records nothing."""
+    import torch
+    import paper_0909_2000_amd as wl
+    ctx = wl.Context(0)
+    x, y, pair = _plot_pair(wl, ctx, seed=72, m=400, n=130)
+    w = 16
+    path = tmp_path / "cache.json"
+    ctx.tune_plot(pair, w, cache_path=str(path))
+    rows, cols = x.size - w, y.size - w
+    entry = json.loads(path.read_text())[_key(torch)]
+    assert entry["plots"][f"{rows}x{cols}x{w}"] == [0, 0, 0]
+    assert ctx.plot_tiling(rows, cols, w) == (0, 0, 0)
+    np.testing.assert_array_equal(pair.plot(w)["wlcs"].cpu().numpy(), oracle_mod.wlcs(x, y, w))
+    tiny = ctx.pair(b"ACGTACGT", b"ACGTACGTAC")
+    ctx.tune_plot(tiny, 8, cache_path=str(path))  # m - w = 0 windows: nothing to tune
+    assert "0x2x8" not in json.loads(path.read_text())[_key(torch)]["plots"]
