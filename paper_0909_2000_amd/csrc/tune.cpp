@@ -12,11 +12,18 @@
 //
 //   { "gfx950-256cu": { "batch_tiles": {"1-16": 512, "17-32": 512, ...},
 //                       "batch_grid": 16,
-//                       "batch_ms": {"default": 81.9, "tuned": 81.0} }, ... }
+//                       "batch_ms": {"default": 81.9, "tuned": 81.0},
+//                       "plots": {"49936x49936x64": [3456, 768, 5], ...},
+//                       "plots_ms": {...} }, ... }
 //
 // The workload is a seeded synthetic batch of uniform random DNA pairs of
 // uneven lengths in every window class; the run time of the method does not
 // depend on the letters, only on m, n and w.
+//
+// The same cache holds measured tilings of single plots ("plots", keyed by
+// rows x cols x window): wlcs_tune_plot times a grid of two-length tilings of
+// one shape on the caller's pair and keeps the fastest; the context then uses
+// it for every plot of that shape instead of the tile model's choice.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
