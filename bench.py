@@ -491,7 +491,7 @@ def bench_serving(ctx, torch, workloads, args):
         if all_at_once:
             for r in reqs:
                 r.arrival = 0.0
-        ex = serve.GpuExecutor(0, streams=3, d2h_bitmaps=d2h)  # its own context, latency tiles
+        ex = serve.GpuExecutor(0, streams=4, d2h_bitmaps=d2h)  # its own context, latency tiles
         srv = serve.Server(ex, budget_bytes=budget, max_jobs=256, max_batch=64, keep_results=False)
         rep = srv.run(reqs)
         torch.cuda.synchronize()

@@ -110,7 +110,7 @@ class GpuExecutor:
     batch's stream before its completion event (result "bitmap_host"), so that
     a job's latency runs until its result is on the host."""
 
-    def __init__(self, device: int = 0, streams: int = 3, ctx=None, d2h_bitmaps: bool = False):
+    def __init__(self, device: int = 0, streams: int = 4, ctx=None, d2h_bitmaps: bool = False):
         import torch
 
         import paper_0909_2000_amd as wl
