@@ -9,9 +9,12 @@ and admits the head while its device footprint (resident letter codes plus
 its outputs) fits the memory budget and a job slot is free.  Admitted jobs
 are launched together as one batch (persistent work-stealing launches,
 ``wlcs_batch``) on one of several streams, so jobs that arrive while earlier
-batches run start on a free stream and overlap them on the device; a batch's
-completion frees its footprint and slots, which admits more jobs.  Latency is
-measured from a job's arrival to the completion of its batch on the device.
+batches run start on a free stream and overlap them on the device.  A batch
+is enqueued as sub-batches of increasing job cost, each with its own
+completion event, so a cheap job completes without waiting for the costly
+ones launched beside it; a job's completion frees its footprint and slot,
+which admits more jobs.  Latency is measured from a job's arrival to the
+completion of its sub-batch on the device.
 
 The scheduler only talks to an executor: ``GpuExecutor`` drives the library on
 one GPU; the tests use a fake executor with a virtual clock to check
@@ -82,6 +85,22 @@ def footprint_bytes(req: Request) -> int:
     return b
 
 
+# A batch is enqueued as sub-batches of increasing cost with an event each; a
+# job up to this many times the cost of the cheapest job of the current
+# sub-batch joins it, a costlier one starts the next.  Every sub-batch costs
+# its own launches and tail, so too fine a split lowers capacity (measured on
+# the serving workload: 16 keeps 98.5% of the capacity of one event per
+# batch and lowers p99 by 10-20% at 0.5-0.75 of capacity; 2 loses 20%).
+SUB_BATCH_RATIO = 16.0
+
+
+def job_cost(js) -> float:
+    """Combing work of a job: x-windows x y-windows x w (its cells, up to the
+    steps' and the window's constant factors)."""
+    r = js.req
+    return float(max(r.x.size - r.w, 1)) / r.hx * max(r.y.size - r.w, 1) * r.w
+
+
 # Batch tiles that favour latency: short tiles give every job many units, so a
 # job spreads over the device even when few others run beside it.
 LATENCY_TILES = {(1, 64): 512, (65, 128): 1024}
@@ -137,8 +156,25 @@ class GpuExecutor:
         return None
 
     def launch(self, batch_id: int, jobs: list) -> None:
+        """Enqueue the jobs on a free stream as sub-batches of increasing cost
+        (a job more than SUB_BATCH_RATIO times the cheapest of the current
+        sub-batch starts the next), each followed by its own completion event:
+        the batch's GPU work is the same, but cheap jobs complete without
+        waiting for the expensive ones launched beside them."""
         k = self.free_stream()
         s = self.streams[k]
+        subs = []
+        for js in sorted(jobs, key=job_cost):
+            if subs and job_cost(js) <= SUB_BATCH_RATIO * job_cost(subs[-1][0]):
+                subs[-1].append(js)
+            else:
+                subs.append([js])
+        pending = []
+        for sub in subs:
+            pending.append((self._launch_sub(s, sub), sub))
+        self.busy[k] = (pending, batch_id)
+
+    def _launch_sub(self, s, jobs: list):
         specs = []
         for js in jobs:
             r = js.req
@@ -161,7 +197,7 @@ class GpuExecutor:
         for js, res, sp in zip(jobs, results, specs):
             js.results = res
             js.results["_pair"] = sp["pair"]  # keeps the resident codes alive until the job is done
-        self.busy[k] = (ev, batch_id)
+        return ev
 
     def dot_counts(self, jobs: list) -> list:
         """Dots each finished job found (None for jobs without a list), read
@@ -174,14 +210,27 @@ class GpuExecutor:
                 out[k] = int(v)
         return out
 
-    def poll(self) -> list:
-        """Batch ids whose work has finished on the device."""
-        done = []
+    def poll_jobs(self) -> list:
+        """(batch id, jobs finished since the last call, whether the whole
+        batch is done) for every batch with newly finished sub-batches; a
+        stream is free again once its batch is done."""
+        out = []
         for k, b in enumerate(self.busy):
-            if b is not None and b[0].query():
-                done.append(b[1])
+            if b is None:
+                continue
+            pending, bid = b
+            fin = []
+            while pending and pending[0][0].query():  # sub-batches finish in stream order
+                fin.extend(pending.pop(0)[1])
+            if fin or not pending:
+                out.append((bid, fin, not pending))
+            if not pending:
                 self.busy[k] = None
-        return done
+        return out
+
+    def poll(self) -> list:
+        """Batch ids whose work has finished on the device (whole batches)."""
+        return [bid for bid, _, done in self.poll_jobs() if done]
 
     def idle_wait(self):
         time.sleep(20e-6)
@@ -227,9 +276,17 @@ class Server:
 
     # -- scheduler -------------------------------------------------------
     def _reap(self):
-        for bid in self.ex.poll():
+        if hasattr(self.ex, "poll_jobs"):  # jobs complete with their own sub-batch
+            finished = self.ex.poll_jobs()
+        else:  # whole batches
+            finished = [(bid, self.running[bid], True) for bid in self.ex.poll()]
+        for bid, batch, batch_done in finished:
             now = self.ex.now()
-            batch = self.running.pop(bid)
+            if batch_done:
+                self.running.pop(bid)
+            else:
+                done_ids = {id(js) for js in batch}
+                self.running[bid] = [js for js in self.running[bid] if id(js) not in done_ids]
             counts = self.ex.dot_counts(batch) if hasattr(self.ex, "dot_counts") else [None] * len(batch)
             retry = []
             for js, found in zip(batch, counts):

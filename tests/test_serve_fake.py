@@ -198,3 +198,76 @@ def test_short_dot_lists_are_rerun_complete(oracle_mod):
         plot = oracle_mod.wlcs(r.x, r.y, r.w)
         assert srv.result(r.jid)["dot_count"] == plot.size
         np.testing.assert_array_equal(srv.result(r.jid)["dots"], oracle_mod.dot_list(plot, r.w, 0))
+
+
+class SubBatchFakeExecutor(FakeExecutor):
+    """Jobs of a batch finish one after another, cheapest first, each at its
+    own time (as the GPU executor's sub-batches with their own events);
+    poll_jobs reports them as they finish."""
+
+    def launch(self, batch_id, jobs):
+        super().launch(batch_id, jobs)  # results, and the stream taken
+        k = next(i for i, b in enumerate(self.busy) if b is not None and b[1] == batch_id)
+        t = self.t + self.overhead
+        fins = []
+        for j in sorted(jobs, key=serve.job_cost):
+            t += float(j.req.x.size) * j.req.y.size * j.req.w / self.rate
+            fins.append((t, j))
+            j.fake_done = t
+        self.busy[k] = (fins[-1][0], batch_id, fins)
+
+    def poll_jobs(self):
+        out = []
+        for k, b in enumerate(self.busy):
+            if b is None:
+                continue
+            fin = [j for t, j in b[2] if t <= self.t + 1e-12]
+            rest = [(t, j) for t, j in b[2] if t > self.t + 1e-12]
+            if fin or not rest:
+                out.append((b[1], fin, not rest))
+            self.busy[k] = (b[0], b[1], rest) if rest else None
+        return out
+
+    def advance(self, next_arrival):
+        fins = [b[2][0][0] for b in self.busy if b is not None and b[2]]
+        cands = fins + ([next_arrival] if next_arrival is not None else [])
+        if cands:
+            self.t = max(self.t, min(cands))
+
+
+def test_jobs_complete_with_their_sub_batch(oracle_mod):
+    """With per-job completion (poll_jobs) every job is done at its own finish
+    time, its footprint is released then, results are unchanged, and the
+    median latency is below that of whole-batch completion on the same
+    stream of jobs."""
+    reqs = _requests(60, 8, rate=400.0)
+    budget = 6 * max(serve.footprint_bytes(r) for r in reqs)
+    ex = SubBatchFakeExecutor(oracle_mod, streams=2)
+    srv = serve.Server(ex, budget_bytes=budget, max_jobs=10, max_batch=4)
+    rep = srv.run(reqs)
+    assert rep["rejected"] == 0 and rep["jobs"] == 60
+    assert srv.peak_use <= budget and srv.in_use == 0 and srv.active == 0 and not srv.running
+    order = [jid for _, jid in srv.admit_log]
+    assert order == sorted(order)
+    for js in srv.jobs.values():
+        assert js.done >= js.launched >= js.admitted >= js.req.arrival
+        assert abs(js.done - js.fake_done) < 1e-9  # observed when it finished, not with its batch
+        alone = oracle_mod.wlcs(js.req.x, js.req.y, js.req.w)
+        np.testing.assert_array_equal(js.results["bitmap"], oracle_mod.dot_bitmap(alone, js.req.threshold))
+    whole = serve.Server(FakeExecutor(oracle_mod, streams=2), budget_bytes=budget, max_jobs=10, max_batch=4)
+    rep_whole = whole.run(_requests(60, 8, rate=400.0))
+    assert rep["p50_s"] < rep_whole["p50_s"]
+
+
+def test_sub_batch_reruns_of_short_dot_lists(oracle_mod):
+    reqs = _requests(10, 9, rate=500.0)
+    for r in reqs:
+        r.indel = False
+        r.threshold = 0
+        r.dot_cap = 5
+    srv = serve.Server(SubBatchFakeExecutor(oracle_mod, streams=2), budget_bytes=1 << 40, max_batch=3)
+    rep = srv.run(reqs)
+    assert rep["rejected"] == 0 and rep["dot_list_reruns"] == 10
+    for r in reqs:
+        plot = oracle_mod.wlcs(r.x, r.y, r.w)
+        assert srv.result(r.jid)["dot_count"] == plot.size
