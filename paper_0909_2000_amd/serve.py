@@ -123,11 +123,13 @@ def _streams(torch, dev, count: int) -> list:
 
 
 class GpuExecutor:
-    """Runs batches on one GPU through libwlcs, one stream per concurrent batch.
-    Without a context of its own it makes one with the latency tiles.  With
-    d2h_bitmaps each job's bitmap is also copied to pinned host memory on the
-    batch's stream before its completion event (result "bitmap_host"), so that
-    a job's latency runs until its result is on the host."""
+    """Runs batches on one GPU through libwlcs, one stream per concurrent batch
+    (from the process's shared stream pool), each batch as sub-batches with
+    their own completion events.  Without a context of its own it makes one
+    with the latency tiles.  With d2h_bitmaps each job's bitmap is also copied
+    to pinned host memory on the stream before its sub-batch's completion event
+    (result "bitmap_host"), so that a job's latency runs until its result is on
+    the host."""
 
     def __init__(self, device: int = 0, streams: int = 4, ctx=None, d2h_bitmaps: bool = False):
         import torch
