@@ -184,10 +184,13 @@ int wlcs_pair_create(wlcs_ctx *ctx, const uint8_t *x, int64_t m, const uint8_t *
                      const uint8_t *alphabet, int32_t sigma, void *stream, wlcs_pair **out);
 
 /* Release a pair's device memory in stream order on its creation stream
- * (no device-wide wait): work already enqueued on that stream still sees the
- * codes; work on other streams that uses the pair must have completed, or be
- * ordered before this point of the creation stream, and the creation stream
- * must still exist.  NULL is accepted. */
+ * (no device-wide wait).  Work already enqueued on that stream still sees the
+ * codes, and so does work that this library enqueued on other streams (plots,
+ * batches, graph replays): every call that reads the pair on another stream
+ * records an event there, and the creation stream waits for those events
+ * before the free.  Work captured into a graph by the caller (not a
+ * wlcs_batch_graph) must have completed.  The creation stream must still
+ * exist.  NULL is accepted. */
 int wlcs_pair_destroy(wlcs_pair *pair);
 
 /* wlcs_plot / wlcs_plot_dp on a resident pair: same window, output, flag and
@@ -284,7 +287,8 @@ int wlcs_batch(wlcs_ctx *ctx, const wlcs_job *jobs, int32_t njobs, void *stream)
 
 /* The same batch captured once into a HIP graph (job table and work counter
  * owned by the graph), to be replayed with wlcs_graph_launch as many times as
- * wanted; each replay recomputes every plot of the batch. */
+ * wanted; each replay recomputes every plot of the batch.  The jobs' pairs and
+ * outputs must outlive the graph. */
 typedef struct wlcs_graph wlcs_graph;
 int wlcs_batch_graph(wlcs_ctx *ctx, const wlcs_job *jobs, int32_t njobs, wlcs_graph **out);
 int wlcs_graph_launch(wlcs_graph *graph, void *stream);

@@ -490,6 +490,40 @@ namespace {
 
 constexpr int32_t kMaxTile = 32768;
 
+// Record that work just enqueued on `stream` reads the pair's codes (see
+// wlcs_pair::use_event).  Nothing to do on the creation stream, nor while the
+// stream is being captured into a graph (the graph's owner keeps the pair
+// alive for as long as it replays it).
+hipError_t note_use(const wlcs_pair* p, hipStream_t stream) {
+    if (stream == p->stream) return hipSuccess;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cs);
+    if (e != hipSuccess) return e;
+    if (cs != hipStreamCaptureStatusNone) return hipSuccess;
+    int k = 0;
+    while (k < p->nuses && p->use_stream[k] != stream) ++k;
+    if (k == p->nuses) {
+        if (p->nuses < wlcs_pair::kUses) {
+            if ((e = hipEventCreateWithFlags(&p->use_event[k], hipEventDisableTiming)) != hipSuccess) return e;
+            ++p->nuses;
+        } else {  // retire the oldest entry: the creation stream waits for it now
+            k = p->next_use;
+            p->next_use = (p->next_use + 1) % wlcs_pair::kUses;
+            if ((e = hipStreamWaitEvent(p->stream, p->use_event[k], 0)) != hipSuccess) return e;
+        }
+        p->use_stream[k] = stream;
+    }
+    return hipEventRecord(p->use_event[k], stream);
+}
+
+// Code-array capacities of a resident pair of m and n letters: room for any
+// window (<= 256 rows of capacity) and any tile pair (<= 2 kMaxTile windows)
+// past the last letter.
+void pair_caps(int64_t m, int64_t n, int64_t& xf_cap, int64_t& yg_cap) {
+    xf_cap = m + 64 + 256 + 64;
+    yg_cap = n + 2 * (int64_t)kMaxTile + 128 + 256 + 64;
+}
+
 int pair_plot_common(Path path, wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, uint8_t* out, int64_t ld,
                      uint64_t* bitmap, int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel,
                      uint32_t flags, void* stream_) {
@@ -517,6 +551,7 @@ int pair_plot_common(Path path, wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w,
     a.sigma = pair->sigma;
     hipStream_t stream = (hipStream_t)stream_;
     hipError_t e = launch_path(path, a, stream);
+    if (e == hipSuccess) e = note_use(pair, stream);
     if (e != hipSuccess) return fail(ctx, e);
     return WLCS_OK;
 }
@@ -571,7 +606,8 @@ int strided_common(Path path, wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, i
     a.xf = pair->xf;
     a.yg = pair->yg;
     a.sigma = pair->sigma;
-    const hipError_t e = launch_path(path, a, stream);
+    hipError_t e = launch_path(path, a, stream);
+    if (e == hipSuccess) e = note_use(pair, stream);
     if (e != hipSuccess) return fail(ctx, e);
     return WLCS_OK;
 }
@@ -585,6 +621,7 @@ struct wlcs_graph {
     unsigned long long** counts = nullptr;  // the jobs' dot counters (zeroed by each replay)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<const wlcs_pair*> pairs;  // read by every replay
 };
 
 namespace {
@@ -928,9 +965,7 @@ int wlcs_pair_create(wlcs_ctx* ctx, const uint8_t* x, int64_t m, const uint8_t* 
     pr->m = m;
     pr->n = n;
     pr->sigma = sigma;
-    // room for any window (<= 256 capacity) and any tile (<= kMaxTile)
-    pr->xf_cap = m + 64 + 256 + 64;
-    pr->yg_cap = n + 2 * (int64_t)kMaxTile + 128 + 256 + 64;
+    pair_caps(m, n, pr->xf_cap, pr->yg_cap);
     pr->stream = stream;
     hipError_t e = hipMallocAsync((void**)&pr->xf, (size_t)pr->xf_cap * 2, stream);
     if (e == hipSuccess) e = hipMallocAsync((void**)&pr->yg, (size_t)pr->yg_cap * 2, stream);
@@ -952,9 +987,13 @@ int wlcs_pair_destroy(wlcs_pair* pair) {
     if (!pair) return WLCS_OK;
     DeviceGuard guard(pair->device);
     int st = WLCS_OK;
-    // stream-ordered release on the creation stream: no device-wide wait
+    // stream-ordered release on the creation stream (no device-wide wait),
+    // after the last work on any other stream that read the codes
+    for (int k = 0; k < pair->nuses; ++k)
+        if (hipStreamWaitEvent(pair->stream, pair->use_event[k], 0) != hipSuccess) st = WLCS_EHIP;
     if (pair->xf && hipFreeAsync(pair->xf, pair->stream) != hipSuccess) st = WLCS_EHIP;
     if (pair->yg && hipFreeAsync(pair->yg, pair->stream) != hipSuccess) st = WLCS_EHIP;
+    for (int k = 0; k < pair->nuses; ++k) (void)hipEventDestroy(pair->use_event[k]);
     delete pair;
     return st;
 }
@@ -1023,6 +1062,7 @@ int wlcs_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, void* stream_
     e = enqueue_batch(ctx, plan, (const wlcs::JobDesc*)dev, (unsigned long long*)(dev + cnt_off),
                       (unsigned long long* const*)(dev + ptr_off), stream);
     if (dev) (void)hipFreeAsync(dev, stream);
+    for (int32_t k = 0; e == hipSuccess && k < njobs; ++k) e = note_use(jobs[k].pair, stream);
     if (e != hipSuccess) return fail(ctx, e);
     return WLCS_OK;
 }
@@ -1056,6 +1096,11 @@ int wlcs_batch_graph(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, wlcs_gr
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     if (cap) (void)hipStreamDestroy(cap);
+    if (e == hipSuccess) {
+        for (int32_t k = 0; k < njobs; ++k)
+            if (std::find(g->pairs.begin(), g->pairs.end(), jobs[k].pair) == g->pairs.end())
+                g->pairs.push_back(jobs[k].pair);
+    }
     if (e != hipSuccess) {
         wlcs_graph_destroy(g);
         return fail(ctx, e);
@@ -1068,7 +1113,10 @@ int wlcs_graph_launch(wlcs_graph* graph, void* stream) {
     if (!graph || !graph->exec) return WLCS_EINVAL;
     DeviceGuard guard(graph->device);
     if (!guard.ok) return WLCS_EHIP;
-    return hipGraphLaunch(graph->exec, (hipStream_t)stream) == hipSuccess ? WLCS_OK : WLCS_EHIP;
+    if (hipGraphLaunch(graph->exec, (hipStream_t)stream) != hipSuccess) return WLCS_EHIP;
+    for (const wlcs_pair* p : graph->pairs)
+        if (note_use(p, (hipStream_t)stream) != hipSuccess) return WLCS_EHIP;
+    return WLCS_OK;
 }
 
 int wlcs_graph_destroy(wlcs_graph* graph) {

@@ -58,7 +58,6 @@ __device__ __forceinline__ int64_t uniform_u64(unsigned long long v) {
     return (int64_t)(((unsigned long long)hi << 32) | lo);
 }
 
-constexpr int group_waves_per_simd(int grp) { return grp == 0 ? min_waves_per_simd(32) : min_waves_per_simd(64); }
 constexpr int group_class(int grp) { return grp == 0 ? 32 : 64; }
 
 // Groups 0 (classes 16 and 32) and 1 (class 64): one wave per unit.
@@ -151,22 +150,6 @@ void launch_group(const JobDesc* jobs_dev, int32_t njobs, int64_t total_units, u
 }
 
 }  // namespace
-
-int batch_variant(int w) {
-    switch (w_class(w)) {
-        case 16: return w == 16 ? kBatch16 : kBatch16Short;
-        case 32: return w == 32 ? kBatch32 : kBatch32Short;
-        case 64: return w == 64 ? kBatch64 : kBatch64Short;
-        default: return w == 128 ? kBatch128 : kBatch128Short;  // w <= kBatchMaxW
-    }
-}
-
-int batch_waves_per_cu(int group) {
-    const int per_simd = group == 0   ? group_waves_per_simd(0)
-                         : group == 1 ? group_waves_per_simd(1)
-                                      : min_waves_per_simd_split(128);
-    return 4 * per_simd;  // four SIMDs per CU
-}
 
 hipError_t launch_batch(int group, const JobDesc* jobs_dev, int32_t njobs, int64_t total_units,
                         unsigned long long* counter, int32_t grid, bool sparse, hipStream_t stream) {

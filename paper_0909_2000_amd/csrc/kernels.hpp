@@ -129,6 +129,13 @@ struct JobDesc {
     int32_t pr0;      // the entry's first tile pair (a job's last pair is an entry of its own)
 };
 
+// Windows staged per lane before a flush: 64 (64-byte row segments) where
+// the LDS budget allows it at the class's occupancy, else 32; 64 whenever only
+// every second window is stored (ws = 2), so a block still fills 32 outputs.
+constexpr int flush_windows(int wc, int ws = 1) { return (wc >= 64 || ws == 2) ? 64 : 32; }
+// Occupancy each window class is compiled for (waves per SIMD): the w labels
+// and w/2 code registers per lane plus the flush temporaries must fit.
+constexpr int min_waves_per_simd(int wc) { return wc <= 32 ? 4 : wc <= 64 ? 3 : wc <= 128 ? 2 : 1; }
 // Score-plot classes (the separator schedule of the seaweed kernel).  Waves
 // per SIMD a class of wc rows is compiled for when one wave holds the whole
 // strip: its wc labels and the codes of its wc / 2 letter rows (wc / 4
@@ -178,10 +185,25 @@ enum BatchVariant {
 };
 constexpr int kBatchGroups = 3;
 constexpr int batch_group(int variant) { return variant <= kBatch32Short ? 0 : variant <= kBatch64Short ? 1 : 2; }
-int batch_variant(int w);
-// resident waves per CU of a group's kernel (the default persistent grid)
-int batch_waves_per_cu(int group);
 constexpr int kBatchMaxW = 128;            // longer windows leave the batched kernels
+// the code path of a window w <= kBatchMaxW
+inline int batch_variant(int w) {
+    switch (w_class(w)) {
+        case 16: return w == 16 ? kBatch16 : kBatch16Short;
+        case 32: return w == 32 ? kBatch32 : kBatch32Short;
+        case 64: return w == 64 ? kBatch64 : kBatch64Short;
+        default: return w == 128 ? kBatch128 : kBatch128Short;
+    }
+}
+// waves per SIMD the one-wave groups are compiled for (their largest class)
+constexpr int group_waves_per_simd(int grp) { return grp == 0 ? min_waves_per_simd(32) : min_waves_per_simd(64); }
+// resident waves per CU of a group's kernel (the default persistent grid)
+inline int batch_waves_per_cu(int group) {
+    const int per_simd = group == 0   ? group_waves_per_simd(0)
+                         : group == 1 ? group_waves_per_simd(1)
+                                      : min_waves_per_simd_split(128);
+    return 4 * per_simd;  // four SIMDs per CU
+}
 // One group's persistent launch over its njobs table entries (unit0 counted
 // from the group's first unit), grid workgroups (group 2: two waves each).
 // sparse: some job stores strided windows or lists dots (the kernel variant

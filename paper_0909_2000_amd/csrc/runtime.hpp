@@ -53,6 +53,16 @@ struct wlcs_pair {
     uint16_t* xf = nullptr;  // capacity xf_cap
     uint16_t* yg = nullptr;  // capacity yg_cap
     int64_t xf_cap = 0, yg_cap = 0;
+    // Other streams that have read the codes: an event recorded after the
+    // last work enqueued there that reads them.  wlcs_pair_destroy makes the
+    // creation stream wait for each before the stream-ordered free, so a
+    // pair dropped while a plot on another stream is still queued is not
+    // released under it.  With more streams than entries, the oldest entry is
+    // retired by making the creation stream wait for its event at once.
+    static constexpr int kUses = 8;
+    mutable hipStream_t use_stream[kUses] = {};
+    mutable hipEvent_t use_event[kUses] = {};
+    mutable int nuses = 0, next_use = 0;
 };
 
 struct wlcs_ctx {

@@ -11,10 +11,6 @@
 
 namespace wlcs {
 
-// Windows staged per lane before a flush: 64 (64-byte row segments) where
-// the LDS budget allows it at the class's occupancy, else 32; 64 whenever only
-// every second window is stored (ws = 2), so a block still fills 32 outputs.
-constexpr int flush_windows(int wc, int ws = 1) { return (wc >= 64 || ws == 2) ? 64 : 32; }
 // dwords per lane row of the staging buffer (one per 4 windows, plus a pad
 // dword that spreads the lanes over the LDS banks)
 constexpr int stage_pitch(int wc, int ws = 1) { return flush_windows(wc, ws) / 4 + 1; }
@@ -30,9 +26,6 @@ __device__ __forceinline__ uint32_t sub_bytes(uint32_t x, uint32_t b4) {
 // the word being cleared apart from the newest marks.
 constexpr int ring_words(int wc) { return wc <= 128 ? 16 : 32; }
 constexpr int stage_dwords(int wc, int ws = 1) { return 2 * 64 * stage_pitch(wc, ws); }
-// Occupancy each window class is compiled for (waves per SIMD): the w labels
-// and w/2 code registers per lane plus the flush temporaries must fit.
-constexpr int min_waves_per_simd(int wc) { return wc <= 32 ? 4 : wc <= 64 ? 3 : wc <= 128 ? 2 : 1; }
 // Stores of a strided or sparse plot for one flushed block: window j0 + b of
 // strip s0 + r sits in byte b of row r of the staged block (stride pitch
 // dwords).  Output column c holds the window c * hy; the lanes of the wave

@@ -84,6 +84,77 @@ def test_tiles_and_relabelling(ctx, oracle_mod, tile):
         np.testing.assert_array_equal(got, want)
 
 
+_LONG_W_CACHE = {}
+
+
+def _long_window_case(oracle_mod, w):
+    """x of 70 windows (two strip blocks, the second ragged) and y of 4,300
+    windows holding mutated copies of x, so the thresholded outputs have dots;
+    the oracle's plot of it (computed once per window)."""
+    if w not in _LONG_W_CACHE:
+        g = workloads.rng(2200 + w)
+        x = workloads.iid(g, w + 70, workloads.DNA)
+        y = workloads.iid(g, w + 4300, workloads.DNA)
+        for k, ys in enumerate((300, 1700, 3900)):
+            seg = x[10 * k:10 * k + w].copy()
+            hit = g.random(w) < 0.08
+            seg[hit] = workloads.iid(g, int(hit.sum()), workloads.DNA)
+            y[ys:ys + w] = seg
+        _LONG_W_CACHE[w] = (x, y, oracle_mod.wlcs(x, y, w))
+    return _LONG_W_CACHE[w]
+
+
+@pytest.mark.parametrize("w", [129, 160, 200, 255])
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+def test_long_windows_across_rebases(ctx, oracle_mod, w, tile):
+    """Windows of 129..255 (the one-wave 256-row class, whose labels reach
+    511 + 2w < 1024 just before the first relabelling) on rows long enough that
+    one tile crosses the relabelling every 512 windows once (1,024-window
+    tiles), three times (2,048) or four times (4,096, one evenly split pair of
+    2,176): whole plot, bitmap and indel distance against the oracle."""
+    _say(f"long windows w={w} tile={tile}")
+    x, y, want = _long_window_case(oracle_mod, w)
+    thr = (3 * w) // 4
+    assert (want >= thr).sum() > 0
+    ctx.set_tile(1, 255, tile)
+    try:
+        got = {k: _cpu(v) for k, v in ctx.plot(x, y, w, threshold=thr, indel=True).items()}
+    finally:
+        ctx.set_tile(1, 255, 0)
+    np.testing.assert_array_equal(got["wlcs"], want)
+    np.testing.assert_array_equal(got["indel"].view(np.uint16), oracle_mod.indel(want, w))
+    np.testing.assert_array_equal(got["bitmap"].view("<u8"), oracle_mod.dot_bitmap(want, thr))
+
+
+def test_long_windows_in_a_batch(ctx, oracle_mod):
+    """Windows above 128 in a batch leave the persistent kernels for
+    single-plot launches on the same stream: with 2,048-window tiles they
+    cross three relabellings per tile, beside jobs of every batched class;
+    every matrix whole against the oracle."""
+    _say("long windows in a batch")
+    pairs, specs, wants = [], [], []
+    for w in (129, 200, 255):
+        x, y, want = _long_window_case(oracle_mod, w)
+        pairs.append(ctx.pair(x, y))
+        specs.append({"pair": pairs[-1], "w": w})
+        wants.append(want)
+    g = workloads.rng(2290)
+    for w in (16, 40, 64, 100, 128):
+        x, y = workloads.iid(g, 90 + w, workloads.DNA), workloads.iid(g, 2500 + w, workloads.DNA)
+        pairs.append(ctx.pair(x, y))
+        specs.append({"pair": pairs[-1], "w": w})
+        wants.append(oracle_mod.wlcs(x, y, w))
+    ctx.set_tile(129, 255, 2048)
+    try:
+        res = ctx.batch(specs)
+        got = [_cpu(r["wlcs"]) for r in res]
+    finally:
+        ctx.set_tile(129, 255, 0)
+    for sp, gw, want in zip(specs, got, wants):
+        assert gw.shape == want.shape, sp["w"]
+        np.testing.assert_array_equal(gw, want, err_msg=f"w={sp['w']}")
+
+
 @pytest.mark.parametrize("long_tile,short_tile,long_pairs", [
     (1024, 64, 1), (512, 128, 2), (576, 192, 3), (2048, 64, 1), (256, 1024, 4), (640, 64, 99)])
 def test_two_tile_lengths(ctx, oracle_mod, long_tile, short_tile, long_pairs):

@@ -32,6 +32,7 @@ kernels:
   pairs skipped at the top of the strip, gives the same exits.
 """
 import itertools
+import re
 
 import numpy as np
 import pytest
@@ -240,27 +241,88 @@ def test_clamp_too_tight_fails(oracle_mod):
     assert bad_found
 
 
+def _shipped_encoding():
+    """The letter encoding, pad code and rebase period as the kernels ship them
+    (read from the kernels' header, so a change there fails the pins below
+    until they are brought along)."""
+    import pathlib
+    src = (pathlib.Path(__file__).resolve().parents[1] / "paper_0909_2000_amd" / "csrc" /
+           "kernels.hpp").read_text()
+    shift = int(re.search(r"constexpr int kCodeShift = (\d+);", src).group(1))
+    pad = int(re.search(r"constexpr uint32_t kPadCode = (\d+);", src).group(1))
+    rebase = int(re.search(r"constexpr int kRebase = (\d+);", src).group(1))
+    # the two code maps, exactly as written there
+    assert "f_code(uint32_t c) { return (uint16_t)(c << kCodeShift); }" in src
+    assert "g_code(uint32_t c) { return (uint16_t)(((64u - c) & 63u) << kCodeShift); }" in src
+    return shift, pad, rebase
+
+
+def _max_label(w, rebase):
+    """Largest label the general schedule gives a seaweed from the top, for
+    window w: walk the tile's columns as the kernel does (w - 1 warm-up
+    columns, then groups of four columns per four windows, the origin moved to
+    window jj - 1 whenever jj is a multiple of the rebase period; the seaweed
+    entering the top of column l carries l - origin + 1) over three periods."""
+    org, top = -w, 0
+    for l in range(w - 1):
+        top = max(top, l - org + 1)
+    for jj in range(0, 3 * rebase, 4):
+        if jj > 0 and jj % rebase == 0:
+            org = jj - 1
+        for l in range(jj + w - 1, jj + w + 3):
+            top = max(top, l - org + 1)
+    return top
+
+
 def test_branch_free_cell_form():
-    """The packed-16-bit cell: codes f(a) = a << 11 for x and g(b) = (32-b) << 11
-    for y add (mod 2^16) to 0 iff a == b and to >= 2^11 otherwise, so with
-    labels below 2^11, bottom = max(s, min(t, Z)), right = s ^ t ^ bottom."""
-    for a in range(32):
-        for b in range(32):
-            z = ((a << 11) + (((32 - b) & 31) << 11)) & 0xFFFF
-            assert (z == 0) == (a == b)
-            assert a == b or z >= 2048
-    g = workloads.rng(270)
-    s = g.integers(0, 2048, 5000)
-    t = g.integers(0, 2048, 5000)
-    match = g.random(5000) < 0.3
-    for sv, tv, mv in zip(s, t, match):
-        z = 0 if mv else 0xF800
-        bottom = max(sv, min(tv, z))
-        right = sv ^ tv ^ bottom
-        if mv:
-            assert (bottom, right) == (sv, tv)
+    """The packed-16-bit cell as the kernels ship it: x letters as
+    f(a) = a << 10 and y letters as g(b) = ((64 - b) mod 64) << 10 add (mod
+    2^16) to Z = 0 iff a == b and to Z >= 1024 otherwise, for all 63 letter
+    codes of y against all 64 x codes (the 64th, 63, is the pad code of the
+    padding rows, which must match no letter).  Every label stays below 1024
+    for every window up to 255 (the largest, 511 + 2w, comes just before the
+    first rebase), so bottom = max(s, min(t, Z)) and right = s ^ t ^ bottom is
+    the combing rule (match: bottom = s, right = t; mismatch: bottom =
+    max(s, t), right = min(s, t)) for every pair of labels that can occur."""
+    shift, pad, rebase = _shipped_encoding()
+    assert (shift, pad, rebase) == (10, 63, 512)
+    a = np.arange(64, dtype=np.int64)[:, None]          # x codes, pad included
+    b = np.arange(63, dtype=np.int64)[None, :]          # y letters
+    z = ((a << shift) + (((64 - b) & 63) << shift)) & 0xFFFF
+    assert np.array_equal(z == 0, a == b)
+    assert (z[a[:, 0] == pad] != 0).all()               # the pad code matches no letter
+    zmin = int(z[z != 0].min())
+    assert zmin == 1 << shift
+    top = max(_max_label(w, rebase) for w in range(1, 256))
+    assert top == 511 + 2 * 255 and top < zmin
+    assert all(_max_label(w, rebase) == 511 + 2 * w for w in (1, 16, 64, 129, 200, 255))
+    # the cell identity for every pair of labels up to the largest one, at Z = 0
+    # (match) and at the smallest mismatch Z and the largest (worst cases)
+    s = np.arange(top + 1, dtype=np.int64)[:, None]
+    t = np.arange(top + 1, dtype=np.int64)[None, :]
+    for zv in (0, zmin, int(z.max())):
+        bottom = np.maximum(s, np.minimum(t, zv))
+        right = s ^ t ^ bottom
+        if zv == 0:
+            assert np.array_equal(bottom, np.broadcast_to(s, bottom.shape))
+            assert np.array_equal(right, np.broadcast_to(t, right.shape))
         else:
-            assert (bottom, right) == (max(sv, tv), min(sv, tv))
+            assert np.array_equal(bottom, np.maximum(s, t))
+            assert np.array_equal(right, np.minimum(s, t))
+
+
+def test_cell_form_fails_past_the_label_bound():
+    """Negative control: a label at the smallest mismatch Z (what a missed
+    rebase would produce) breaks the mismatch rule."""
+    shift, _, _ = _shipped_encoding()
+    zmin = 1 << shift
+    s, t = zmin, 5
+    bottom = max(s, min(t, zmin))
+    right = s ^ t ^ bottom
+    assert (bottom, right) == (max(s, t), min(s, t))  # still right at s == Z ...
+    s, t = 5, zmin + 1
+    bottom = max(s, min(t, zmin))
+    assert bottom != max(s, t)                         # ... but not above it
 
 
 @pytest.mark.parametrize("pad", [1, 7, 15])
