@@ -30,7 +30,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-pthread",
                                "-Wall", "-Werror", _SRC, "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
@@ -56,6 +56,10 @@ def _load():
                                          ctypes.c_int32, i64p, ctypes.c_int64, u8p,
                                          ctypes.c_int64, ctypes.c_int32]
         lib.oracle_wlcs_rows.restype = ctypes.c_int
+        lib.oracle_wlcs_batch.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_int32, i64p, ctypes.c_int64, u8p, ctypes.c_int64,
+                                          ctypes.c_int32]
+        lib.oracle_wlcs_batch.restype = ctypes.c_int
         lib.oracle_wlcs_at.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, ctypes.c_int32,
                                        i64p, i64p, ctypes.c_int64, u8p]
         lib.oracle_wlcs_at.restype = ctypes.c_int
@@ -170,6 +174,30 @@ def wlcs_rows(x, y, w: int, rows, full_range: bool = False,
                                      _p(ids, ctypes.c_int64), ids.size, _p(out), cols, nt)
         if r != 0:
             raise ValueError(f"oracle_wlcs_rows failed ({r})")
+    return out
+
+
+def wlcs_batch(x, y, w: int, rows=None, full_range: bool = False,
+               nthreads: int | None = None) -> np.ndarray:
+    """The plot (or the selected rows, as wlcs_rows) by O-batch: the same
+    dynamic program per window pair, evaluated for 64 neighbouring y-windows
+    side by side (loops interchanged over independent windows; see
+    wlcs_oracle.c).  Equal to wlcs() entry by entry."""
+    x, y = _bytes(x), _bytes(y)
+    cols = n_windows(y.size, w, full_range)
+    if rows is None:
+        ids, nrows = None, n_windows(x.size, w, full_range)
+    else:
+        ids = np.ascontiguousarray(rows, dtype=np.int64)
+        nrows = ids.size
+    out = np.zeros((nrows, cols), dtype=np.uint8)
+    if nrows and cols:
+        nt = nthreads or default_threads()
+        r = _load().oracle_wlcs_batch(_p(x), x.size, _p(y), y.size, w, int(full_range),
+                                      _p(ids, ctypes.c_int64) if ids is not None else None, nrows,
+                                      _p(out), cols, nt)
+        if r != 0:
+            raise ValueError(f"oracle_wlcs_batch failed ({r})")
     return out
 
 

@@ -205,6 +205,122 @@ int oracle_wlcs_at(const uint8_t *x, int64_t m, const uint8_t *y, int64_t n, int
     return ORACLE_OK;
 }
 
+/* ---- O-batch: the same recurrence for 64 neighbouring y-windows at once ----
+ * oracle_wlcs_batch computes what oracle_wlcs computes, with the same dynamic
+ * program for every window pair; only the loops over independent windows are
+ * interchanged.  For one x-window a = x[i..i+w) and the y-windows
+ * b_k = y[j0+k .. j0+k+w) (k < 64), the 64 tables are filled together, cell
+ * by cell in the textbook order (row p = 1..w, then column q = 1..w), one
+ * byte per window (every entry is at most w <= 255):
+ *
+ *     L_k[p][q] = L_k[p-1][q-1] + 1             if a[p-1] == b_k[q-1]
+ *               = max(L_k[p-1][q], L_k[p][q-1])  otherwise
+ *
+ * Only the previous row of each table is kept (row p overwrites row p-1 from
+ * left to right, the textbook space-saving form), with the entries
+ * L_k[p-1][q-1] and L_k[p][q-1] carried along the row.  Letter q-1 of the 64
+ * windows is y[j0+q-1 .. j0+q+63): one contiguous load, so the compiler turns
+ * the loop over k into vector instructions.  The tests pin this function
+ * equal to oracle_wlcs entry by entry. */
+#define OB_LANES 64
+
+__attribute__((target_clones("avx2", "default")))
+static void batch_windows(const uint8_t *a, int w, const uint8_t *y, uint8_t *row, uint8_t *res)
+{
+    for (int q = 0; q <= w; ++q)
+        for (int k = 0; k < OB_LANES; ++k) row[q * OB_LANES + k] = 0;  /* L[0][q] = 0 */
+    for (int p = 1; p <= w; ++p) {
+        const uint8_t ap = a[p - 1];
+        uint8_t diag[OB_LANES], left[OB_LANES];
+        for (int k = 0; k < OB_LANES; ++k) diag[k] = left[k] = 0;     /* L[p-1][0] = L[p][0] = 0 */
+        for (int q = 1; q <= w; ++q) {
+            uint8_t *up = row + q * OB_LANES;                           /* L[p-1][q], becomes L[p][q] */
+            const uint8_t *bq = y + q - 1;                              /* b_k[q-1] = y[j0+k+q-1] */
+            for (int k = 0; k < OB_LANES; ++k) {
+                const uint8_t u = up[k];
+                const uint8_t v = bq[k] == ap ? (uint8_t)(diag[k] + 1) : (u > left[k] ? u : left[k]);
+                diag[k] = u;
+                left[k] = v;
+                up[k] = v;
+            }
+        }
+    }
+    for (int k = 0; k < OB_LANES; ++k) res[k] = row[w * OB_LANES + k];
+}
+
+typedef struct {
+    const uint8_t *x, *ypad;
+    int32_t w;
+    int64_t cols;
+    const int64_t *row_ids;
+    uint8_t *out;
+    int64_t ld;
+    int64_t r0, r1;
+    int status;
+} batch_job;
+
+static void *batch_worker(void *arg)
+{
+    batch_job *jb = (batch_job *)arg;
+    const int w = jb->w;
+    uint8_t *row = (uint8_t *)malloc((size_t)(w + 1) * OB_LANES);
+    if (!row) {
+        jb->status = ORACLE_ENOMEM;
+        return NULL;
+    }
+    uint8_t res[OB_LANES];
+    for (int64_t r = jb->r0; r < jb->r1; ++r) {
+        const int64_t i = jb->row_ids ? jb->row_ids[r] : r;
+        for (int64_t j0 = 0; j0 < jb->cols; j0 += OB_LANES) {
+            batch_windows(jb->x + i, w, jb->ypad + j0, row, res);
+            const int64_t nk = jb->cols - j0 < OB_LANES ? jb->cols - j0 : OB_LANES;
+            memcpy(jb->out + r * jb->ld + j0, res, (size_t)nk);
+        }
+    }
+    free(row);
+    return NULL;
+}
+
+/* The plot rows of oracle_wlcs (row_ids NULL: every x-window; else out row r
+ * holds x-window row_ids[r]) by O-batch. */
+int oracle_wlcs_batch(const uint8_t *x, int64_t m, const uint8_t *y, int64_t n, int32_t w,
+                      int32_t full_range, const int64_t *row_ids, int64_t nrows, uint8_t *out, int64_t ld,
+                      int32_t nthreads)
+{
+    if (m < 0 || n < 0 || w < 1 || w > 255 || nrows < 0) return ORACLE_EINVAL;
+    int64_t rows = n_windows(m, w, full_range), cols = n_windows(n, w, full_range);
+    if (!row_ids) nrows = rows;
+    if (nrows == 0 || cols == 0) return ORACLE_OK;
+    if (!x || !y || !out || ld < cols) return ORACLE_EINVAL;
+    if (row_ids)
+        for (int64_t r = 0; r < nrows; ++r)
+            if (row_ids[r] < 0 || row_ids[r] >= rows) return ORACLE_EINVAL;
+    /* y with room for the last group's 64 lanes (their results are dropped) */
+    uint8_t *ypad = (uint8_t *)calloc((size_t)n + OB_LANES, 1);
+    if (!ypad) return ORACLE_ENOMEM;
+    memcpy(ypad, y, (size_t)n);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (nthreads > nrows) nthreads = (int)nrows;
+    batch_job jobs[256];
+    pthread_t th[256];
+    int started[256];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (batch_job){x, ypad, w, cols, row_ids, out, ld, nrows * t / nthreads,
+                              nrows * (t + 1) / nthreads, ORACLE_OK};
+        started[t] = (t > 0) && pthread_create(&th[t], NULL, batch_worker, &jobs[t]) == 0;
+    }
+    batch_worker(&jobs[0]);
+    int status = jobs[0].status;
+    for (int t = 1; t < nthreads; ++t) {
+        if (started[t]) pthread_join(th[t], NULL);
+        else batch_worker(&jobs[t]);
+        if (jobs[t].status != ORACLE_OK) status = jobs[t].status;
+    }
+    free(ypad);
+    return status;
+}
+
 /* ---- alignment-score plots ----------------------------------------------
  * Section 2 also scores alignments with match 1, mismatch 0 and gap -1/2.  The
  * oracle computes that score directly by the standard dynamic program, kept in

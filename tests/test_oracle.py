@@ -264,3 +264,66 @@ def test_pins_reject_mutants(mutant):
     np.testing.assert_array_equal(good, brute_plot(x, y, w))
     bad = _plot_py(x, y, w, **mutant)
     assert bad.shape != good.shape or np.any(bad != brute_plot(x, y, w))
+
+
+# ---- O-batch: the same recurrence, 64 y-windows side by side ---------------
+
+def test_batch_equals_scalar_on_the_1k_dna_pair(oracle_mod):
+    """The loop-interchanged oracle equals the plain one on the whole
+    1,000 x 1,000 DNA plot at w = 16, for any thread count."""
+    p = workloads.config(1)
+    want = oracle_mod.wlcs(p.x, p.y, p.w)
+    np.testing.assert_array_equal(oracle_mod.wlcs_batch(p.x, p.y, p.w), want)
+    np.testing.assert_array_equal(oracle_mod.wlcs_batch(p.x, p.y, p.w, nthreads=1), want)
+    np.testing.assert_array_equal(oracle_mod.wlcs_batch(p.x, p.y, p.w, nthreads=5), want)
+
+
+@pytest.mark.parametrize("w", [1, 2, 3, 7, 15, 16, 17, 31, 33, 63, 64, 65, 100, 127, 128, 129, 200, 255])
+def test_batch_equals_scalar_on_random_shapes(oracle_mod, w):
+    """Every window class, column counts that are and are not multiples of
+    the 64 lanes, the full range, selected rows, three alphabets."""
+    g = workloads.rng(5000 + w)
+    for alpha in (workloads.DNA, workloads.PROTEIN, b"AB"):
+        m = w + int(g.integers(1, 40))
+        n = w + int(g.choice([1, 63, 64, 65, 127, 130, int(g.integers(1, 300))]))
+        x, y = workloads.iid(g, m, alpha), workloads.iid(g, n, alpha)
+        for full in (False, True):
+            want = oracle_mod.wlcs(x, y, w, full_range=full)
+            np.testing.assert_array_equal(oracle_mod.wlcs_batch(x, y, w, full_range=full), want)
+            if want.shape[0] > 2:
+                rows = g.choice(want.shape[0], size=min(5, want.shape[0]), replace=False)
+                np.testing.assert_array_equal(oracle_mod.wlcs_batch(x, y, w, rows=rows, full_range=full),
+                                              want[rows])
+
+
+def test_batch_degenerate_and_errors(oracle_mod):
+    x = workloads.iid(workloads.rng(5300), 40, workloads.DNA)
+    assert oracle_mod.wlcs_batch(x, x[:10], 12).shape == (28, 0)
+    assert oracle_mod.wlcs_batch(x[:12], x, 12).shape == (0, 28)
+    with pytest.raises(ValueError):
+        oracle_mod.wlcs_batch(x, x, 8, rows=[40])
+    with pytest.raises(ValueError):
+        oracle_mod.wlcs_batch(x, x, 0)
+
+
+def test_full_plot_digests_match_the_scalar_oracle(oracle_mod):
+    """The stored per-row digests of the full 50,000 x 50,000 and 30,000 x
+    30,000 plots (written by O-batch) agree with the plain dynamic program on
+    rows spread over both plots."""
+    import hashlib
+    import json
+    import os
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    with open(os.path.join(gold, "plot_digests.json")) as f:
+        recs = {r["config"]: r for r in json.load(f)["plots"]}
+    for cfg, rows in ((2, [0, 7777, 24968, 49935]), (3, [0, 15000, 29871])):
+        rec = recs[cfg]
+        p = workloads.config(cfg)
+        with open(os.path.join(gold, rec["row_digests_file"]), "rb") as f:
+            raw = f.read()
+        assert hashlib.sha256(raw).hexdigest() == rec["row_digests_sha256"]
+        want = np.frombuffer(raw, dtype="<u8")
+        assert want.size == rec["rows"] == p.m - p.w
+        got = oracle_mod.wlcs_rows(p.x, p.y, p.w, rows)
+        for r, row in zip(rows, got):
+            assert int.from_bytes(hashlib.blake2b(row.tobytes(), digest_size=8).digest(), "little") == want[r]
