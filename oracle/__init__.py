@@ -85,12 +85,17 @@ def _bytes(s) -> np.ndarray:
 
 
 def default_threads() -> int:
-    """Host threads for the oracle: the CPUs this process may run on, at most 16."""
+    """Host threads for the oracle: every CPU this process may run on (its
+    affinity mask), bounded by OMP_NUM_THREADS when that is set (the share of
+    the host a job is given)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return max(1, min(16, n))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
 
 
 def _p(a: np.ndarray, t=ctypes.c_uint8):

@@ -240,8 +240,12 @@ class GpuExecutor:
 
 class Server:
     def __init__(self, executor, budget_bytes: int, max_jobs: int = 256, max_batch: int = 64,
-                 keep_results: bool = True):
+                 keep_results: bool = True, on_done=None):
+        """on_done(request, results), if given, is called once per job when it
+        completes (its sub-batch's event has fired), before the results are
+        released (keep_results=False) -- e.g. to check or copy them."""
         self.ex = executor
+        self.on_done = on_done
         self.budget = int(budget_bytes)
         self.max_jobs = max_jobs
         self.max_batch = max_batch
@@ -304,6 +308,8 @@ class Server:
                     retry.append(js)
                     continue
                 js.done = now
+                if self.on_done is not None:
+                    self.on_done(js.req, js.results)
                 if not self.keep:
                     js.results = None
             for js in reversed(retry):  # ahead of every job that arrived later
