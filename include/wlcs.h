@@ -49,6 +49,7 @@ extern "C" {
 #define WLCS_EHIP (-4)      /* HIP runtime or launch failure (wlcs_ctx_last_hip_error) */
 #define WLCS_ENOMEM (-5)    /* host or device allocation failed */
 #define WLCS_EIO (-6)       /* a file could not be written (wlcs_tune's cache) */
+#define WLCS_ESCRATCH (-7)  /* a batch needs more than wlcs_batch_noalloc's fixed scratch */
 
 #define WLCS_MAX_W 255         /* WLCS values must fit the uint8 output */
 #define WLCS_MAX_SIGMA 63      /* letters per alphabet (a 64th code is kept for padding rows) */
@@ -284,6 +285,27 @@ typedef struct {
  * the table built from it are consumed before the call returns; pairs and
  * outputs must stay valid until the stream has run the batch. */
 int wlcs_batch(wlcs_ctx *ctx, const wlcs_job *jobs, int32_t njobs, void *stream);
+
+/* wlcs_batch for callers that cannot allocate (code under stream capture,
+ * serving loops, harnesses that forbid allocation): the same plots, the same
+ * kernels and the same job checks, but the job table, the work counters and
+ * the dot counters' addresses live in a fixed device scratch of
+ * WLCS_NOALLOC_SCRATCH_BYTES (1 MiB) that each device holds for the life of
+ * the process, written in stream order by small kernels that carry the
+ * table in their arguments.  No device, pinned or managed memory is allocated
+ * or freed, and nothing is copied through a staging buffer; the host-side
+ * plan reuses per-thread buffers once they have held a batch as large.  A
+ * batch whose table, counters and addresses exceed the scratch returns
+ * WLCS_ESCRATCH before anything is enqueued: a job takes one or two table
+ * entries of 176 bytes (two when its rows span more than one pair of
+ * y-tiles) and 8 bytes if it lists dots, so about 2,900 jobs always fit.  Every call on a device shares that device's
+ * scratch: calls that overlap on one device (on different streams, or from
+ * different threads) race and must not be made; calls one after another on
+ * one stream are ordered.  Windows above 128 run as in wlcs_batch (their
+ * single-plot launches use no scratch).  Pairs and outputs must stay valid
+ * until the stream has run the batch. */
+#define WLCS_NOALLOC_SCRATCH_BYTES (1u << 20)
+int wlcs_batch_noalloc(wlcs_ctx *ctx, const wlcs_job *jobs, int32_t njobs, void *stream);
 
 /* The same batch captured once into a HIP graph (job table and work counter
  * owned by the graph), to be replayed with wlcs_graph_launch as many times as

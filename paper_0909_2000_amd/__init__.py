@@ -97,6 +97,7 @@ def _load():
     lib.wlcs_score_plot.argtypes = [vp, u8p, i64, u8p, i64, i32, i32, u8p, i32, vp, i64, vp, i64, i32,
                                     u32, vp]
     lib.wlcs_batch.argtypes = [vp, ctypes.POINTER(Job), i32, vp]
+    lib.wlcs_batch_noalloc.argtypes = [vp, ctypes.POINTER(Job), i32, vp]
     lib.wlcs_batch_graph.argtypes = [vp, ctypes.POINTER(Job), i32, ctypes.POINTER(vp)]
     lib.wlcs_graph_launch.argtypes = [vp, vp]
     lib.wlcs_graph_destroy.argtypes = [vp]
@@ -114,8 +115,8 @@ def _load():
     for f in ("wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_ctx_set_tile", "wlcs_ctx_set_tiles",
               "wlcs_measure_valu_peak",
               "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot",
-              "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_graph", "wlcs_graph_launch",
-              "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
+              "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_noalloc", "wlcs_batch_graph",
+              "wlcs_graph_launch", "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
               "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
               "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs",
               "wlcs_pair_plot_blcs", "wlcs_tune_plot", "wlcs_ctx_get_plot_tiling"):
@@ -129,7 +130,7 @@ def exported_symbols() -> list:
     return ["wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_status_str",
             "wlcs_ctx_set_tile", "wlcs_ctx_set_tiles", "wlcs_measure_valu_peak", "wlcs_plot", "wlcs_plot_dp",
             "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch",
-            "wlcs_batch_graph", "wlcs_graph_launch", "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
+            "wlcs_batch_noalloc", "wlcs_batch_graph", "wlcs_graph_launch", "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
             "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
             "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs", "wlcs_pair_plot_blcs",
             "wlcs_tune_plot", "wlcs_ctx_get_plot_tiling"]
@@ -381,6 +382,19 @@ class Context:
         st = lib.wlcs_batch(self._h, arr, len(specs), ctypes.c_void_p(stream.cuda_stream))
         if st != 0:
             raise WlcsError(st, "wlcs_batch", lib.wlcs_ctx_last_hip_error(self._h))
+        return results
+
+    def batch_noalloc(self, specs, stream=None) -> list:
+        """The same plots through wlcs_batch_noalloc: the library allocates no
+        device memory for the call (the outputs here are still torch tensors
+        unless the specs bring their own).  Calls that overlap on one device
+        race on its fixed scratch."""
+        lib = _load()
+        arr, results = self._jobs(specs)
+        stream = self._stream(stream)
+        st = lib.wlcs_batch_noalloc(self._h, arr, len(specs), ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise WlcsError(st, "wlcs_batch_noalloc", lib.wlcs_ctx_last_hip_error(self._h))
         return results
 
     def batch_graph(self, specs) -> "BatchGraph":

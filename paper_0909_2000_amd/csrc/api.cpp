@@ -638,6 +638,14 @@ int32_t batch_tile(const wlcs_ctx* ctx, int64_t cols, int32_t w) {
     return (int32_t)t;
 }
 
+// One table entry being planned: a job's tile pairs but the last, or its last pair.
+struct PlanItem {
+    wlcs::JobDesc d;
+    double cost;  // of one unit
+    bool last;    // the job's last tile pair
+    int32_t seq;  // order of creation (ties keep it)
+};
+
 struct BatchPlan {
     // jobs with w <= kBatchMaxW, by kernel group, then by decreasing unit cost
     // within a group; a group's unit0 values count from its own first unit
@@ -647,16 +655,26 @@ struct BatchPlan {
     bool sparse[wlcs::kBatchGroups] = {};        // some job of the group is strided or lists dots
     std::vector<wlcs::PlotArgs> singles;         // longer windows: single-plot launches
     std::vector<unsigned long long*> counts;     // every job's dot counter, zeroed first
+    std::vector<PlanItem> items;                 // working list of plan_batch
+    // empty again, keeping the vectors' storage for the next batch
+    void clear() {
+        table.clear();
+        singles.clear();
+        counts.clear();
+        items.clear();
+        for (int g = 0; g < wlcs::kBatchGroups; ++g) {
+            first[g + 1] = 0;
+            units[g] = 0;
+            sparse[g] = false;
+        }
+        first[0] = 0;
+    }
 };
 
 int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& plan) {
     if (!ctx || njobs < 0 || (njobs > 0 && !jobs)) return WLCS_EINVAL;
-    struct Item {
-        wlcs::JobDesc d;
-        double cost;  // of one unit
-        bool last;    // the job's last tile pair
-    };
-    std::vector<Item> items;
+    using Item = PlanItem;
+    std::vector<Item>& items = plan.items;
     for (int32_t k = 0; k < njobs; ++k) {
         const wlcs_job& j = jobs[k];
         if (j.flags & ~WLCS_FULL_RANGE) return WLCS_EINVAL;
@@ -715,6 +733,7 @@ int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& pl
             it.d.pr0 = 0;
             it.last = false;
             it.cost = 2.0 * (double)(a.tile + j.w - 1) * (double)j.w;
+            it.seq = (int32_t)items.size();
             items.push_back(it);
         }
         int64_t start;
@@ -723,13 +742,17 @@ int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& pl
         it.d.pr0 = a.npairs - 1;
         it.last = true;
         it.cost = 2.0 * (double)(tlast + j.w - 1) * (double)j.w;
+        it.seq = (int32_t)items.size();
         items.push_back(it);
     }
-    std::stable_sort(items.begin(), items.end(), [](const Item& p, const Item& q) {
+    // (an unstable sort with the creation order as the last key: the same
+    // order as a stable sort, without its temporary buffer)
+    std::sort(items.begin(), items.end(), [](const Item& p, const Item& q) {
         const int gp = wlcs::batch_group(p.d.variant), gq = wlcs::batch_group(q.d.variant);
         if (gp != gq) return gp < gq;
         if (p.last != q.last) return q.last;
-        return p.cost > q.cost;
+        if (p.cost != q.cost) return p.cost > q.cost;
+        return p.seq < q.seq;
     });
     if (items.size() > 0x7FFFFFFF) return WLCS_ERANGE;  // table entries are counted in int32
     for (const Item& it : items) {
@@ -791,6 +814,12 @@ int wlcs_ctx_create(int device, wlcs_ctx** out) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         ctx->cus = cus;
+    // the allocation-free batch's scratch on this device (once per device)
+    const hipError_t e = wlcs::scratch_address(device, &ctx->scratch);
+    if (e != hipSuccess) {
+        ctx->scratch = nullptr;
+        ctx->scratch_err = (int)e;
+    }
     *out = ctx;
     return WLCS_OK;
 }
@@ -850,6 +879,7 @@ const char* wlcs_status_str(int status) {
         case WLCS_EHIP: return "HIP runtime error";
         case WLCS_ENOMEM: return "out of memory";
         case WLCS_EIO: return "file could not be written";
+        case WLCS_ESCRATCH: return "batch too large for the fixed scratch of wlcs_batch_noalloc";
         default: return "unknown status";
     }
 }
@@ -1063,6 +1093,39 @@ int wlcs_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, void* stream_
                       (unsigned long long* const*)(dev + ptr_off), stream);
     if (dev) (void)hipFreeAsync(dev, stream);
     for (int32_t k = 0; e == hipSuccess && k < njobs; ++k) e = note_use(jobs[k].pair, stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    return WLCS_OK;
+}
+
+static_assert(wlcs::kNoAllocScratchBytes == WLCS_NOALLOC_SCRATCH_BYTES, "scratch size of the C ABI");
+static_assert(sizeof(wlcs::JobDesc) == 176, "table entry size stated in the C ABI");
+
+int wlcs_batch_noalloc(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, void* stream_) {
+    // the plan's vectors are kept per thread: once they have held a batch
+    // this large, planning takes no host memory either
+    thread_local BatchPlan plan;
+    plan.clear();
+    int st = plan_batch(ctx, jobs, njobs, plan);
+    if (st != WLCS_OK) return st;
+    if (plan.table.empty() && plan.singles.empty() && plan.counts.empty()) return WLCS_OK;
+    // the scratch holds the job table, the groups' work counters (zeroed by a
+    // kernel before each group's launch) and the dot counters' addresses
+    const size_t tbytes = plan.table.size() * sizeof(wlcs::JobDesc);
+    const size_t cnt_off = (tbytes + 255) / 256 * 256;
+    const size_t ptr_off = cnt_off + 256, pbytes = plan.counts.size() * sizeof(unsigned long long*);
+    if (plan.table.size() > wlcs::kNoAllocScratchBytes || plan.counts.size() > wlcs::kNoAllocScratchBytes ||
+        ptr_off + pbytes > wlcs::kNoAllocScratchBytes)
+        return WLCS_ESCRATCH;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
+    if (!ctx->scratch) return fail(ctx, (hipError_t)ctx->scratch_err);
+    hipStream_t stream = (hipStream_t)stream_;
+    uint8_t* const scr = ctx->scratch;
+    hipError_t e = wlcs::launch_upload(scr, (const uint8_t*)plan.table.data(), tbytes, stream);
+    if (e == hipSuccess && pbytes) e = wlcs::launch_upload(scr + ptr_off, (const uint8_t*)plan.counts.data(), pbytes, stream);
+    if (e == hipSuccess)
+        e = enqueue_batch(ctx, plan, (const wlcs::JobDesc*)scr, (unsigned long long*)(scr + cnt_off),
+                          (unsigned long long* const*)(scr + ptr_off), stream);
     if (e != hipSuccess) return fail(ctx, e);
     return WLCS_OK;
 }

@@ -20,7 +20,10 @@
 // the tail of the queue holds the cheapest units.  Windows up to 128
 // run here; longer windows run as separate single-plot launches on the same
 // stream.
+#include <string.h>
+
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.hpp"
 #include "seaweed_unit.hpp"
@@ -121,6 +124,28 @@ __global__ __launch_bounds__(128, min_waves_per_simd_split(128)) void batch_kern
     }
 }
 
+// Scratch of the allocation-free batch (wlcs_batch_noalloc): the job table,
+// the groups' work counters and the dot counters' addresses of one batch.
+// Each device holds its own copy for the life of the process; host code uses
+// the address hipGetSymbolAddress gives for the device (scratch_address),
+// never this name.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+// One piece of the host bytes to place in the scratch, carried in the
+// launch's own argument: nothing on the host has to outlive the call, and
+// no copy engine or staging buffer is involved.
+struct UploadChunk {
+    uint32_t off;    // byte offset in the destination (a multiple of 4)
+    uint32_t words;  // dwords carried
+    uint32_t data[kUploadChunkWords];
+};
+static_assert(sizeof(UploadChunk) + sizeof(void*) <= 4096, "kernel arguments");
+
+__global__ void upload_chunk(uint8_t* __restrict__ dst, UploadChunk c) {
+    uint32_t* d = (uint32_t*)(dst + c.off);
+    for (uint32_t k = threadIdx.x; k < c.words; k += blockDim.x) d[k] = c.data[k];
+}
+
 __global__ void zero_counter(unsigned long long* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
 }
@@ -171,6 +196,37 @@ hipError_t launch_zero_each(unsigned long long* const* ptrs, int32_t n, hipStrea
     const int32_t blocks = std::min<int32_t>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(zero_each, dim3((uint32_t)blocks), dim3(256), 0, stream, ptrs, n);
     return hipGetLastError();
+}
+
+hipError_t scratch_address(int device, uint8_t** ptr) {
+    static std::mutex mu;
+    static uint8_t* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        // the caller has made `device` current; each device has its own copy
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = (uint8_t*)p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_upload(uint8_t* dst, const uint8_t* src, size_t bytes, hipStream_t stream) {
+    if (bytes % 4) return hipErrorInvalidValue;
+    for (size_t off = 0; off < bytes; off += 4 * kUploadChunkWords) {
+        UploadChunk c;
+        c.off = (uint32_t)off;
+        c.words = (uint32_t)std::min<size_t>(kUploadChunkWords, (bytes - off) / 4);
+        memcpy(c.data, src + off, 4 * (size_t)c.words);
+        hipLaunchKernelGGL(upload_chunk, dim3(1), dim3(256), 0, stream, dst, c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace wlcs

@@ -213,4 +213,16 @@ hipError_t launch_batch(int group, const JobDesc* jobs_dev, int32_t njobs, int64
 // *ptrs[k] = 0 for k < n
 hipError_t launch_zero_each(unsigned long long* const* ptrs, int32_t n, hipStream_t stream);
 
+// The fixed device scratch of the allocation-free batch (batch.hip): its
+// size, and its address on `device` (looked up once per device, with that
+// device current).
+constexpr size_t kNoAllocScratchBytes = 1u << 20;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_address(int device, uint8_t** ptr);
+// Copy `bytes` (a multiple of 4) host bytes to device memory dst in stream
+// order, carried in the arguments of small kernels (kUploadChunkWords dwords
+// each): the host bytes may be reused on return.
+constexpr int kUploadChunkWords = 960;
+hipError_t launch_upload(uint8_t* dst, const uint8_t* src, size_t bytes, hipStream_t stream);
+
 }  // namespace wlcs

@@ -81,6 +81,10 @@ struct wlcs_ctx {
     int tile_cache_next = 0;
     wlcs_rt::TileChoice tuned[wlcs_rt::kTuned];  // measured tilings by shape (general plots, ws = 1)
     int ntuned = 0, tuned_next = 0;
+    // the device's fixed scratch of wlcs_batch_noalloc (looked up at creation;
+    // null with the HIP error kept if the lookup failed)
+    uint8_t* scratch = nullptr;
+    int scratch_err = 0;
 };
 
 namespace wlcs_rt {

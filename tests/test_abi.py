@@ -147,3 +147,10 @@ def test_struct_layouts_match_the_header(tmp_path):
 
 def test_status_string_for_file_errors(lib):
     assert lib.wlcs_status_str(-6) == b"file could not be written"
+
+
+def test_noalloc_batch_checks_and_status(lib):
+    """The allocation-free batch rejects a missing context before any device
+    work, and its size error has a status string of its own."""
+    assert lib.wlcs_batch_noalloc(None, None, 0, None) == EINVAL
+    assert lib.wlcs_status_str(-7) == b"batch too large for the fixed scratch of wlcs_batch_noalloc"
