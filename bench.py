@@ -367,6 +367,12 @@ def main():
         log(f"step 5 (paper's vertical step): {step5['ms']:.2f} ms, {step5['dots']} dots, "
             f"DP {step5['dp_ms']:.1f} ms ({step5['speedup_over_dp']:.0f}x)")
 
+    dots_filter = None
+    if not args.no_configs:
+        dots_filter = bench_dots_filter(ctx, torch, workloads)
+        log("dot list at WLCS >= 48, every strip: {:.2f} ms; probe filter: {}".format(
+            dots_filter["plain_ms"], ", ".join(f"h={h} {v['ms']:.2f} ms" for h, v in dots_filter["filtered"].items())))
+
     rec = {
         "metric": METRIC, "value": value, "unit": "window-cells/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -380,7 +386,7 @@ def main():
                                   else "built-in tile model")},
         "roofline": roofline, "cpu_baseline": cpu, "gpu_dp_baseline": dp,
         "other_configs": others, "paper_shaped_score_plots": paper_shapes,
-        "batched": batched, "serving": serving, "step5_lcs_plot": step5,
+        "batched": batched, "serving": serving, "step5_lcs_plot": step5, "dot_list_filter": dots_filter,
         "encode_ms": encode_ms, "parity_sampled_rows": parity,
         "kernel_ms": {"min": float(np.min(kern_ms)), "median": float(np.median(kern_ms)),
                       "max": float(np.max(kern_ms))},
@@ -539,7 +545,8 @@ def _timed_once(torch, fn):
 def serving_child(args):
     """The serving leg alone (a child process of the benchmark): waits for a
     line on stdin, serves, prints one JSON line on stdout."""
-    sys.stdin.readline()
+    if sys.stdin.readline().strip() != "go":
+        return  # the parent ended before the serving leg (its end of the pipe closed)
     import torch
 
     import workloads
@@ -616,6 +623,44 @@ def bench_serving(ctx, torch, workloads, args):
                        "outputs": "dot list (12-byte records: i, j, WLCS, indel) at T=ceil(3w/4), "
                                   "first capacity max(4096, windows/64) per job, jobs with more "
                                   "dots rerun with an exact list"}}
+
+
+def bench_dots_filter(ctx, torch, workloads, reps=5):
+    """The 50,000 x 50,000 DNA pair's dot list at WLCS >= 48 (every window
+    pair, w = 64): the plain dot list of every strip, then the exact probe
+    filter at several probe steps (only every h-th strip combed, the rows in
+    reach of the threshold evaluated one by one); every filtered list is
+    compared with the plain one."""
+    import numpy as np
+    import paper_0909_2000_amd as wl
+    p = workloads.config(2)
+    pair = ctx.pair(p.x, p.y)
+    cap = 4 << 20
+    dots = torch.empty((cap, 3), dtype=torch.int32, device="cuda")
+    count = torch.empty(1, dtype=torch.int64, device="cuda")
+
+    def plain():
+        pair.plot_strided(p.w, 1, 1, threshold=p.threshold, want_plot=False, dots_out=dots, count_out=count)
+
+    plain()
+    torch.cuda.synchronize()
+    plain_ms = float(np.median([_timed_once(torch, plain) for _ in range(reps)]))
+    want, n_want = wl.dot_records({"dots": dots, "dot_count": count})
+    out = {"m": p.m, "n": p.n, "w": p.w, "threshold": p.threshold, "dots": n_want, "plain_ms": plain_ms,
+           "filtered": {}}
+    for h in (2, 4, 6, 8, 12):
+        def filt():
+            pair.dots_filtered(p.w, p.threshold, probe_step=h, dots_out=dots, count_out=count)
+        filt()
+        torch.cuda.synchronize()
+        ms = float(np.median([_timed_once(torch, filt) for _ in range(reps)]))
+        got, n_got = wl.dot_records({"dots": dots, "dot_count": count})
+        out["filtered"][str(h)] = {"ms": ms, "speedup": plain_ms / ms,
+                                   "equal": bool(n_got == n_want and np.array_equal(got, want))}
+    pair.close()
+    del dots
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_step5(ctx, torch, workloads, reps=5):

@@ -252,6 +252,33 @@ int wlcs_pair_plot_dp_strided(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, i
                               int32_t threshold, uint16_t *indel, int64_t ld_indel, wlcs_dot *dots,
                               int64_t dot_cap, uint64_t *dot_count, uint32_t flags, void *stream);
 
+/* The dot list of a resident pair (every window pair with WLCS >= threshold,
+ * as wlcs_pair_plot_strided lists it with hx = hy = 1), exact, without combing
+ * every strip.  Section 3 notes that the per-window dynamic program can use
+ * the threshold, and the Conclusions propose a heuristic like that of Ott et
+ * al. for the seaweed method; this is an exact version of such a filter.  It
+ * rests on one property of the plot: moving the x-window by one letter changes
+ * its LLCS with any y-window by at most one, so |WLCS(i + d, j) - WLCS(i, j)|
+ * <= |d|.  The probe strips -- every probe_step-th x-window and the last one
+ * -- are combed and listed at threshold - floor(probe_step / 2); every other
+ * row takes its nearest probe (the lower one on ties), and only its windows
+ * whose probe entry comes within reach of the threshold are evaluated, each
+ * exactly (bit-parallel LCS of the window pair).  probe_step = 1 combs every
+ * strip.  The list is unique and complete; the order of the records is not
+ * defined.  The probe entries go to a list of probe_cap records (0: the
+ * library picks one entry per 32 probe window pairs, at least 65,536, at most
+ * 2^27); if they exceed it, a gated launch lists every strip instead, so the
+ * result stays exact.  *dot_count (device) receives the number of dots, even
+ * past dot_cap; records beyond dot_cap are not written.  Cost: the probe
+ * strips (a 1 / probe_step share of the plot) plus the candidates, whose
+ * number grows quickly as threshold - probe_step / 2 nears the background
+ * level of the plot.  Errors: WLCS_ERANGE for w outside 1..WLCS_MAX_W or
+ * probe_step < 1; WLCS_EINVAL for a null dot_count, threshold outside 0..255,
+ * or negative capacities. */
+int wlcs_pair_dots_filtered(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, int32_t threshold,
+                            int32_t probe_step, int64_t probe_cap, wlcs_dot *dots, int64_t dot_cap,
+                            uint64_t *dot_count, uint32_t flags, void *stream);
+
 /* ---- batched plots ------------------------------------------------------
  * Many plots of uneven m, n and w in persistent, work-stealing launches: the
  * plots' units (64 x-windows against two y-tiles) go into device-wide queues
@@ -297,8 +324,8 @@ int wlcs_batch(wlcs_ctx *ctx, const wlcs_job *jobs, int32_t njobs, void *stream)
  * plan reuses per-thread buffers once they have held a batch as large.  A
  * batch whose table, counters and addresses exceed the scratch returns
  * WLCS_ESCRATCH before anything is enqueued: a job takes one or two table
- * entries of 176 bytes (two when its rows span more than one pair of
- * y-tiles) and 8 bytes if it lists dots, so about 2,900 jobs always fit.  Every call on a device shares that device's
+ * entries of 184 bytes (two when its rows span more than one pair of
+ * y-tiles) and 8 bytes if it lists dots, so about 2,780 jobs always fit.  Every call on a device shares that device's
  * scratch: calls that overlap on one device (on different streams, or from
  * different threads) race and must not be made; calls one after another on
  * one stream are ordered.  Windows above 128 run as in wlcs_batch (their

@@ -111,6 +111,7 @@ def _load():
                                              ctypes.POINTER(i32)]
     strided_args = [vp, vp, i32, i32, i32, vp, i64, vp, i64, i32, vp, i64, vp, i64, vp, ctypes.c_uint32, vp]
     lib.wlcs_pair_plot_strided.argtypes = strided_args
+    lib.wlcs_pair_dots_filtered.argtypes = [vp, vp, i32, i32, i32, i64, vp, i64, vp, ctypes.c_uint32, vp]
     lib.wlcs_pair_plot_dp_strided.argtypes = strided_args
     for f in ("wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_ctx_set_tile", "wlcs_ctx_set_tiles",
               "wlcs_measure_valu_peak",
@@ -119,7 +120,7 @@ def _load():
               "wlcs_graph_launch", "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
               "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
               "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs",
-              "wlcs_pair_plot_blcs", "wlcs_tune_plot", "wlcs_ctx_get_plot_tiling"):
+              "wlcs_pair_plot_blcs", "wlcs_pair_dots_filtered", "wlcs_tune_plot", "wlcs_ctx_get_plot_tiling"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -133,6 +134,7 @@ def exported_symbols() -> list:
             "wlcs_batch_noalloc", "wlcs_batch_graph", "wlcs_graph_launch", "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
             "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
             "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs", "wlcs_pair_plot_blcs",
+            "wlcs_pair_dots_filtered",
             "wlcs_tune_plot", "wlcs_ctx_get_plot_tiling"]
 
 
@@ -569,6 +571,28 @@ class Pair:
         hy == 1 and no dot list is asked for."""
         return self._run_strided("wlcs_pair_plot_strided", w, hx, hy, threshold, indel, want_plot, bitmap,
                                  dot_cap, full_range, out, bitmap_out, indel_out, dots_out, count_out, stream)
+
+    def dots_filtered(self, w, threshold, probe_step=8, probe_cap=0, dot_cap=None, dots_out=None,
+                      count_out=None, full_range=False, stream=None) -> dict:
+        """The exact dot list (WLCS >= threshold) through the probe filter
+        (wlcs_pair_dots_filtered): 'dots' (records as plot_strided lists them)
+        and 'dot_count' (device), for wl.dot_records."""
+        lib = _load()
+        c = self.ctx
+        dev = torch.device("cuda", c.device)
+        if dots_out is None and dot_cap:
+            dots_out = torch.empty((int(dot_cap), 3), dtype=torch.int32, device=dev)
+        if count_out is None:
+            count_out = torch.empty(1, dtype=torch.int64, device=dev)
+        stream = c._stream(stream)
+        st = lib.wlcs_pair_dots_filtered(c.handle, self._h, int(w), int(threshold), int(probe_step),
+                                         int(probe_cap), dots_out.data_ptr() if dots_out is not None else None,
+                                         int(dots_out.shape[0]) if dots_out is not None else 0,
+                                         count_out.data_ptr(), WLCS_FULL_RANGE if full_range else 0,
+                                         ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise WlcsError(st, "wlcs_pair_dots_filtered", lib.wlcs_ctx_last_hip_error(c.handle))
+        return {"dots": dots_out, "dot_count": count_out}
 
     def plot_dp_strided(self, w, hx=1, hy=1, threshold=None, indel=False, want_plot=True, bitmap=None,
                         dot_cap=None, full_range=False, out=None, bitmap_out=None, indel_out=None,

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwlcs.so")
-SOURCES = ["api.cpp", "tune.cpp", "seaweed.hip", "dp.hip", "batch.hip", "blcs.hip", "probe.hip"]
+SOURCES = ["api.cpp", "tune.cpp", "seaweed.hip", "dp.hip", "batch.hip", "blcs.hip", "filter.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1051,6 +1051,104 @@ int wlcs_pair_plot_dp_strided(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, i
                           dots, dot_cap, dot_count, flags, stream);
 }
 
+int wlcs_pair_dots_filtered(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, int32_t threshold,
+                            int32_t probe_step, int64_t probe_cap, wlcs_dot* dots, int64_t dot_cap,
+                            uint64_t* dot_count, uint32_t flags, void* stream_) {
+    if (flags & ~WLCS_FULL_RANGE) return WLCS_EINVAL;
+    if (!pair || !dot_count || (!dots && dot_cap > 0) || dot_cap < 0 || probe_cap < 0) return WLCS_EINVAL;
+    if (w < 1 || w > WLCS_MAX_W || probe_step < 1) return WLCS_ERANGE;
+    if (threshold < 0 || threshold > 255) return WLCS_EINVAL;
+    const bool full = (flags & WLCS_FULL_RANGE) != 0;
+    const int64_t rows = n_windows(pair->m, w, full), cols = n_windows(pair->n, w, full);
+    if (rows > 0 && cols > 0 && ((rows - 1) > 0xFFFFFFFFll || (cols - 1) > 0xFFFFFFFFll))
+        return WLCS_ERANGE;  // window starts must fit the record's 32-bit fields
+    if (!ctx || ctx->device != pair->device) return WLCS_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
+    hipStream_t stream = (hipStream_t)stream_;
+    hipError_t e = wlcs::launch_zero_u64((unsigned long long*)dot_count, stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    if (rows == 0 || cols == 0) return WLCS_OK;
+    const int64_t h = probe_step;
+    const int64_t rows_a = (rows + h - 1) / h;            // probe strips 0, h, 2h, ...
+    const bool extra = (rows - 1) % h != 0;               // and the last x-window
+    const int64_t probe_rows = rows_a + (extra ? 1 : 0);
+    if (probe_cap == 0)  // about one entry in 32 of the probe strips, at least 64 Ki, at most 128 Mi
+        probe_cap = std::min<int64_t>(std::max<int64_t>(65536, probe_rows * cols / 32), (int64_t)1 << 27);
+    if (pair->m + wlcs::w_class(w) > pair->xf_cap) return WLCS_EINVAL;  // cannot happen for a valid pair
+    // probe list, its counter and the fallback flag, for this call
+    const size_t list_bytes = (size_t)probe_cap * sizeof(wlcs::DotRec);
+    const size_t cnt_off = (list_bytes + 255) / 256 * 256;
+    uint8_t* scr = nullptr;
+    if ((e = hipMallocAsync((void**)&scr, cnt_off + 256, stream)) != hipSuccess) return fail(ctx, e);
+    wlcs::DotRec* probe = (wlcs::DotRec*)scr;
+    unsigned long long* probe_count = (unsigned long long*)(scr + cnt_off);
+    uint32_t* fallback = (uint32_t*)(scr + cnt_off + 64);
+    e = wlcs::launch_zero_u64(probe_count, stream);
+    if (e == hipSuccess) e = wlcs::launch_zero_u64((unsigned long long*)fallback, stream);
+    const int32_t tp = std::max(0, threshold - (int32_t)(h / 2));
+    // the probe strips, listed at the lowered threshold; each launch's tiles
+    // and the y codes it reads as for a strided plot of the pair
+    auto probe_launch = [&](int64_t prow, int64_t x0, int64_t stride) -> hipError_t {
+        wlcs::PlotArgs a = make_args(prow, cols, w, nullptr, 0, nullptr, 0, tp, nullptr, 0);
+        a.xstride = stride;
+        a.x0 = x0;
+        a.dots = probe;
+        a.dot_cap = probe_cap;
+        a.dot_count = probe_count;
+        choose_tiles(ctx, a, prow, cols, w);
+        int64_t xf_len, yg_len;
+        needed_lengths(Path::Seaweed, 1, cols, w, a, xf_len, yg_len);
+        if (yg_len > pair->yg_cap) return hipErrorInvalidValue;
+        a.xf = pair->xf + x0;
+        a.yg = pair->yg;
+        a.sigma = pair->sigma;
+        return wlcs::launch_seaweed(a, stream);
+    };
+    if (e == hipSuccess) e = probe_launch(rows_a, 0, h);
+    if (e == hipSuccess && extra) e = probe_launch(1, rows - 1, 1);
+    if (e == hipSuccess) {
+        wlcs::FilterArgs f;
+        f.xf = pair->xf;
+        f.yg = pair->yg;
+        f.probe = probe;
+        f.probe_cap = probe_cap;
+        f.probe_count = probe_count;
+        f.rows = rows;
+        f.w = w;
+        f.sigma = pair->sigma;
+        f.h = (int32_t)h;
+        f.threshold = threshold;
+        f.dots = (wlcs::DotRec*)dots;
+        f.dot_cap = dots ? dot_cap : 0;
+        f.dot_count = (unsigned long long*)dot_count;
+        f.fallback = fallback;
+        f.grid = 4 * ctx->cus;
+        e = wlcs::launch_candidates(f, stream);
+    }
+    if (e == hipSuccess) {
+        // every strip, listed at the threshold, if (and only if) the probe
+        // list overflowed; otherwise every workgroup returns at once
+        wlcs::PlotArgs a = make_args(rows, cols, w, nullptr, 0, nullptr, 0, threshold, nullptr, 0);
+        a.dots = (wlcs::DotRec*)dots;
+        a.dot_cap = dots ? dot_cap : 0;
+        a.dot_count = (unsigned long long*)dot_count;
+        a.gate = fallback;
+        choose_tiles(ctx, a, rows, cols, w);
+        int64_t xf_len, yg_len;
+        needed_lengths(Path::Seaweed, 1, cols, w, a, xf_len, yg_len);
+        if (yg_len > pair->yg_cap) e = hipErrorInvalidValue;
+        a.xf = pair->xf;
+        a.yg = pair->yg;
+        a.sigma = pair->sigma;
+        if (e == hipSuccess) e = wlcs::launch_seaweed(a, stream);
+    }
+    (void)hipFreeAsync(scr, stream);
+    if (e == hipSuccess) e = note_use(pair, stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    return WLCS_OK;
+}
+
 int wlcs_pair_plot_blcs(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, uint8_t* wlcs, int64_t ld,
                         uint64_t* bitmap, int64_t ld_words, int32_t threshold, uint16_t* indel, int64_t ld_indel,
                         uint32_t flags, void* stream) {
@@ -1098,7 +1196,7 @@ int wlcs_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, void* stream_
 }
 
 static_assert(wlcs::kNoAllocScratchBytes == WLCS_NOALLOC_SCRATCH_BYTES, "scratch size of the C ABI");
-static_assert(sizeof(wlcs::JobDesc) == 176, "table entry size stated in the C ABI");
+static_assert(sizeof(wlcs::JobDesc) == 184, "table entry size stated in the C ABI");
 
 int wlcs_batch_noalloc(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, void* stream_) {
     // the plan's vectors are kept per thread: once they have held a batch

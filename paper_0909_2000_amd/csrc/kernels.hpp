@@ -35,6 +35,8 @@ static_assert(sizeof(DotRec) == 12, "dot record layout");
 
 struct PlotArgs {
     int64_t xstride = 1;     // x codes between consecutive strips
+    int64_t x0 = 0;          // x-window of the first strip (dot records count from it)
+    const uint32_t* gate = nullptr;  // strided / sparse plots: if set, run only when *gate != 0
     int32_t ws = 1;          // store every ws-th combed window (1 or 2)
     int32_t bias = 0;        // subtracted from every stored value
     int64_t hy = 1;          // strided plots: output column c is the window c * hy
@@ -72,6 +74,7 @@ struct Geom {
     int32_t bias;      // subtracted from every stored value (0..127)
     int64_t hy;        // strided plots: output column c is the window c * hy
     int64_t dot_cap;   // dot records the sparse output holds
+    int64_t x0;        // x-window of strip 0 (the dot records' i is x0 + strip * xstride)
 };
 
 // Tile pairs along a row of cols windows: the first nbig pairs have tiles of
@@ -109,6 +112,7 @@ inline Geom geom_of(const PlotArgs& a) {
     g.bias = a.bias;
     g.hy = a.hy;
     g.dot_cap = a.dot_cap;
+    g.x0 = a.x0;
     const uintptr_t base = (uintptr_t)a.wlcs;
     g.wmode = (a.ld % 16 == 0 && base % 16 == 0) ? 2 : (a.ld % 4 == 0 && base % 4 == 0) ? 1 : 0;
     return g;
@@ -212,6 +216,26 @@ hipError_t launch_batch(int group, const JobDesc* jobs_dev, int32_t njobs, int64
                         unsigned long long* counter, int32_t grid, bool sparse, hipStream_t stream);
 // *ptrs[k] = 0 for k < n
 hipError_t launch_zero_each(unsigned long long* const* ptrs, int32_t n, hipStream_t stream);
+
+// The exact threshold filter for dot lists (filter.hip): from the probe
+// strips' listed entries (every h-th x-window and the last one, listed at
+// threshold - h / 2), the dots of every row.  If the probe list overflowed,
+// nothing is listed and *fallback is set.
+struct FilterArgs {
+    const uint16_t* xf;  // f-codes of x
+    const uint16_t* yg;  // g-codes of y
+    const DotRec* probe;
+    int64_t probe_cap;
+    const unsigned long long* probe_count;
+    int64_t rows;        // x-windows of the plot
+    int32_t w, sigma, h, threshold;
+    DotRec* dots;        // the caller's list (may be null while counting)
+    int64_t dot_cap;
+    unsigned long long* dot_count;
+    uint32_t* fallback;
+    int32_t grid;        // workgroups of 64 lanes (the kernel strides over the entries)
+};
+hipError_t launch_candidates(const FilterArgs& f, hipStream_t stream);
 
 // The fixed device scratch of the allocation-free batch (batch.hip): its
 // size, and its address on `device` (looked up once per device, with that

@@ -65,7 +65,11 @@ __global__ __launch_bounds__(64, DL ? min_waves_per_simd_dl(WC) : min_waves_per_
                                                                               uint16_t* __restrict__ indel,
                                                                               DotRec* __restrict__ dots,
                                                                               unsigned long long* __restrict__ dot_count,
-                                                                              Geom g) {
+                                                                              Geom g,
+                                                                              const uint32_t* __restrict__ gate) {
+    if constexpr (SP) {
+        if (gate && *gate == 0u) return;  // a launch kept only in case an earlier pass asks for it
+    }
     __shared__ uint32_t ring[ring_words(WC) * 64];
     __shared__ uint32_t stage[stage_dwords(WC, WS)];
     // pair-major order: the last tile pair of every strip block (usually
@@ -106,7 +110,10 @@ template <int WC, bool EXACT, bool SP>
 __global__ __launch_bounds__(128, min_waves_per_simd_split(WC)) void seaweed_kernel_rsplit(
     const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32, uint8_t* __restrict__ out,
     uint32_t* __restrict__ bm32, uint16_t* __restrict__ indel, DotRec* __restrict__ dots,
-    unsigned long long* __restrict__ dot_count, Geom g) {
+    unsigned long long* __restrict__ dot_count, Geom g, const uint32_t* __restrict__ gate) {
+    if constexpr (SP) {
+        if (gate && *gate == 0u) return;
+    }
     __shared__ uint32_t ring[ring_words(WC) * 64];
     __shared__ uint32_t stage[stage_dwords(WC, 1)];
     __shared__ uint32_t hand[kDlHandDwords];
@@ -132,20 +139,20 @@ void launch_ws(const PlotArgs& a, const Geom& g, uint32_t units, hipStream_t str
     if constexpr (WS == 1 && general_split(WC)) {
         if (a.w == WC)
             hipLaunchKernelGGL((seaweed_kernel_rsplit<WC, true, SP>), dim3(units), dim3(128), 0, stream, a.xf, yg32,
-                               a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+                               a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g, a.gate);
         else
             hipLaunchKernelGGL((seaweed_kernel_rsplit<WC, false, SP>), dim3(units), dim3(128), 0, stream, a.xf, yg32,
-                               a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+                               a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g, a.gate);
     } else {
         if constexpr (WC < 256) {  // windows are at most 255 long: none fills the 256-row class
             if (a.w == WC) {
                 hipLaunchKernelGGL((seaweed_kernel<WC, true, WS, SP>), dim3(units), dim3(64), 0, stream, a.xf, yg32,
-                                   a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+                                   a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g, a.gate);
                 return;
             }
         }
         hipLaunchKernelGGL((seaweed_kernel<WC, false, WS, SP>), dim3(units), dim3(64), 0, stream, a.xf, yg32,
-                           a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+                           a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g, a.gate);
     }
 }
 
@@ -163,7 +170,7 @@ hipError_t launch_dl(const PlotArgs& a, hipStream_t stream) {
                            (const uint32_t*)a.yg, a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
     else
         hipLaunchKernelGGL((seaweed_kernel<WC, false, 2, false, true>), dim3((uint32_t)units), dim3(64), 0, stream,
-                           a.xf, (const uint32_t*)a.yg, a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g);
+                           a.xf, (const uint32_t*)a.yg, a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g, a.gate);
     return hipGetLastError();
 }
 

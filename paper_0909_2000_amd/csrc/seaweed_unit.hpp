@@ -84,7 +84,7 @@ __device__ __forceinline__ void strided_flush(uint8_t* __restrict__ out, uint16_
         const unsigned long long k = k0 + __popcll(mask & ((1ull << lane) - 1ull));
         if (hit && k < (unsigned long long)g.dot_cap) {
             uint32_t* rec = (uint32_t*)(dots + k);
-            rec[0] = (uint32_t)((s0 + r) * g.xstride);
+            rec[0] = (uint32_t)(g.x0 + (s0 + r) * g.xstride);
             rec[1] = (uint32_t)(c * hy);
             rec[2] = v | ((uint32_t)(2 * w - 2 * (int)v) << 16);
         }

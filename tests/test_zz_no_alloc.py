@@ -97,7 +97,7 @@ def test_noalloc_batch_refuses_a_table_beyond_the_scratch():
     g = workloads.rng(4500)
     x, y = workloads.iid(g, 300, workloads.DNA), workloads.iid(g, 300, workloads.DNA)
     pair = ctx.pair(x, y)
-    n = 6200  # one table entry of 176 bytes each: more than the 1 MiB scratch
+    n = 6200  # one table entry of 184 bytes each: more than the 1 MiB scratch
     counts = torch.full((n,), -5, dtype=torch.int64, device="cuda")
     specs = [{"pair": pair, "w": 16, "threshold": 12, "dot_cap": 0, "want_plot": False,
               "count_out": counts[k:k + 1]} for k in range(n)]
