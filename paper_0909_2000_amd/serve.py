@@ -60,6 +60,30 @@ class JobState:
     results: dict | None = None
     batch_id: int = -1
     retries: int = 0           # reruns with a longer dot list
+    # "pending" until the job ends: "done", "rejected" (can never fit),
+    # "failed" (its launch failed; error holds why), "cancelled", "timed_out"
+    status: str = "pending"
+    error: str | None = None
+    cancel_requested: bool = False  # cancelled while its work was on the device
+    timed_out: bool = False         # its batch outran the server's batch timeout
+
+
+class LaunchError(RuntimeError):
+    """A batch was launched in part: `unlaunched` are the jobs that were not
+    (the executor keeps track of the rest), `cause` the original error."""
+
+    def __init__(self, unlaunched: list, cause: BaseException):
+        super().__init__(f"{len(unlaunched)} jobs not launched: {cause!r}")
+        self.unlaunched, self.cause = unlaunched, cause
+
+
+def is_out_of_memory(e: BaseException) -> bool:
+    """Whether a launch failed for lack of device memory (the library's
+    WLCS_ENOMEM, or the allocator's out-of-memory error)."""
+    e = getattr(e, "cause", e)
+    if getattr(e, "status", None) == -5:
+        return True
+    return type(e).__name__ in ("OutOfMemoryError", "MemoryError") or "out of memory" in str(e).lower()
 
 
 def windows(length: int, w: int) -> int:
@@ -172,8 +196,18 @@ class GpuExecutor:
             else:
                 subs.append([js])
         pending = []
-        for sub in subs:
-            pending.append((self._launch_sub(s, sub), sub))
+        try:
+            for sub in subs:
+                pending.append((self._launch_sub(s, sub), sub))
+        except Exception as e:  # e.g. no device memory left for a sub-batch's pair or outputs
+            launched = [js for _, sub in pending for js in sub]
+            if pending:
+                self.busy[k] = (pending, batch_id)  # what was enqueued completes as usual
+            done = {id(js) for js in launched}
+            for js in jobs:
+                if id(js) not in done:
+                    js.results = None
+            raise LaunchError([js for js in jobs if id(js) not in done], e) from e
         self.busy[k] = (pending, batch_id)
 
     def _launch_sub(self, s, jobs: list):
@@ -240,12 +274,17 @@ class GpuExecutor:
 
 class Server:
     def __init__(self, executor, budget_bytes: int, max_jobs: int = 256, max_batch: int = 64,
-                 keep_results: bool = True, on_done=None):
+                 keep_results: bool = True, on_done=None, batch_timeout_s: float | None = None):
         """on_done(request, results), if given, is called once per job when it
         completes (its sub-batch's event has fired), before the results are
-        released (keep_results=False) -- e.g. to check or copy them."""
+        released (keep_results=False) -- e.g. to check or copy them.
+        batch_timeout_s: a batch still running this long after its launch (on
+        the executor's clock) has its unfinished jobs marked timed out; their
+        memory is released only when the device work ends, and their results
+        are dropped."""
         self.ex = executor
         self.on_done = on_done
+        self.batch_timeout = batch_timeout_s
         self.budget = int(budget_bytes)
         self.max_jobs = max_jobs
         self.max_batch = max_batch
@@ -262,6 +301,11 @@ class Server:
         self.admit_log: list = []          # (time, jid) in admission order
         self.overlaps = 0                  # launches made while another batch ran
         self.retries = 0                   # jobs rerun because their dot list was too short
+        self.launch_retries = 0            # jobs put back in the queue after a launch ran out of memory
+        self.failed: list = []
+        self.cancelled: list = []
+        self.timed_out: list = []
+        self.launched_at: dict = {}        # batch id -> executor time of its launch
 
     # -- client side -----------------------------------------------------
     def submit(self, req: Request) -> int:
@@ -269,6 +313,7 @@ class Server:
         self.jobs[req.jid] = js
         if js.footprint > self.budget:
             js.done = self.ex.now()
+            js.status = "rejected"
             self.rejected.append(req.jid)  # can never fit
         else:
             self.waiting.append(js)
@@ -276,6 +321,31 @@ class Server:
 
     def poll(self, jid: int) -> bool:
         return self.jobs[jid].done >= 0
+
+    def status(self, jid: int) -> str:
+        return self.jobs[jid].status
+
+    def cancel(self, jid: int) -> bool:
+        """Cancel a job that has not ended: a waiting or admitted job leaves at
+        once (its memory is released); a job whose work is on the device keeps
+        its memory until that work ends, then its results are dropped.  False
+        if the job had already ended."""
+        js = self.jobs.get(jid)
+        if js is None or js.done >= 0 or js.cancel_requested:
+            return False
+        now = self.ex.now()
+        if js in self.waiting:
+            self.waiting.remove(js)
+        elif js in self.admitted:
+            self.admitted.remove(js)
+            self.in_use -= js.footprint
+            self.active -= 1
+        else:  # running: ends with its sub-batch
+            js.cancel_requested = True
+            return True
+        js.status, js.done, js.results = "cancelled", now, None
+        self.cancelled.append(jid)
+        return True
 
     def result(self, jid: int) -> dict | None:
         return self.jobs[jid].results
@@ -290,6 +360,7 @@ class Server:
             now = self.ex.now()
             if batch_done:
                 self.running.pop(bid)
+                self.launched_at.pop(bid, None)
             else:
                 done_ids = {id(js) for js in batch}
                 self.running[bid] = [js for js in self.running[bid] if id(js) not in done_ids]
@@ -298,6 +369,11 @@ class Server:
             for js, found in zip(batch, counts):
                 self.in_use -= js.footprint
                 self.active -= 1
+                if js.cancel_requested or js.timed_out:
+                    js.status = "cancelled" if js.cancel_requested else "timed_out"
+                    (self.cancelled if js.cancel_requested else self.timed_out).append(js.req.jid)
+                    js.done, js.results = now, None
+                    continue
                 if found is not None and js.req.dot_cap is not None and found > js.req.dot_cap:
                     # the list was too short: rerun the job with room for every dot
                     js.req = dataclasses.replace(js.req, dot_cap=found)
@@ -308,6 +384,7 @@ class Server:
                     retry.append(js)
                     continue
                 js.done = now
+                js.status = "done"
                 if self.on_done is not None:
                     self.on_done(js.req, js.results)
                 if not self.keep:
@@ -315,6 +392,7 @@ class Server:
             for js in reversed(retry):  # ahead of every job that arrived later
                 if js.footprint > self.budget:
                     js.done = now
+                    js.status = "rejected"
                     self.rejected.append(js.req.jid)
                 else:
                     self.waiting.appendleft(js)
@@ -344,10 +422,52 @@ class Server:
                 js.launched = now
                 js.batch_id = bid
             self.running[bid] = batch
-            self.ex.launch(bid, batch)
+            self.launched_at[bid] = now
+            try:
+                self.ex.launch(bid, batch)
+            except Exception as e:
+                self._launch_failed(bid, batch, e)
+
+    def _launch_failed(self, bid: int, batch: list, e: Exception):
+        """A launch failed for some (LaunchError) or all of the batch's jobs.
+        Jobs that were not launched give their memory back; if they failed for
+        lack of device memory while other batches hold some, they return to
+        the head of the queue (in order) to be admitted again once memory is
+        released; otherwise they fail with the error recorded."""
+        left = e.unlaunched if isinstance(e, LaunchError) else list(batch)
+        ids = {id(js) for js in left}
+        rest = [js for js in batch if id(js) not in ids]
+        if rest:
+            self.running[bid] = rest
+        else:
+            self.running.pop(bid, None)
+            self.launched_at.pop(bid, None)
+        for js in left:
+            self.in_use -= js.footprint
+            self.active -= 1
+            js.results, js.batch_id, js.launched = None, -1, -1.0
+        now = self.ex.now()
+        if is_out_of_memory(e) and self.running:
+            for js in reversed(left):
+                self.waiting.appendleft(js)
+            self.launch_retries += len(left)
+        else:
+            for js in left:
+                js.status, js.error, js.done = "failed", repr(getattr(e, "cause", e)), now
+                self.failed.append(js.req.jid)
+
+    def _check_timeouts(self):
+        if self.batch_timeout is None:
+            return
+        now = self.ex.now()
+        for bid, batch in self.running.items():
+            if now - self.launched_at.get(bid, now) > self.batch_timeout:
+                for js in batch:
+                    js.timed_out = True
 
     def step(self):
         self._reap()
+        self._check_timeouts()
         self._admit()
         self._launch()
 
@@ -374,22 +494,24 @@ class Server:
         return self.report()
 
     def report(self) -> dict:
-        lat = np.array([js.done - js.req.arrival for js in self.jobs.values()
-                        if js.done >= 0 and js.req.jid not in self.rejected])
+        lat = np.array([js.done - js.req.arrival for js in self.jobs.values() if js.status == "done"])
         first = min((js.req.arrival for js in self.jobs.values()), default=0.0)
         last = max((js.done for js in self.jobs.values()), default=0.0)
         cells = sum(float(js.req.x.size) * js.req.y.size * js.req.w for js in self.jobs.values()
-                    if js.req.jid not in self.rejected)
+                    if js.status == "done")
+        ndone = sum(1 for js in self.jobs.values() if js.status == "done")
         span = max(last - first, 1e-9)
         return {
             "jobs": len(self.jobs), "rejected": len(self.rejected),
             "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_s": float(lat.mean()) if lat.size else None,
-            "span_s": span, "jobs_per_s": (len(self.jobs) - len(self.rejected)) / span,
+            "span_s": span, "jobs_per_s": ndone / span,
             "window_cells_per_s": cells / span, "batches": self.next_batch,
             "overlapped_launches": self.overlaps, "peak_bytes": self.peak_use,
             "budget_bytes": self.budget, "dot_list_reruns": self.retries,
+            "failed": len(self.failed), "cancelled": len(self.cancelled), "timed_out": len(self.timed_out),
+            "launch_retries": self.launch_retries,
         }
 
 

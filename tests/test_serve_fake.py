@@ -271,3 +271,138 @@ def test_sub_batch_reruns_of_short_dot_lists(oracle_mod):
     for r in reqs:
         plot = oracle_mod.wlcs(r.x, r.y, r.w)
         assert srv.result(r.jid)["dot_count"] == plot.size
+
+
+# ---- failures forced from the host -------------------------------------
+
+class OutOfMemoryError(RuntimeError):
+    """What the device allocator raises when it has no memory left."""
+
+
+class OomExecutor(FakeExecutor):
+    """Fails a launch for lack of memory while `busy_limit` batches already
+    run (an allocator that cannot hold more), or always when the batch holds
+    one of the listed jobs."""
+
+    def __init__(self, oracle, busy_limit=None, bad_jobs=(), **kw):
+        super().__init__(oracle, **kw)
+        self.busy_limit, self.bad_jobs = busy_limit, set(bad_jobs)
+        self.failures = 0
+
+    def launch(self, batch_id, jobs):
+        running = sum(b is not None for b in self.busy)
+        if any(j.req.jid in self.bad_jobs for j in jobs) or \
+                (self.busy_limit is not None and running >= self.busy_limit):
+            self.failures += 1
+            raise OutOfMemoryError("out of memory (injected)")
+        super().launch(batch_id, jobs)
+
+
+def _check_results(srv, reqs, oracle_mod, statuses=("done",)):
+    for r in reqs:
+        js = srv.jobs[r.jid]
+        if js.status != "done":
+            continue
+        plot = oracle_mod.wlcs(r.x, r.y, r.w)
+        np.testing.assert_array_equal(srv.result(r.jid)["indel"], oracle_mod.indel(plot, r.w))
+
+
+def test_out_of_memory_launch_waits_for_running_batches(oracle_mod):
+    """A launch that finds no memory while other batches run puts its jobs
+    back at the head of the queue; they run once memory is released, and
+    every result equals the oracle's."""
+    reqs = _requests(30, 91, rate=4000.0)
+    ex = OomExecutor(oracle_mod, busy_limit=1, streams=3)
+    srv = serve.Server(ex, budget_bytes=1 << 30, max_jobs=64, max_batch=4)
+    rep = srv.run(reqs)
+    assert ex.failures > 0 and rep["launch_retries"] > 0
+    assert rep["failed"] == 0 and all(srv.status(r.jid) == "done" for r in reqs)
+    assert srv.in_use == 0 and srv.active == 0
+    _check_results(srv, reqs, oracle_mod)
+
+
+def test_out_of_memory_with_nothing_running_fails_the_jobs(oracle_mod):
+    """With no other batch to wait for, the jobs of a launch that finds no
+    memory fail with the error recorded; the others are not affected and the
+    budget is given back."""
+    reqs = _requests(12, 92, rate=5.0)  # sparse arrivals: one batch at a time
+    ex = OomExecutor(oracle_mod, bad_jobs={3})
+    srv = serve.Server(ex, budget_bytes=1 << 30, max_jobs=64, max_batch=4)
+    rep = srv.run(reqs)
+    failed = [r.jid for r in reqs if srv.status(r.jid) == "failed"]
+    assert failed and rep["failed"] == len(failed)
+    assert all("out of memory" in srv.jobs[j].error for j in failed)
+    assert all(srv.status(r.jid) in ("done", "failed") for r in reqs)
+    assert srv.in_use == 0 and srv.active == 0
+    _check_results(srv, reqs, oracle_mod)
+
+
+class PartialExecutor(FakeExecutor):
+    """Launches the first job of batch 1 and then runs out of memory."""
+
+    def launch(self, batch_id, jobs):
+        if batch_id == 1 and len(jobs) > 1:
+            super().launch(batch_id, jobs[:1])
+            raise serve.LaunchError(list(jobs[1:]), OutOfMemoryError("out of memory (injected)"))
+        super().launch(batch_id, jobs)
+
+
+def test_partly_launched_batch(oracle_mod):
+    """A batch launched in part: the launched job completes with it, the rest
+    return to the queue (another batch holds memory) and complete later."""
+    reqs = _requests(24, 93, rate=1e9)
+    for r in reqs:
+        r.arrival = 0.0  # all at once: full batches of 4
+    ex = PartialExecutor(oracle_mod, streams=3)
+    srv = serve.Server(ex, budget_bytes=1 << 30, max_jobs=64, max_batch=4)
+    rep = srv.run(reqs)
+    assert rep["launch_retries"] == 3 and rep["failed"] == 0
+    assert all(srv.status(r.jid) == "done" for r in reqs)
+    assert srv.in_use == 0 and srv.active == 0
+    _check_results(srv, reqs, oracle_mod)
+
+
+def test_cancel_waiting_admitted_and_running_jobs(oracle_mod):
+    reqs = _requests(10, 94, rate=1e9)  # all arrive at once
+    ex = FakeExecutor(oracle_mod, streams=1)
+    srv = serve.Server(ex, budget_bytes=1 << 30, max_jobs=64, max_batch=3)
+    for r in reqs:
+        srv.submit(r)
+    srv.step()  # admits everything, launches the first batch of 3
+    running = [js.req.jid for js in srv.running[0]]
+    admitted = [js.req.jid for js in srv.admitted]
+    assert len(running) == 3 and admitted
+    assert srv.cancel(running[0]) and srv.cancel(admitted[0])
+    assert not srv.cancel(running[0])  # already asked
+    use_before = srv.in_use
+    assert srv.status(admitted[0]) == "cancelled" and srv.in_use < use_before + 1
+    while srv.busy():
+        srv.step()
+        ex.advance(None)
+    assert srv.status(running[0]) == "cancelled" and srv.result(running[0]) is None
+    assert srv.status(admitted[0]) == "cancelled"
+    rep = srv.report()
+    assert rep["cancelled"] == 2
+    others = [r for r in reqs if r.jid not in (running[0], admitted[0])]
+    assert all(srv.status(r.jid) == "done" for r in others)
+    assert not srv.cancel(others[0].jid)  # already done
+    assert srv.in_use == 0 and srv.active == 0
+    _check_results(srv, others, oracle_mod)
+
+
+def test_batch_timeout_on_the_virtual_clock(oracle_mod):
+    """A batch that outruns the timeout has its jobs marked timed out (their
+    results dropped, their memory released when the work ends); batches that
+    finish in time are not affected."""
+    reqs = _requests(16, 95, rate=20.0, lo=20, hi=60)
+    big = reqs[5]
+    big.x = np.concatenate([big.x] * 40)  # about 40x the work of the others
+    ex = FakeExecutor(oracle_mod, streams=2, rate=2e6)
+    srv = serve.Server(ex, budget_bytes=1 << 30, max_jobs=64, max_batch=1, batch_timeout_s=0.05)
+    rep = srv.run(reqs)
+    assert srv.status(big.jid) == "timed_out" and srv.result(big.jid) is None
+    assert rep["timed_out"] >= 1
+    assert all(srv.status(r.jid) in ("done", "timed_out") for r in reqs)
+    assert sum(srv.status(r.jid) == "done" for r in reqs) >= 14
+    assert srv.in_use == 0 and srv.active == 0
+    _check_results(srv, reqs, oracle_mod)
