@@ -18,7 +18,8 @@
 // the recurrence of blcs.hip): the candidates of one probe entry share the
 // y-window, so each lane builds that window's letter masks once (in LDS, one
 // column per lane) and runs the w-step recurrence over the letters of each
-// candidate x-window.
+// candidate x-window.  Both windows' codes are read 32 at a time into
+// registers with 17 aligned 32-bit loads, so the steps wait on LDS only.
 //
 // If the probe entries exceed the probe list, the kernel lists nothing and
 // raises a flag instead; a gated launch of the plain dot list over every strip
@@ -41,6 +42,25 @@ __device__ __forceinline__ void bl_step(uint32_t (&v)[NW], const uint32_t* m) {
         carry = co;
         borrow = bo;
         v[k] = sum | dif;
+    }
+}
+
+// Codes per register chunk of a window (two 16-bit codes per register).
+constexpr int kChunk = 32;
+
+// kChunk 16-bit codes starting at element pos of a16, two per register (code
+// 2k in the low half of c[k]), read as kChunk / 2 + 1 aligned 32-bit loads:
+// an odd start is realigned per lane with v_alignbit.  Reads elements up to
+// pos + kChunk + 1.
+__device__ __forceinline__ void load_chunk(const uint16_t* __restrict__ a16, int64_t pos, uint32_t (&c)[kChunk / 2]) {
+    const uint32_t* wp = (const uint32_t*)(a16 + (pos & ~(int64_t)1));
+    const uint32_t sh = (uint32_t)(pos & 1) * 16u;
+    uint32_t prev = wp[0];
+#pragma unroll
+    for (int k = 0; k < kChunk / 2; ++k) {
+        const uint32_t next = wp[k + 1];
+        c[k] = __builtin_amdgcn_alignbit(next, prev, sh);
+        prev = next;
     }
 }
 
@@ -83,11 +103,17 @@ __global__ __launch_bounds__(64) void candidates_kernel(const uint16_t* __restri
         for (int c = 0; c < sigma; ++c)
 #pragma unroll
             for (int k = 0; k < NW; ++k) masks[(c * NW + k) * 64 + lane] = 0u;
-        for (int q = 0; q < w; ++q) {
-            const int64_t t = j + q;
-            const uint32_t g = (yg32[t >> 1] >> ((uint32_t)(t & 1) * 16u)) & 0xFFFFu;
-            const uint32_t c = (64u - (g >> kCodeShift)) & 63u;
-            masks[(c * NW + (q >> 5)) * 64 + lane] |= 1u << (q & 31);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {  // one chunk of 32 letters per mask word
+            uint32_t yc[kChunk / 2];
+            load_chunk((const uint16_t*)yg32, j + kChunk * k, yc);
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) {
+                if (kChunk * k + q >= w) break;  // uniform
+                const uint32_t g = (yc[q >> 1] >> ((q & 1) * 16)) & 0xFFFFu;
+                const uint32_t c = (64u - (g >> kCodeShift)) & 63u;
+                masks[(c * NW + k) * 64 + lane] |= 1u << q;
+            }
         }
         for (int d = -H; d <= H; ++d) {
             const int64_t i = p + d;
@@ -99,13 +125,18 @@ __global__ __launch_bounds__(64) void candidates_kernel(const uint16_t* __restri
             uint32_t vec[NW];
 #pragma unroll
             for (int k = 0; k < NW; ++k) vec[k] = 0xFFFFFFFFu;
-            const uint16_t* xp = xf + i;
-            for (int a = 0; a < w; ++a) {
-                const uint32_t c = (uint32_t)xp[a] >> kCodeShift;
-                uint32_t m[NW];
+            for (int a0 = 0; a0 < w; a0 += kChunk) {  // the x-window's letters, a chunk at a time
+                uint32_t xc[kChunk / 2];
+                load_chunk(xf, i + a0, xc);
 #pragma unroll
-                for (int k = 0; k < NW; ++k) m[k] = masks[(c * NW + k) * 64 + lane];
-                bl_step<NW>(vec, m);
+                for (int a = 0; a < kChunk; ++a) {
+                    if (a0 + a >= w) break;  // uniform
+                    const uint32_t c = ((xc[a >> 1] >> ((a & 1) * 16)) & 0xFFFFu) >> kCodeShift;
+                    uint32_t m[NW];
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) m[k] = masks[(c * NW + k) * 64 + lane];
+                    bl_step<NW>(vec, m);
+                }
             }
             uint32_t ones = 0;
 #pragma unroll
