@@ -77,12 +77,10 @@ def measured_traffic(workload: str, cells: float = 0.0):
     """HBM bytes per launch of the timed kernel, from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs, each scaled by what the same counter read for
     a plain 1 GiB device copy; None when the kernel sources changed since.
-    The detail also carries the VALU instruction counters of the same kernel:
-    wave instructions x 64 lanes per cell (5 packed instructions per two cells
-    is 2.5), and the share of SIMD cycles that issued a VALU instruction (a
-    wave64 instruction holds a 16-lane SIMD for 4 cycles; GRBM_GUI_ACTIVE is
-    the busy cycles summed over the 8 XCDs, each with 32 CUs x 4 SIMDs; the
-    4-cycle rule is approximate, so a saturated VALU can read slightly above 1)."""
+    The detail also carries the VALU counters of the same kernel: wave
+    instructions x 64 lanes per cell (5 instructions per two cells is 2.5),
+    and, from the counter run's own launch time and GRBM_COUNT, the shader
+    clock and the SIMD cycles per wave64 VALU instruction."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"seaweed_counters_{workload.replace('-planted', '')}.json")
     if not os.path.exists(path):
@@ -105,11 +103,24 @@ def measured_traffic(workload: str, cells: float = 0.0):
     vc = d.get("valu_counters_per_dispatch")
     if vc and cells:
         mean = lambda k: sum(vc[k]) / len(vc[k])
-        insts, gui = mean("SQ_INSTS_VALU"), mean("GRBM_GUI_ACTIVE")
+        insts = mean("SQ_INSTS_VALU")
         detail["valu"] = {"lane_instructions_per_cell": insts * 64 / cells,
-                          "issue_share": insts * 4 / (gui * 32 * 4),
-                          "salu_per_valu": mean("SQ_INSTS_SALU") / insts,
-                          "lds_per_valu": mean("SQ_INSTS_LDS") / insts}
+                          "salu_per_valu": mean("SQ_INSTS_SALU") / insts}
+        ns = d.get("valu_run_kernel_ns")
+        if ns and "GRBM_COUNT" in vc:
+            # the counter run's last launch (the first runs while the clock
+            # ramps up); GRBM_COUNT is summed over the 8 XCDs, each XCD's
+            # count runs at the shader clock
+            cyc = vc["GRBM_COUNT"][-1] / 8
+            detail["valu"].update({
+                "counter_run_launch_ms": ns[-1] / 1e6,
+                "clock_ghz": cyc / ns[-1],
+                # SIMD cycles per wave64 VALU instruction, every other cycle
+                # included (1,024 SIMDs)
+                "simd_cycles_per_valu_instruction": cyc / (vc["SQ_INSTS_VALU"][-1] / 1024),
+                "cu_busy_share": vc["SQ_BUSY_CU_CYCLES"][-1] / 256 / cyc,
+                # the counter's accounting: one quad-cycle per wave64 instruction
+                "valu_quad_cycles_per_instruction": vc["SQ_ACTIVE_INST_VALU"][-1] / vc["SQ_INSTS_VALU"][-1]})
     return detail["read_bytes"] + detail["write_bytes"], detail
 
 
