@@ -147,28 +147,54 @@ def test_graph_replays(ctx, oracle_mod):
     graph.close()
 
 
+def _batch_digests():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_plots.txt")
+    out = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, w, rows, cols, d = line.split()
+            out[int(k)] = (int(w), int(rows), int(cols), d)
+    return out
+
+
 def test_batch_configuration_full_size(ctx, oracle_mod):
     """256 DNA pairs, m, n uniform in [1000, 20000], w from {16, 32, 64, 128},
-    in one persistent launch: every plot's sampled row and entries against the
-    oracle, a few plots against their single-plot run."""
+    in one persistent launch: every plot whole against the oracle (the digests
+    of tests/golden/batch_plots.txt, written by
+    tests/golden/make_batch_digests.py from the oracle alone) and against its
+    single-plot run on the device, plus a sampled row and entries against the
+    oracle directly."""
+    import hashlib
     import torch
     pairs = workloads.batch_config()
+    gold = _batch_digests()
+    assert len(gold) == len(pairs) == 256
     _say(f"batch configuration: {len(pairs)} pairs")
     specs = [{"pair": ctx.pair(p.x, p.y), "w": p.w} for p in pairs]
     res = ctx.batch(specs)
     torch.cuda.synchronize()
     g = workloads.rng(16)
+    bad = []
     for k, (p, r) in enumerate(zip(pairs, res)):
         W = r["wlcs"]
         rows, cols = W.shape
         assert (rows, cols) == (p.m - p.w, p.n - p.w)
+        assert gold[k][:3] == (p.w, rows, cols), k
+        if hashlib.blake2b(_np(W).tobytes(), digest_size=8).hexdigest() != gold[k][3]:
+            bad.append(("oracle", k))
+        if not torch.equal(W, specs[k]["pair"].plot(p.w)["wlcs"]):
+            bad.append(("single plot", k))
         row = int(g.integers(0, rows))
         np.testing.assert_array_equal(_np(W[row:row + 1]), oracle_mod.wlcs_rows(p.x, p.y, p.w, [row]))
         ii, jj = g.integers(0, rows, 16), g.integers(0, cols, 16)
         got = _np(W[torch.as_tensor(ii, device="cuda"), torch.as_tensor(jj, device="cuda")])
         np.testing.assert_array_equal(got, oracle_mod.wlcs_at(p.x, p.y, p.w, ii, jj))
-    for k in (0, 17, 101, 255):
-        assert torch.equal(res[k]["wlcs"], specs[k]["pair"].plot(specs[k]["w"])["wlcs"])
+        r["wlcs"] = None  # release the pair's plot as the check goes
+        del W
+    assert not bad, bad[:20]
 
 
 def _sorted_dots(res):
