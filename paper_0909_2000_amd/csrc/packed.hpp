@@ -203,10 +203,18 @@ __device__ __forceinline__ uint32_t dp_cell(uint32_t up, uint32_t left, uint32_t
 
 // Per half: 1 if p < w (unsigned), else 0 -- min(sat(w - p), 1).  Written as
 // two packed instructions (the compiler would otherwise split the halves).
+// w2 is wave-uniform and is read from a scalar register.
 __device__ __forceinline__ uint32_t pk_below(uint32_t w2, uint32_t p2, uint32_t one2) {
     uint32_t v;
-    asm("v_pk_sub_u16 %0, %1, %2 clamp\n\tv_pk_min_u16 %0, %0, %3" : "=&v"(v) : "v"(w2), "v"(p2), "v"(one2));
+    asm("v_pk_sub_u16 %0, %1, %2 clamp\n\tv_pk_min_u16 %0, %0, %3"
+        : "=&v"(v)
+        : "s"(__builtin_amdgcn_readfirstlane(w2)), "v"(p2), "v"(one2));
     return v;
+}
+
+// Per half: a >> 1.
+__device__ __forceinline__ uint32_t pk_shr1(uint32_t a) {
+    return as_u(as_v(a) >> (u16x2){(unsigned short)1, (unsigned short)1});
 }
 
 // Per half: val << (amount & 15), one v_pk_lshlrev_b16.

@@ -26,19 +26,14 @@ __device__ __forceinline__ uint32_t sub_bytes(uint32_t x, uint32_t b4) {
 // the word being cleared apart from the newest marks.
 constexpr int ring_words(int wc) { return wc <= 128 ? 16 : 32; }
 constexpr int stage_dwords(int wc, int ws = 1) { return 2 * 64 * stage_pitch(wc, ws); }
-// Stores of a strided or sparse plot for one flushed block: window j0 + b of
-// strip s0 + r sits in byte b of row r of the staged block (stride pitch
-// dwords).  Output column c holds the window c * hy; the lanes of the wave
-// cover the block's output columns of one strip at a time, so the stores of a
-// strip are contiguous.  Dots (windows with WLCS >= threshold) are appended to
-// the list in two passes over the block: the first counts them (ballots), one
-// vector atomic reserves a run of slots for the whole block, the second
-// writes them (skipped once the list is full).  The counter keeps counting
-// past dot_cap; records beyond it are not written.
-__device__ __forceinline__ void strided_flush(uint8_t* __restrict__ out, uint16_t* __restrict__ indel,
-                                              DotRec* __restrict__ dots, unsigned long long* __restrict__ dot_count,
-                                              const Geom& g, int64_t s0, int64_t j0, int nk, int w,
-                                              const uint8_t* staged, int pitch) {
+// Stores of a strided plot for one flushed block: window j0 + b of strip
+// s0 + r sits in byte b of row r of the staged block (stride pitch dwords).
+// Output column c holds the window c * hy; the lanes of the wave cover the
+// block's output columns of one strip at a time, so the stores of a strip are
+// contiguous.
+__device__ __forceinline__ void strided_stores(uint8_t* __restrict__ out, uint16_t* __restrict__ indel,
+                                               const Geom& g, int64_t s0, int64_t j0, int nk, int w,
+                                               const uint8_t* staged, int pitch) {
     if (nk <= 0) return;
     const int lane = threadIdx.x & 63;
     const int64_t hy = g.hy;
@@ -50,45 +45,101 @@ __device__ __forceinline__ void strided_flush(uint8_t* __restrict__ out, uint16_
     const int b = act ? (int)(c * hy - j0) : 0;
     const int64_t rest = g.rows - s0;
     const int nrows = rest < 64 ? (int)rest : 64;
-    if (g.hy > 1 && (out || indel)) {
-#pragma unroll 1
-        for (int r = 0; r < nrows; ++r) {
-            const int64_t s = s0 + r;
-            const uint32_t v = staged[r * pitch * 4 + b];
-            if (act) {
-                if (out) out[s * g.ld + c] = (uint8_t)v;
-                if (indel) indel[s * g.ld_indel + c] = (uint16_t)(2 * w - 2 * (int)v);
-            }
-        }
-    }
-    if (!dot_count) return;
-    uint32_t total = 0;  // wave-uniform
 #pragma unroll 1
     for (int r = 0; r < nrows; ++r) {
+        const int64_t s = s0 + r;
         const uint32_t v = staged[r * pitch * 4 + b];
-        total += (uint32_t)__popcll(__ballot(act && (int)v >= g.threshold));
-    }
-    if (total == 0) return;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(dot_count, (unsigned long long)total);
-    const unsigned long long start =
-        ((unsigned long long)__builtin_amdgcn_readlane((uint32_t)(base >> 32), 0) << 32) |
-        __builtin_amdgcn_readlane((uint32_t)base, 0);
-    if (!dots || start >= (unsigned long long)g.dot_cap) return;  // uniform
-    unsigned long long k0 = start;  // wave-uniform running slot
-#pragma unroll 1
-    for (int r = 0; r < nrows && k0 < (unsigned long long)g.dot_cap; ++r) {
-        const uint32_t v = staged[r * pitch * 4 + b];
-        const bool hit = act && (int)v >= g.threshold;
-        const uint64_t mask = __ballot(hit);
-        const unsigned long long k = k0 + __popcll(mask & ((1ull << lane) - 1ull));
-        if (hit && k < (unsigned long long)g.dot_cap) {
-            uint32_t* rec = (uint32_t*)(dots + k);
-            rec[0] = (uint32_t)(g.x0 + (s0 + r) * g.xstride);
-            rec[1] = (uint32_t)(c * hy);
-            rec[2] = v | ((uint32_t)(2 * w - 2 * (int)v) << 16);
+        if (act) {
+            if (out) out[s * g.ld + c] = (uint8_t)v;
+            if (indel) indel[s * g.ld_indel + c] = (uint16_t)(2 * w - 2 * (int)v);
         }
-        k0 += (unsigned long long)__popcll(mask);
+    }
+}
+
+// Flags of the four staged windows of dword d (byte i = window 4q + i): bit
+// 8i + 7 is set iff the window's value is at least the threshold.  SMALL
+// (every value below 128, windows of at most 127 letters): per byte,
+// (v | 0x80) - T keeps bit 7 iff v >= T, with no borrow between the bytes for
+// T <= 128 (t4 = T in every byte).  Otherwise the bytes are split into the
+// even and the odd pair of 16-bit lanes, where (v | 0x8000) - T keeps bit 15
+// iff v >= T for any v <= 255 and T <= 256 (t2 = T in both halves).
+template <bool SMALL>
+__device__ __forceinline__ uint32_t dot_flags(uint32_t d, uint32_t t4, uint32_t t2) {
+    if (SMALL) return ((d | 0x80808080u) - t4) & 0x80808080u;
+    const uint32_t e = d & 0x00FF00FFu, o = (d >> 8) & 0x00FF00FFu;
+    const uint32_t fe = ((e | 0x80008000u) - t2) & 0x80008000u;
+    const uint32_t fo = ((o | 0x80008000u) - t2) & 0x80008000u;
+    return (fe >> 8) | fo;
+}
+
+// The dots (windows with WLCS >= threshold, at output positions) of one
+// flushed block, listed by the lane that owns each strip: lane r flags the
+// staged windows of strip s0 + r (a dword per four windows, `row`) and counts
+// them; a scan of the counts over the wave gives each lane its offset, one
+// atomic add reserves a run of slots for the whole block (so that a dense list
+// does not serialise on the counter), and each lane writes its records in
+// window order, the strips one after another.  The block's output positions
+// (bit b: window j0 + b is an output; every window for hy = 1, every hy-th
+// for hy > 1) are the same for every lane.  The counter keeps counting past
+// dot_cap; records beyond it are not written.
+template <int FL, bool SMALL>
+__device__ __forceinline__ void list_dots(DotRec* __restrict__ dots, unsigned long long* __restrict__ dot_count,
+                                          const Geom& g, int64_t s0, int64_t j0, int nk, int w,
+                                          const uint32_t* row) {
+    static_assert(FL <= 64, "one 64-bit mask of output positions per block");
+    if (nk <= 0 || g.threshold > w) return;  // uniform
+    const int lane = threadIdx.x & 63;
+    uint64_t obits;  // wave-uniform
+    if (g.hy == 1) {
+        obits = nk >= 64 ? ~0ull : (1ull << nk) - 1ull;
+    } else {
+        obits = 0;
+        const int64_t c_lo = (j0 + g.hy - 1) / g.hy;
+        for (int64_t b = c_lo * g.hy - j0; b < nk; b += g.hy) obits |= 1ull << b;
+    }
+    const uint32_t t = (uint32_t)(g.threshold > 0 ? g.threshold : 0);
+    const uint32_t t4 = t * 0x01010101u, t2 = t * 0x00010001u;
+    // byte-form output mask of dword q: bit 8i + 7 for each output window 4q + i
+    auto omask = [&](int q) -> uint32_t {
+        const uint32_t nib = (uint32_t)(obits >> (4 * q)) & 0xFu;
+        return ((nib * 0x00204081u) & 0x01010101u) << 7;
+    };
+    uint32_t cnt = 0;
+    if (s0 + lane < g.rows) {  // a lane past the last strip holds a copy
+#pragma unroll
+        for (int q = 0; q < FL / 4; ++q) cnt += (uint32_t)__popc(dot_flags<SMALL>(row[q], t4, t2) & omask(q));
+    }
+    uint32_t incl = cnt;  // inclusive scan of the counts over the lanes
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, d);
+        if (lane >= d) incl += y;
+    }
+    const uint32_t total = (uint32_t)__shfl((int)incl, 63);  // wave-uniform
+    if (total == 0) return;
+    unsigned long long base0 = 0;
+    if (lane == 0) base0 = atomicAdd(dot_count, (unsigned long long)total);
+    const unsigned long long base =
+        (((unsigned long long)__builtin_amdgcn_readlane((uint32_t)(base0 >> 32), 0) << 32) |
+         __builtin_amdgcn_readlane((uint32_t)base0, 0)) + (incl - cnt);
+    const unsigned long long cap = (unsigned long long)g.dot_cap;
+    if (!dots || cnt == 0 || base >= cap) return;
+    unsigned long long k = base;
+    const uint32_t ii = (uint32_t)(g.x0 + (s0 + lane) * g.xstride);
+#pragma unroll 1
+    for (int q = 0; q < FL / 4 && k < cap; ++q) {
+        const uint32_t d = row[q];
+        uint32_t m = dot_flags<SMALL>(d, t4, t2) & omask(q);
+        while (m != 0 && k < cap) {
+            const int bit = __builtin_ctz(m);  // 8i + 7
+            m &= m - 1u;
+            const uint32_t v = (d >> (bit - 7)) & 0xFFu;
+            uint32_t* rec = (uint32_t*)(dots + k);
+            rec[0] = ii;
+            rec[1] = (uint32_t)(j0 + 4 * q + (bit >> 3));
+            rec[2] = v | ((uint32_t)(2 * w - 2 * (int)v) << 16);
+            ++k;
+        }
     }
 }
 
@@ -186,7 +237,7 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     uint32_t h[HN];
 #pragma unroll
     for (int k = 0; k < HN; ++k) h[k] = 0;
-    if constexpr (!UPPER) {
+    if constexpr (!UPPER && (DL || WC > 32)) {  // the LDS ring of pending marks (longer windows)
 #pragma unroll
         for (int q = 0; q < RW; ++q) ring[q * 64 + lane] = 0;
     }
@@ -216,29 +267,52 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     const uint32_t one2 = 0x00010001u;
     uint32_t ynext = DL ? 0u : yload(0);
 
+    // Windows of at most 32 letters keep the pending marks in registers
+    // instead of the LDS ring: bit q of a tile's mask marks the start column
+    // (l - w + 1) + q of the current window l - w + 1.  Moving to the next
+    // column takes bit 0 out (that start column leaves the window: the mark
+    // consumed) and shifts the rest down by one.  Up to 16 letters the masks
+    // of both tiles share one register, a 16-bit half each; up to 32 each
+    // tile has a register of its own.
+    constexpr bool RMASK = !DL && WC <= 32;
+    uint32_t m2 = 0, mA = 0, mB = 0;
+
     // The sliding count after column l (tile-relative), from the packed label
     // t leaving its bottom; returns w - count for the window starting at
     // l - w + 1.
     auto count = [&](int l, uint32_t t) -> uint32_t {
-        // consume the mark of start column l - w (prefetched after the
+        // consume the mark of start column l - w (ring: prefetched after the
         // previous column's marks were set)
         uint32_t f2 = 0;
         const int pc = l - w;
-        if (pc >= 0) {
+        if constexpr (RMASK && WC <= 16) {
+            f2 = m2 & one2;
+        } else if constexpr (RMASK) {
+            f2 = __builtin_amdgcn_perm(mB, mA, 0x0c040c00u) & one2;  // bit 0 of each mask
+        } else if (pc >= 0) {
             f2 = (ring_pf >> (pc & 15)) & 0x00010001u;
             if ((pc & 15) == 15) ring_lane[((pc >> 4) & (RW - 1)) * 64] = 0;
         }
         // p = start - (l - w + 1) lies in [0, w) iff the exit's span is below w
         const uint32_t p2 = pk_sub(t, pk_rep(l - org + 2 - w));
         const uint32_t v2 = pk_below(w2, p2, one2);
-        const uint32_t pos2 = pk_add(p2, pk_rep(l - w + 1));
-        const uint32_t bit2 = pk_lshl(pos2, v2);
-        // ring word of each mark: bits 4.. of its start column
-        const uint32_t wlo = bfe<4, RB>(pos2), whi = bfe<20, RB>(pos2);
-        atomicOr(&ring_lane[wlo * 64], bit2 & 0xFFFFu);
-        atomicOr(&ring_lane[whi * 64], bit2 & 0xFFFF0000u);
+        if constexpr (RMASK && WC <= 16) {
+            m2 = pk_shr1(m2) | pk_lshl(p2, v2);  // p < w <= 16 wherever v = 1
+        } else if constexpr (RMASK) {
+            mA = (mA >> 1) | ((v2 & 0xFFFFu) << (p2 & 31u));  // p < w <= 32 wherever v = 1
+            mB = (mB >> 1) | ((v2 >> 16) << ((p2 >> 16) & 31u));
+        } else {
+            const uint32_t pos2 = pk_add(p2, pk_rep(l - w + 1));
+            const uint32_t bit2 = pk_lshl(pos2, v2);
+            // ring word of each mark: bits 4.. of its start column
+            const uint32_t wlo = bfe<4, RB>(pos2), whi = bfe<20, RB>(pos2);
+            atomicOr(&ring_lane[wlo * 64], bit2 & 0xFFFFu);
+            atomicOr(&ring_lane[whi * 64], bit2 & 0xFFFF0000u);
+        }
         rem2 = pk_add(pk_sub(rem2, v2), f2);
-        if (pc + 1 >= 0) ring_pf = ring_lane[(((pc + 1) >> 4) & (RW - 1)) * 64];
+        if constexpr (!RMASK) {
+            if (pc + 1 >= 0) ring_pf = ring_lane[(((pc + 1) >> 4) & (RW - 1)) * 64];
+        }
         return rem2;
     };
 
@@ -459,8 +533,10 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
             // with WS = 2 only the even ones are outputs
             const int nk = (int)(te - j0 < FL ? (te - j0 > 0 ? te - j0 : 0) : FL);
             if (SP) {
-                if (g.hy > 1 || dot_count) strided_flush(out, indel, dots, dot_count, g, s0, j0, nk, w,
-                                                         (const uint8_t*)(stage + half * 64 * PITCH), PITCH);
+                const uint32_t* sblock = stage + half * 64 * PITCH;
+                if (g.hy > 1 && (out || indel))
+                    strided_stores(out, indel, g, s0, j0, nk, w, (const uint8_t*)sblock, PITCH);
+                if (dot_count) list_dots<FL, (WC <= 64)>(dots, dot_count, g, s0, j0, nk, w, sblock + lane * PITCH);
                 if (g.hy > 1) continue;  // uniform
             }
             const int nvalid = (nk + WS - 1) / WS;
