@@ -88,6 +88,21 @@ int wlcs_ctx_last_hip_error(const wlcs_ctx *ctx);
  * operations per second. */
 int wlcs_measure_valu_peak(wlcs_ctx *ctx, int32_t iters, double *ops_per_s);
 
+/* Measurement helper, not part of the method: wave64 VALU instructions issued
+ * per second per SIMD (four per CU) with waves_per_simd (1..4) waves resident
+ * on every SIMD, for one kind of instruction stream: 0 packed 16-bit
+ * (v_pk_max_u16) and 1 plain 32-bit (v_xor_b32), each on eight independent
+ * accumulators; 2 the seaweed cell down a column of eight rows (five
+ * instructions per cell, three packed and two plain, each cell waiting for
+ * the label of the cell above, as in the plot kernels).  One workgroup of
+ * 256 x waves_per_simd threads per CU runs iters (1..10^6) rounds of 16
+ * (kinds 0, 1) or 40 (kind 2) instructions per wave, once to warm up (at most
+ * 1,000 rounds) and once timed with HIP events.  Synchronous, like
+ * wlcs_measure_valu_peak.  WLCS_EINVAL for a null context or pointer or an
+ * argument out of range (nothing runs). */
+int wlcs_measure_valu_issue(wlcs_ctx *ctx, int32_t kind, int32_t waves_per_simd, int32_t iters,
+                            double *instr_per_s);
+
 /* Human-readable text for a status code (static storage). */
 const char *wlcs_status_str(int status);
 

@@ -20,6 +20,8 @@
 namespace wlcs {
 // probe.hip: blocks x 256 threads of independent packed 16-bit VALU chains
 hipError_t launch_valu_peak(uint32_t* out, int32_t blocks, int32_t iters, hipStream_t stream);
+hipError_t launch_valu_issue(uint32_t* out, int32_t kind, int32_t blocks, int32_t k, int32_t iters,
+                             hipStream_t stream);
 }  // namespace wlcs
 
 using wlcs_rt::kMaxSlots;
@@ -862,6 +864,42 @@ int wlcs_measure_valu_peak(wlcs_ctx* ctx, int32_t iters, double* ops_per_s) {
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
     if (e == hipSuccess && ms > 0.0f)
         *ops_per_s = (double)blocks * 256.0 * (double)iters * 64.0 * 2.0 / (ms * 1e-3);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (stream) (void)hipStreamDestroy(stream);
+    if (out) (void)hipFree(out);
+    if (e != hipSuccess) return fail(ctx, e);
+    return ms > 0.0f ? WLCS_OK : WLCS_EHIP;
+}
+
+int wlcs_measure_valu_issue(wlcs_ctx* ctx, int32_t kind, int32_t waves_per_simd, int32_t iters,
+                            double* instr_per_s) {
+    if (!ctx || !instr_per_s || kind < 0 || kind > 2 || waves_per_simd < 1 || waves_per_simd > 4 || iters < 1 ||
+        iters > 1000000)
+        return WLCS_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, hipErrorInvalidDevice);
+    const int32_t blocks = ctx->cus;  // one workgroup of 256 k threads per CU: k waves on each SIMD
+    const int32_t k = waves_per_simd;
+    uint32_t* out = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipMalloc((void**)&out, (size_t)blocks * 256 * k * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e == hipSuccess) e = wlcs::launch_valu_issue(out, kind, blocks, k, iters < 1000 ? iters : 1000, stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
+    if (e == hipSuccess) e = wlcs::launch_valu_issue(out, kind, blocks, k, iters, stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (e == hipSuccess && ms > 0.0f) {
+        const double per_round = kind == 2 ? 40.0 : 16.0;
+        // waves x rounds x instructions, over the device's SIMDs (four per CU)
+        *instr_per_s = (double)blocks * 4.0 * k * (double)iters * per_round / (4.0 * ctx->cus) / (ms * 1e-3);
+    }
     for (hipEvent_t x : ev)
         if (x) (void)hipEventDestroy(x);
     if (stream) (void)hipStreamDestroy(stream);

@@ -5,8 +5,18 @@
 // instruction waits for the one before it, over enough waves to fill every
 // SIMD of every CU.  The second operand is a scalar register, so each
 // instruction reads a single vector register.
+//
+// The second helper measures the issue rate of wave64 VALU instructions with
+// a chosen number of waves resident on every SIMD: one workgroup of 256 k
+// threads per CU puts k waves on each of its four SIMDs at once.  Each wave
+// runs rounds of one kind of instruction stream: packed 16-bit or plain 32-bit
+// instructions on eight independent accumulators, or the seaweed cell down a
+// column of eight rows (each cell waits for the label the cell above sends
+// down, the dependency of the plot kernels).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "packed.hpp"
 
 namespace wlcs {
 namespace {
@@ -42,6 +52,64 @@ __global__ __launch_bounds__(256) void valu_peak_kernel(uint32_t* __restrict__ o
 // blocks x 256 threads; element operations per launch: blocks * 256 * iters * 64 * 2
 hipError_t launch_valu_peak(uint32_t* out, int32_t blocks, int32_t iters, hipStream_t stream) {
     hipLaunchKernelGGL(valu_peak_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, out, iters);
+    return hipGetLastError();
+}
+
+namespace {
+
+#define WLCS_ISSUE_ROUND(OP)                                                                        \
+    asm volatile(OP " %0, %0, %8\n\t" OP " %1, %1, %8\n\t" OP " %2, %2, %8\n\t" OP " %3, %3, %8\n\t" \
+                 OP " %4, %4, %8\n\t" OP " %5, %5, %8\n\t" OP " %6, %6, %8\n\t" OP " %7, %7, %8"      \
+                 : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)          \
+                 : "v"(b))
+
+// KIND 0: 16 v_pk_max_u16 per round, KIND 1: 16 v_xor_b32, KIND 2: eight
+// seaweed cells (40 instructions) down one column.
+template <int KIND>
+__global__ __launch_bounds__(1024) void valu_issue_kernel(uint32_t* __restrict__ out, int32_t iters) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t a0 = t, a1 = t ^ 0x11111111u, a2 = t ^ 0x22222222u, a3 = t ^ 0x33333333u;
+    uint32_t a4 = t ^ 0x44444444u, a5 = t ^ 0x55555555u, a6 = t ^ 0x66666666u, a7 = t ^ 0x77777777u;
+    const uint32_t b = t * 0x9E3779B9u;
+    for (int32_t i = 0; i < iters; ++i) {
+        if constexpr (KIND == 0) {
+            WLCS_ISSUE_ROUND("v_pk_max_u16");
+            WLCS_ISSUE_ROUND("v_pk_max_u16");
+        } else if constexpr (KIND == 1) {
+            WLCS_ISSUE_ROUND("v_xor_b32");
+            WLCS_ISSUE_ROUND("v_xor_b32");
+        } else {
+            // labels a0..a7 of eight rows, their letters in two registers,
+            // the column's letter (uniform) and top label from the round
+            const uint32_t y = (uint32_t)__builtin_amdgcn_readfirstlane(i * 0x00010001);
+            uint32_t d = wlcs::seaweed_cell_top(a0, (uint32_t)__builtin_amdgcn_readfirstlane(i), b, y);
+            d = wlcs::seaweed_cell<1>(a1, d, b, y);
+            d = wlcs::seaweed_cell<0>(a2, d, t, y);
+            d = wlcs::seaweed_cell<1>(a3, d, t, y);
+            d = wlcs::seaweed_cell<0>(a4, d, b, y);
+            d = wlcs::seaweed_cell<1>(a5, d, b, y);
+            d = wlcs::seaweed_cell<0>(a6, d, t, y);
+            d = wlcs::seaweed_cell<1>(a7, d, t, y);
+            a0 ^= d & 1u;  // keeps the column's exit alive
+        }
+    }
+    out[t] = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
+}
+#undef WLCS_ISSUE_ROUND
+
+}  // namespace
+
+// blocks x (256 k) threads; wave64 VALU instructions per wave and round:
+// 16 (kinds 0, 1) or 40 (kind 2)
+hipError_t launch_valu_issue(uint32_t* out, int32_t kind, int32_t blocks, int32_t k, int32_t iters,
+                             hipStream_t stream) {
+    const dim3 grid((uint32_t)blocks), block((uint32_t)(256 * k));
+    if (kind == 0)
+        hipLaunchKernelGGL(valu_issue_kernel<0>, grid, block, 0, stream, out, iters);
+    else if (kind == 1)
+        hipLaunchKernelGGL(valu_issue_kernel<1>, grid, block, 0, stream, out, iters);
+    else
+        hipLaunchKernelGGL(valu_issue_kernel<2>, grid, block, 0, stream, out, iters);
     return hipGetLastError();
 }
 

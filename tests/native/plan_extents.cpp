@@ -40,6 +40,7 @@ hipError_t launch_batch(int, const JobDesc*, int32_t, int64_t, unsigned long lon
 }
 hipError_t launch_zero_each(unsigned long long* const*, int32_t, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_valu_peak(uint32_t*, int32_t, int32_t, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_valu_issue(uint32_t*, int32_t, int32_t, int32_t, int32_t, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_candidates(const FilterArgs&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t scratch_address(int, uint8_t**) { return hipErrorNotSupported; }
 hipError_t launch_upload(uint8_t*, const uint8_t*, size_t, hipStream_t) { return hipErrorNotSupported; }

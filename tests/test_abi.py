@@ -109,6 +109,7 @@ def test_pair_and_ctx_argument_checks(lib):
     assert lib.wlcs_ctx_set_tiles(None, 1, 16, 1024, 64, 2) == EINVAL
     v = ctypes.c_double(-1.0)
     assert lib.wlcs_measure_valu_peak(None, 100, ctypes.byref(v)) == EINVAL and v.value == -1.0
+    assert lib.wlcs_measure_valu_issue(None, 0, 1, 100, ctypes.byref(v)) == EINVAL and v.value == -1.0
     assert lib.wlcs_ctx_create(0, None) == EINVAL
     assert lib.wlcs_tune_plot(None, None, 64, 1, 0, None, 0) == EINVAL
     t = [ctypes.c_int32(7) for _ in range(3)]
