@@ -105,6 +105,7 @@ def measured_traffic(workload: str, cells: float = 0.0):
         mean = lambda k: sum(vc[k]) / len(vc[k])
         insts = mean("SQ_INSTS_VALU")
         detail["valu"] = {"lane_instructions_per_cell": insts * 64 / cells,
+                          "instructions_per_launch": insts,
                           "salu_per_valu": mean("SQ_INSTS_SALU") / insts}
         ns = d.get("valu_run_kernel_ns")
         if ns and "GRBM_COUNT" in vc:
@@ -122,6 +123,67 @@ def measured_traffic(workload: str, cells: float = 0.0):
                 # the counter's accounting: one quad-cycle per wave64 instruction
                 "valu_quad_cycles_per_instruction": vc["SQ_ACTIVE_INST_VALU"][-1] / vc["SQ_INSTS_VALU"][-1]})
     return detail["read_bytes"] + detail["write_bytes"], detail
+
+
+# kernel sources whose digest the counter summary records (a summary of
+# other sources is stale and its bytes are not reported)
+COUNTER_DIGEST_FILES = ["paper_0909_2000_amd/csrc/seaweed.hip", "paper_0909_2000_amd/csrc/seaweed_unit.hpp",
+                        "paper_0909_2000_amd/csrc/packed.hpp", "paper_0909_2000_amd/csrc/kernels.hpp"]
+
+
+def write_counters(prof_dir: str, workload: str, commands: list) -> str:
+    """Summarise rocprofv3 runs of this benchmark into
+    profiles/seaweed_counters_<workload>.json: the timed kernel's FETCH_SIZE
+    and WRITE_SIZE per dispatch (runs bytes_FETCH_SIZE and bytes_WRITE_SIZE,
+    made with --calib-copy) beside the same counters of the plain 1 GiB copy,
+    and its VALU and clock counters with the launch times of that run
+    (valu_<workload>).  No GPU is used."""
+    import csv
+    import hashlib
+
+    def dispatches(sub, pick):
+        rows = list(csv.DictReader(open(os.path.join(prof_dir, sub, "run_counter_collection.csv"))))
+        per = {}
+        for r in rows:
+            e = per.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})
+            e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        return pick([per[k] for k in sorted(per)])
+
+    def timed_kernel(ds):  # the plot kernel of the run: its dispatches, in order
+        plot = [d for d in ds if "seaweed_kernel" in d["name"]]
+        name = max(plot, key=lambda d: d.get("SQ_INSTS_VALU", d.get("FETCH_SIZE", d.get("WRITE_SIZE", 0))))["name"]
+        return [d for d in plot if d["name"] == name]
+
+    def copy_kernel(ds):  # the largest device copy of the run
+        return [max((d for d in ds if "copyBuffer" in d["name"]), key=lambda d: list(d.values())[-1])]
+
+    fetch = dispatches("bytes_FETCH_SIZE", timed_kernel)
+    write = dispatches("bytes_WRITE_SIZE", timed_kernel)
+    cf = dispatches("bytes_FETCH_SIZE", copy_kernel)[0]
+    cw = dispatches("bytes_WRITE_SIZE", copy_kernel)[0]
+    valu = dispatches(f"valu_{workload}", timed_kernel)
+    trace = list(csv.DictReader(open(os.path.join(prof_dir, f"valu_{workload}", "run_kernel_trace.csv"))))
+    ns = [int(t["End_Timestamp"]) - int(t["Start_Timestamp"]) for t in trace
+          if t["Kernel_Name"] == valu[0]["name"]]
+    h = hashlib.sha1()
+    for fn in COUNTER_DIGEST_FILES:
+        with open(os.path.join(ROOT, fn), "rb") as f:
+            h.update(f.read())
+    name = valu[0]["name"]
+    short = name[name.index("seaweed_kernel"):name.index(">") + 1] if ">" in name else name
+    counters = sorted(k for k in valu[0] if k != "name")
+    out = {"kernel": short, "workload": workload, "kernel_digest": h.hexdigest(),
+           "digest_files": COUNTER_DIGEST_FILES,
+           "fetch_kib_per_dispatch": [d["FETCH_SIZE"] for d in fetch],
+           "write_kib_per_dispatch": [d["WRITE_SIZE"] for d in write],
+           "copy_bytes": 1 << 30, "copy_fetch_kib": cf["FETCH_SIZE"], "copy_write_kib": cw["WRITE_SIZE"],
+           "valu_counters_per_dispatch": {k: [d[k] for d in valu] for k in counters},
+           "valu_run_kernel_ns": ns, "commands": commands}
+    path = os.path.join(ROOT, "profiles", f"seaweed_counters_{workload}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    return path
 
 
 def main():
@@ -151,8 +213,20 @@ def main():
                     help="skip the alignment-score plots shaped like the paper's experiments")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--write-counters", metavar="DIR",
+                    help="write profiles/seaweed_counters_<workload>.json from the rocprofv3 runs under DIR "
+                         "(bytes_FETCH_SIZE, bytes_WRITE_SIZE, valu_<workload>) and exit; no GPU")
+    ap.add_argument("--counter-commands", metavar="FILE",
+                    help="with --write-counters: a text file of the rocprofv3 commands, one a line")
     args = ap.parse_args()
 
+    if args.write_counters:
+        cmds = []
+        if args.counter_commands:
+            with open(args.counter_commands) as f:
+                cmds = [ln.strip() for ln in f if ln.strip()]
+        print(write_counters(args.write_counters, args.workload, cmds))
+        return
     if args.serving_child:
         serving_child(args)
         return
@@ -251,6 +325,12 @@ def main():
     measured_peak = max(ctx.measure_valu_peak(8000) for _ in range(2))
     log(f"measured packed-u16 VALU peak: {measured_peak / 1e12:.1f} TOP/s "
         f"(published {PEAK_U16_OPS / 1e12:.1f})")
+    # the library's issue-rate probe: wave64 VALU instructions per second per
+    # SIMD at one to four resident waves per SIMD, for packed 16-bit and plain
+    # 32-bit streams and for the seaweed cell's own dependency chain
+    issue = {kind: [ctx.measure_valu_issue(kind, k) for k in (1, 2, 3, 4)] for kind in ("pk16", "b32", "cell")}
+    log("VALU issue probe (M instructions/s per SIMD, 1..4 waves): " +
+        "; ".join(f"{k} " + " ".join(f"{r / 1e6:.0f}" for r in v) for k, v in issue.items()))
     launch_s = avg_kernel_ms / 1e3
     if traffic_detail is not None and "write_bytes" in traffic_detail:
         traffic_detail["write_TB_per_s"] = traffic_detail["write_bytes"] / launch_s / 1e12
@@ -262,7 +342,14 @@ def main():
                 "measured_peak": measured_peak / 1e12, "frac_of_measured_peak": achieved / measured_peak,
                 "peak_probe": "wlcs_measure_valu_peak: independent v_pk_max_u16 chains on every SIMD",
                 "ops_per_cell": OPS_PER_CELL, "cells_per_launch": cells,
-                "avg_launch_ms": avg_kernel_ms}
+                "avg_launch_ms": avg_kernel_ms,
+                "valu_issue_probe_instr_per_s_per_simd": {k: [float(r) for r in v] for k, v in issue.items()}}
+    valu = (traffic_detail or {}).get("valu")
+    if valu and "instructions_per_launch" in valu:
+        # the timed kernel's own issue rate: its (deterministic) VALU
+        # instruction count over this run's launch time, per SIMD
+        simds = 4 * torch.cuda.get_device_properties(dev).multi_processor_count
+        roofline["valu_instr_per_s_per_simd"] = valu["instructions_per_launch"] / simds / launch_s
 
     # serving right after the headline plot: measured after the heavier legs
     # below, its latencies read 30-40% higher (the legs are independent)

@@ -84,6 +84,7 @@ def _load():
     lib.wlcs_ctx_set_tile.argtypes = [vp, i32, i32, i32]
     lib.wlcs_ctx_set_tiles.argtypes = [vp, i32, i32, i32, i32, i32]
     lib.wlcs_measure_valu_peak.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+    lib.wlcs_measure_valu_issue.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_double)]
     plot_args = [vp, u8p, i64, u8p, i64, i32, u8p, i32, vp, i64, vp, i64, i32, vp, i64, u32, vp]
     lib.wlcs_plot.argtypes = plot_args
     lib.wlcs_plot_dp.argtypes = plot_args
@@ -114,7 +115,7 @@ def _load():
     lib.wlcs_pair_dots_filtered.argtypes = [vp, vp, i32, i32, i32, i64, vp, i64, vp, ctypes.c_uint32, vp]
     lib.wlcs_pair_plot_dp_strided.argtypes = strided_args
     for f in ("wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_ctx_set_tile", "wlcs_ctx_set_tiles",
-              "wlcs_measure_valu_peak",
+              "wlcs_measure_valu_peak", "wlcs_measure_valu_issue",
               "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot",
               "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_noalloc", "wlcs_batch_graph",
               "wlcs_graph_launch", "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
@@ -129,8 +130,8 @@ def _load():
 def exported_symbols() -> list:
     """Names of the C ABI entry points the binding uses."""
     return ["wlcs_ctx_create", "wlcs_ctx_destroy", "wlcs_ctx_last_hip_error", "wlcs_status_str",
-            "wlcs_ctx_set_tile", "wlcs_ctx_set_tiles", "wlcs_measure_valu_peak", "wlcs_plot", "wlcs_plot_dp",
-            "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch",
+            "wlcs_ctx_set_tile", "wlcs_ctx_set_tiles", "wlcs_measure_valu_peak", "wlcs_measure_valu_issue",
+            "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot", "wlcs_pair_plot_dp", "wlcs_batch",
             "wlcs_batch_noalloc", "wlcs_batch_graph", "wlcs_graph_launch", "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
             "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
             "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs", "wlcs_pair_plot_blcs",
@@ -152,6 +153,16 @@ def dot_records(res: dict) -> np.ndarray:
     k = min(count, int(dots.shape[0])) if dots is not None else 0
     recs = dots[:k].cpu().numpy().view(DOT).reshape(-1) if k else np.zeros(0, dtype=DOT)
     return np.sort(recs, order=("i", "j")), count
+
+
+def plot_rows(rows: int, cols: int, dtype, device):
+    """A rows x cols output (plot or indel distances) whose rows start a
+    multiple of 16 bytes apart (a view of a padded allocation): the kernels
+    store each strip's block of windows with 16-byte stores, where rows of any
+    other length take one store per window.  The padding is never written."""
+    per = 16 // torch.empty((), dtype=dtype).element_size()
+    ld = max(-(-cols // per) * per, per)
+    return torch.empty((rows, ld), dtype=dtype, device=device)[:, :cols]
 
 
 def n_windows(length: int, w: int, full_range: bool = False) -> int:
@@ -215,6 +226,19 @@ class Context:
             raise WlcsError(st, "wlcs_measure_valu_peak", _load().wlcs_ctx_last_hip_error(self._h))
         return v.value
 
+    VALU_KINDS = {"pk16": 0, "b32": 1, "cell": 2}
+
+    def measure_valu_issue(self, kind: str, waves_per_simd: int, iters: int = 100000) -> float:
+        """wlcs_measure_valu_issue: wave64 VALU instructions issued per second
+        per SIMD with waves_per_simd (1..4) waves resident on every SIMD, for
+        one kind of stream ("pk16", "b32" or "cell"; a measurement helper)."""
+        v = ctypes.c_double(0.0)
+        st = _load().wlcs_measure_valu_issue(self._h, self.VALU_KINDS[kind], int(waves_per_simd), int(iters),
+                                             ctypes.byref(v))
+        if st != 0:
+            raise WlcsError(st, "wlcs_measure_valu_issue", _load().wlcs_ctx_last_hip_error(self._h))
+        return v.value
+
     def set_tiles(self, w_lo: int, w_hi: int, long_tile: int, short_tile: int, long_pairs: int):
         """wlcs_ctx_set_tiles: long tiles for the first long_pairs tile pairs
         of every strip block, short tiles after them."""
@@ -225,12 +249,12 @@ class Context:
     def _outputs(self, rows, cols, threshold, indel, out, bitmap_out, indel_out, want_plot):
         dev = torch.device("cuda", self.device)
         if out is None and want_plot:
-            out = torch.empty((rows, cols), dtype=torch.uint8, device=dev)
+            out = plot_rows(rows, cols, torch.uint8, dev)
         words = (cols + 63) // 64
         if threshold is not None and bitmap_out is None:
             bitmap_out = torch.empty((rows, words), dtype=torch.int64, device=dev)
         if indel and indel_out is None:
-            indel_out = torch.empty((rows, cols), dtype=torch.int16, device=dev)
+            indel_out = plot_rows(rows, cols, torch.int16, dev)
         for t in (out, bitmap_out, indel_out):
             if t is not None and (t.device != dev or t.dim() != 2 or t.stride(1) != 1):
                 raise ValueError("outputs must be 2-D row-major tensors on the context's device")
@@ -416,7 +440,7 @@ class Context:
         cols = n_windows(ya.size, w, full_range)
         dev = torch.device("cuda", self.device)
         if out is None and want_plot:
-            out = torch.empty((rows, cols), dtype=torch.int8, device=dev)
+            out = plot_rows(rows, cols, torch.int8, dev)
         if threshold is not None and bitmap_out is None:
             bitmap_out = torch.empty((rows, (cols + 63) // 64), dtype=torch.int64, device=dev)
         for t in (out, bitmap_out):

@@ -24,6 +24,10 @@ constexpr uint32_t kPadCode = 63;
 // Windows between two relabellings of the seaweed labels (a multiple of 32).
 constexpr int kRebase = 512;
 
+// Geom::wmode bit: the indel rows start 16 bytes apart (each lane stores its
+// strip's indel values with 16-byte stores).
+constexpr int32_t kIndelRows16 = 4;
+
 // One plot's worth of kernel arguments (host side).
 // One dot of a sparse plot: window starts, WLCS and indel distance (the
 // wlcs_dot record of the C ABI).
@@ -70,7 +74,8 @@ struct Geom {
     int64_t xstride;   // x codes between consecutive strips (1: every x-window)
     int32_t w, tile, npairs, threshold;
     int32_t tile2, nbig;  // pairs from nbig on have tiles of tile2 windows
-    int32_t wmode;     // plot stores: 2 = 16-byte rows, 1 = 4-byte rows, 0 = bytes
+    int32_t wmode;     // bits 0-1, plot stores: 2 = 16-byte rows, 1 = 4-byte rows, 0 = bytes;
+                       // bit 2 (kIndelRows16): indel rows start 16 bytes apart (16-byte stores)
     int32_t bias;      // subtracted from every stored value (0..127)
     int64_t hy;        // strided plots: output column c is the window c * hy
     int64_t dot_cap;   // dot records the sparse output holds
@@ -115,6 +120,7 @@ inline Geom geom_of(const PlotArgs& a) {
     g.x0 = a.x0;
     const uintptr_t base = (uintptr_t)a.wlcs;
     g.wmode = (a.ld % 16 == 0 && base % 16 == 0) ? 2 : (a.ld % 4 == 0 && base % 4 == 0) ? 1 : 0;
+    if (a.ld_indel % 8 == 0 && (uintptr_t)a.indel % 16 == 0) g.wmode |= kIndelRows16;
     return g;
 }
 

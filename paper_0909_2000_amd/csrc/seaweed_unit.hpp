@@ -521,7 +521,12 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         }
         if constexpr (UPPER) continue;  // the lower wave stores
         stage_sync();
-        const int64_t s = s0 + lane;  // this lane's strip
+        // this lane's strip (for windows of at most 32 letters, at four
+        // waves per SIMD, an opaque copy per flush: the row addresses
+        // derived from it are then formed here instead of being held in
+        // registers through the combing, which spilled them)
+        int64_t s = s0 + lane;
+        if constexpr (WC <= 32) asm volatile("" : "+v"(s));
 #pragma unroll 1
         for (int half = 0; half < 2; ++half) {
             const int64_t ts = half ? tB : tA;
@@ -572,11 +577,12 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
 #pragma unroll
                 for (int k = 0; k < FO / 4; ++k) d[k] = sub_bytes(d[k], (uint32_t)g.bias * 0x01010101u);
             }
-            if (out && g.wmode > 0 && nvalid > 0) {
+            const int pmode = g.wmode & 3;
+            if (out && pmode > 0 && nvalid > 0) {
                 if (s < g.rows) {
                     uint8_t* row = out + s * g.ld + o0;
                     if (nvalid == FO) {
-                        if (g.wmode == 2) {
+                        if (pmode == 2) {
 #pragma unroll
                             for (int k = 0; k < FO / 16; ++k)
                                 ((uint4*)row)[k] = make_uint4(d[4 * k], d[4 * k + 1], d[4 * k + 2], d[4 * k + 3]);
@@ -584,12 +590,34 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
 #pragma unroll
                             for (int k = 0; k < FO / 4; ++k) ((uint32_t*)row)[k] = d[k];
                         }
-                    } else {
-                        for (int b = 0; b < nvalid; ++b) row[b] = (uint8_t)(d[b >> 2] >> (8 * (b & 3)));
+                    } else {  // a partial block: from the staged row (d cannot be indexed at run time)
+                        const uint8_t* ob = (const uint8_t*)(stage + half * 64 * PITCH + lane * PITCH);
+                        for (int b = 0; b < nvalid; ++b) row[b] = (uint8_t)(ob[b * WS] - (uint32_t)g.bias);
                     }
                 }
             }
-            if (((out && g.wmode == 0) || indel) && nvalid > 0) {
+            if (WS == 1 && indel && (g.wmode & kIndelRows16) && nvalid > 0 && s < g.rows) {
+                // this strip's indel distances 2w - 2v, read again from its
+                // staged row: four per 8-byte store (two u16 lanes per dword,
+                // the bytes spread by v_perm)
+                const uint32_t* own = stage + half * 64 * PITCH + lane * PITCH;
+                uint16_t* irow = indel + s * g.ld_indel + o0;
+                if (nvalid == FO) {
+                    const uint32_t w2x2 = (uint32_t)(2 * w) * 0x00010001u;
+#pragma unroll 2
+                    for (int k = 0; k < FO / 4; ++k) {
+                        const uint32_t v = own[k];
+                        const uint32_t lo = __builtin_amdgcn_perm(0u, v, 0x0c010c00u);  // bytes 0, 1
+                        const uint32_t hi = __builtin_amdgcn_perm(0u, v, 0x0c030c02u);  // bytes 2, 3
+                        ((uint2*)irow)[k] = make_uint2(pk_sub(w2x2, pk_add(lo, lo)), pk_sub(w2x2, pk_add(hi, hi)));
+                    }
+                } else {
+                    const uint8_t* ob = (const uint8_t*)own;
+                    for (int b = 0; b < nvalid; ++b) irow[b] = (uint16_t)(2 * w - 2 * (int)ob[b]);
+                }
+            }
+            const bool indel_t = indel && (WS != 1 || !(g.wmode & kIndelRows16));
+            if (((out && pmode == 0) || indel_t) && nvalid > 0) {
                 // transposed: the lanes cover FO outputs of 64 / FO strips per step
                 constexpr int RPI = 64 / FO;
                 const int q = lane % FO;
@@ -600,8 +628,8 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                     const int64_t sr = s0 + r;
                     const uint32_t v = sbytes[(half * 64 * PITCH + r * PITCH) * 4 + q * WS];
                     if (sr < g.rows && q < nvalid) {
-                        if (out && g.wmode == 0) out[sr * g.ld + o0 + q] = (uint8_t)(v - (uint32_t)g.bias);
-                        if (indel) indel[sr * g.ld_indel + o0 + q] = (uint16_t)(2 * w - 2 * (int)v);
+                        if (out && pmode == 0) out[sr * g.ld + o0 + q] = (uint8_t)(v - (uint32_t)g.bias);
+                        if (indel_t) indel[sr * g.ld_indel + o0 + q] = (uint16_t)(2 * w - 2 * (int)v);
                     }
                 }
             }
