@@ -274,8 +274,10 @@ int wlcs_pair_plot_dp_strided(wlcs_ctx *ctx, const wlcs_pair *pair, int32_t w, i
  * al. for the seaweed method; this is an exact version of such a filter.  It
  * rests on one property of the plot: moving the x-window by one letter changes
  * its LLCS with any y-window by at most one, so |WLCS(i + d, j) - WLCS(i, j)|
- * <= |d|.  The probe strips -- every probe_step-th x-window and the last one
- * -- are combed and listed at threshold - floor(probe_step / 2); every other
+ * <= |d|.  The probe strips -- every probe_step-th x-window, starting at
+ * half the remainder of (rows - 1) / probe_step so that no row is more than
+ * floor(probe_step / 2) rows from a probe -- are combed and listed at
+ * threshold - floor(probe_step / 2); every other
  * row takes its nearest probe (the lower one on ties), and only its windows
  * whose probe entry comes within reach of the threshold are evaluated, each
  * exactly (bit-parallel LCS of the window pair).  probe_step = 1 combs every

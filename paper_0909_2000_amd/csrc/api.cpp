@@ -1108,9 +1108,11 @@ int wlcs_pair_dots_filtered(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, int
     if (e != hipSuccess) return fail(ctx, e);
     if (rows == 0 || cols == 0) return WLCS_OK;
     const int64_t h = probe_step;
-    const int64_t rows_a = (rows + h - 1) / h;            // probe strips 0, h, 2h, ...
-    const bool extra = (rows - 1) % h != 0;               // and the last x-window
-    const int64_t probe_rows = rows_a + (extra ? 1 : 0);
+    // probe strips first, first + h, ..., starting at half the remainder of
+    // (rows - 1) / h, so that the rows before the first probe and after the
+    // last one are at most floor(h / 2) rows from it, like every other row
+    const int64_t first = ((rows - 1) % h) / 2;
+    const int64_t probe_rows = (rows - 1 - first) / h + 1;
     if (probe_cap == 0)  // about one entry in 32 of the probe strips, at least 64 Ki, at most 128 Mi
         probe_cap = std::min<int64_t>(std::max<int64_t>(65536, probe_rows * cols / 32), (int64_t)1 << 27);
     if (pair->m + wlcs::w_class(w) > pair->xf_cap) return WLCS_EINVAL;  // cannot happen for a valid pair
@@ -1143,8 +1145,7 @@ int wlcs_pair_dots_filtered(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, int
         a.sigma = pair->sigma;
         return wlcs::launch_seaweed(a, stream);
     };
-    if (e == hipSuccess) e = probe_launch(rows_a, 0, h);
-    if (e == hipSuccess && extra) e = probe_launch(1, rows - 1, 1);
+    if (e == hipSuccess) e = probe_launch(probe_rows, first, h);
     if (e == hipSuccess) {
         wlcs::FilterArgs f;
         f.xf = pair->xf;
@@ -1153,6 +1154,7 @@ int wlcs_pair_dots_filtered(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, int
         f.probe_cap = probe_cap;
         f.probe_count = probe_count;
         f.rows = rows;
+        f.first = first;
         f.w = w;
         f.sigma = pair->sigma;
         f.h = (int32_t)h;

@@ -4,11 +4,11 @@
 // Moving an x-window by one letter drops one letter and adds one, so its LLCS
 // with any y-window changes by at most one: |WLCS(i + d, j) - WLCS(i, j)| <=
 // |d|.  The host runtime therefore combs only the probe strips -- every h-th
-// x-window and the last one -- with the seaweed kernel, listing their entries
-// at the lowered threshold T - floor(h / 2).  Every other row i has a
-// designated nearest probe p (the lower one on ties), at most floor(h / 2)
-// rows away, and a dot (i, j) implies WLCS(p, j) >= T - |i - p|, so p has
-// listed (p, j).  The kernel below takes each listed probe entry (p, j, v):
+// x-window, starting at half the remainder of (rows - 1) / h so that no row
+// lies more than floor(h / 2) rows from a probe -- with the seaweed kernel,
+// listing their entries at the lowered threshold T - floor(h / 2).  Every
+// other row i has a designated nearest probe p (the lower one on ties), and a
+// dot (i, j) implies WLCS(p, j) >= T - |i - p|, so p has listed (p, j).  The kernel below takes each listed probe entry (p, j, v):
 // probe entries with v >= T are dots as they stand, and every row i whose
 // designated probe is p with v + |i - p| >= T is a candidate, evaluated
 // exactly and listed if it reaches T.  Each window pair is considered from one
@@ -80,7 +80,8 @@ template <int NW>
 __global__ __launch_bounds__(64) void candidates_kernel(const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32,
                                                         const DotRec* __restrict__ probe, int64_t probe_cap,
                                                         const unsigned long long* __restrict__ probe_count,
-                                                        int64_t rows, int32_t w, int32_t sigma, int32_t h,
+                                                        int64_t rows, int64_t first, int32_t w, int32_t sigma,
+                                                        int32_t h,
                                                         int32_t threshold, DotRec* __restrict__ dots, int64_t dot_cap,
                                                         unsigned long long* __restrict__ dot_count,
                                                         uint32_t* __restrict__ fallback) {
@@ -92,6 +93,7 @@ __global__ __launch_bounds__(64) void candidates_kernel(const uint16_t* __restri
         return;
     }
     const int H = h / 2;
+    const int64_t last = first + (rows - 1 - first) / h * h;  // the last probe row
     const int64_t stride = (int64_t)gridDim.x * 64;
     for (int64_t e = (int64_t)blockIdx.x * 64 + lane; e < (int64_t)n; e += stride) {
         const DotRec r = probe[e];
@@ -117,10 +119,18 @@ __global__ __launch_bounds__(64) void candidates_kernel(const uint16_t* __restri
         }
         for (int d = -H; d <= H; ++d) {
             const int64_t i = p + d;
-            if (d == 0 || i < 0 || i >= rows || i % h == 0 || i == rows - 1) continue;  // not a probe row
-            const int64_t lo = i / h * h;
-            const int64_t hi = lo + h <= rows - 1 ? lo + h : rows - 1;
-            const int64_t near = i - lo <= hi - i ? lo : hi;  // the designated probe of row i
+            if (d == 0 || i < 0 || i >= rows) continue;
+            // the designated probe of row i (a probe row is its own, so it
+            // is never a candidate of another probe)
+            int64_t near;
+            if (i <= first) {
+                near = first;
+            } else if (i >= last) {
+                near = last;
+            } else {
+                const int64_t lo = first + (i - first) / h * h;
+                near = i - lo <= lo + h - i ? lo : lo + h;
+            }
             if (near != p || v + (d < 0 ? -d : d) < threshold) continue;
             uint32_t vec[NW];
 #pragma unroll
@@ -160,7 +170,7 @@ hipError_t candidates_nw(const FilterArgs& f, hipStream_t stream) {
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((candidates_kernel<NW>), dim3((uint32_t)f.grid), dim3(64), lds, stream, f.xf,
-                       (const uint32_t*)f.yg, f.probe, f.probe_cap, f.probe_count, f.rows, f.w, f.sigma, f.h,
+                       (const uint32_t*)f.yg, f.probe, f.probe_cap, f.probe_count, f.rows, f.first, f.w, f.sigma, f.h,
                        f.threshold, f.dots, f.dot_cap, f.dot_count, f.fallback);
     return hipGetLastError();
 }

@@ -224,7 +224,7 @@ hipError_t launch_batch(int group, const JobDesc* jobs_dev, int32_t njobs, int64
 hipError_t launch_zero_each(unsigned long long* const* ptrs, int32_t n, hipStream_t stream);
 
 // The exact threshold filter for dot lists (filter.hip): from the probe
-// strips' listed entries (every h-th x-window and the last one, listed at
+// strips' listed entries (every h-th x-window from `first`, listed at
 // threshold - h / 2), the dots of every row.  If the probe list overflowed,
 // nothing is listed and *fallback is set.
 struct FilterArgs {
@@ -234,6 +234,7 @@ struct FilterArgs {
     int64_t probe_cap;
     const unsigned long long* probe_count;
     int64_t rows;        // x-windows of the plot
+    int64_t first;       // the first probe row (the probes are first, first + h, ...)
     int32_t w, sigma, h, threshold;
     DotRec* dots;        // the caller's list (may be null while counting)
     int64_t dot_cap;

@@ -6,8 +6,10 @@ x-window by one letter drops one letter and adds one, so the LLCS changes by
 at most one, and |WLCS(i + d, j) - WLCS(i, j)| <= |d| (pinned by the oracle's
 invariant tests).  So:
 
-* probe rows: every h-th x-window and the last one, each listed completely at
-  the lowered threshold T - floor(h / 2);
+* probe rows: every h-th x-window, starting at half the remainder of
+  (rows - 1) / h (so the rows before the first probe and after the last are
+  no farther from it than any other row), each listed completely at the
+  lowered threshold T - floor(h / 2);
 * every other row i has a designated nearest probe p (the lower one on ties),
   at most floor(h / 2) rows away; a dot (i, j) implies
   WLCS(p, j) >= T - |i - p| >= T - floor(h / 2), so p lists (p, j);
@@ -25,13 +27,13 @@ import workloads
 
 
 def probes(rows: int, h: int) -> list:
-    return sorted(set(range(0, rows, h)) | {rows - 1})
+    first = ((rows - 1) % h) // 2
+    return list(range(first, rows, h))
 
 
 def nearest_probe(i: int, rows: int, h: int) -> int:
-    lo = (i // h) * h
-    hi = lo + h if lo + h <= rows - 1 else rows - 1
-    return lo if i - lo <= hi - i else hi
+    P = probes(rows, h)
+    return min(P, key=lambda p: (abs(i - p), p))  # the nearest, the lower one on ties
 
 
 def filtered_dots(oracle_mod, x, y, w, T, h, probe_slack=None):
@@ -78,15 +80,28 @@ def _case(seed, w, m, n, planted=True):
     return x, y
 
 
+def designated_as_the_kernel_computes(i: int, rows: int, h: int) -> int:
+    """The candidate kernel's closed form of a row's designated probe."""
+    first = ((rows - 1) % h) // 2
+    last = first + (rows - 1 - first) // h * h
+    if i <= first:
+        return first
+    if i >= last:
+        return last
+    lo = first + (i - first) // h * h
+    return lo if i - lo <= lo + h - i else lo + h
+
+
 def test_nearest_probe_is_within_half_a_step():
-    for rows in (1, 2, 3, 7, 16, 17, 40):
-        for h in (1, 2, 3, 4, 5, 8, 50):
-            P = set(probes(rows, h))
-            assert 0 in P and rows - 1 in P
-            for i in range(rows):
+    for rows in list(range(1, 41)) + [49936, 29872]:
+        for h in (1, 2, 3, 4, 5, 6, 7, 8, 12, 50):
+            P = probes(rows, h)
+            assert all(b - a == h for a, b in zip(P, P[1:]))
+            assert P[0] <= h // 2 and rows - 1 - P[-1] <= h // 2
+            for i in (range(rows) if rows < 100 else list(range(200)) + list(range(rows - 200, rows))):
                 p = nearest_probe(i, rows, h)
-                assert p in P and abs(i - p) <= h // 2
-                assert all(abs(i - p) <= abs(i - q) for q in P)
+                assert abs(i - p) <= h // 2
+                assert designated_as_the_kernel_computes(i, rows, h) == p, (rows, h, i)
 
 
 @pytest.mark.parametrize("h", [1, 2, 3, 4, 5, 8, 13, 200])
