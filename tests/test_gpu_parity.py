@@ -268,6 +268,27 @@ def test_row_strides(lib, ctx, oracle_mod, pad):
     assert np.all(got[:, cols:] == 0xEE)  # nothing written past the row
 
 
+@pytest.mark.parametrize("pad", [0, 1, 3, 11])
+def test_indel_row_strides(ctx, oracle_mod, pad):
+    """Indel rows 397 + pad u16 apart: 400 and 408 start 16 bytes apart and
+    take each lane's 8-byte stores, 397 and 398 the transposed 2-byte stores.
+    Either way every value equals the oracle's 2w - 2 WLCS, the last partial
+    block of each row included, and nothing is written past a row."""
+    import torch
+    g = workloads.rng(3100 + pad)
+    for w in (16, 40, 64, 100):
+        x, y = workloads.iid(g, 150 + w, workloads.DNA), workloads.iid(g, 397 + w, workloads.DNA)
+        want = oracle_mod.wlcs(x, y, w)
+        rows, cols = want.shape
+        buf = torch.full((rows, cols + pad), -7, dtype=torch.int16, device="cuda")
+        res = ctx.plot(x, y, w, threshold=w // 2, indel=True, indel_out=buf[:, :cols])
+        got = _cpu(buf)
+        np.testing.assert_array_equal(got[:, :cols].view(np.uint16), oracle_mod.indel(want, w))
+        assert np.all(got[:, cols:] == -7)
+        np.testing.assert_array_equal(_cpu(res["wlcs"]), want)
+        np.testing.assert_array_equal(_bitmap_u64(res["bitmap"]), oracle_mod.dot_bitmap(want, w // 2))
+
+
 @pytest.mark.parametrize("w,thr", [(16, 12), (64, 48), (33, 0), (20, 21)])
 def test_epilogues(ctx, oracle_mod, w, thr):
     g = workloads.rng(4000 + w)
