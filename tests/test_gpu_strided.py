@@ -70,6 +70,29 @@ def test_strided_plot_and_dots_vs_oracle(oracle_mod, m, n, w, hx, hy, alpha, pat
         np.testing.assert_array_equal(bm.cpu().numpy().view("<u8"), oracle_mod.dot_bitmap(want, thr))
 
 
+@pytest.mark.parametrize("w,hy", [(16, 1), (16, 3), (100, 1), (100, 2)])
+def test_dot_lists_at_the_threshold_extremes(oracle_mod, w, hy):
+    """Threshold 0 lists every window pair (every lane of every block has
+    dots: the wave scan and the per-lane records at full density), threshold
+    w only the exact matches, and a threshold above w none at all."""
+    import torch
+    import paper_0909_2000_amd as wl
+    g = workloads.rng(6100 + w + hy)
+    x, y = _pair_with_homology(g, 260 + w, 300 + w, workloads.DNA, w)
+    want = oracle_mod.wlcs_strided(x, y, w, 2, hy)
+    ctx = wl.Context(0)
+    pair = ctx.pair(x, y)
+    for thr in (0, w, w + 1):
+        res = pair.plot_strided(w, 2, hy, threshold=thr, want_plot=False, dot_cap=want.size + 1)
+        torch.cuda.synchronize()
+        dots, count = wl.dot_records(res)
+        ref = oracle_mod.dot_list(want, w, thr, 2, hy)
+        assert count == ref.size, (thr, count, ref.size)
+        if thr == 0:
+            assert count == want.size
+        np.testing.assert_array_equal(dots.view(np.uint8), ref.view(np.uint8))
+
+
 def test_dot_list_capacity_and_count_only(oracle_mod):
     import torch
     import paper_0909_2000_amd as wl
