@@ -14,7 +14,9 @@ are released:
   equals the thresholded plot;
 * a seeded sample of 520 jobs of every size: its bitmap and indel distances
   equal the job run alone on the device, on a stream of its own, from the
-  same resident strings.
+  same resident strings;
+* 20 seeded jobs among the larger ones: two seeded rows of each plot (from
+  its indel distances) equal the oracle's rows of that job.
 """
 import hashlib
 import os
@@ -48,7 +50,7 @@ def _bitmap_of(plot: np.ndarray, thr: int) -> np.ndarray:
     return np.packbits(bits, axis=1, bitorder="little").view("<u8").reshape(rows, words)
 
 
-def test_every_job_of_the_serving_stream():
+def test_every_job_of_the_serving_stream(oracle_mod):
     import torch
     from paper_0909_2000_amd import serve
 
@@ -57,8 +59,11 @@ def test_every_job_of_the_serving_stream():
     jobs = workloads.serving_jobs(rate=1.0, njobs=2000)
     reqs = serve.requests_from_workload(jobs, rate_scale=1200.0)
     sample = set(int(k) for k in workloads.rng(5050).choice(len(reqs), 520, replace=False))
+    g = workloads.rng(5060)
+    large = sorted(r.jid for r in reqs if r.jid not in small)
+    rows_checked = {int(j): None for j in g.choice(large, 20, replace=False)}
     alone_stream = torch.cuda.Stream()
-    seen = {"oracle": 0, "alone": 0}
+    seen = {"oracle": 0, "alone": 0, "oracle_rows": 0}
     bad = []
 
     def on_done(req, res):
@@ -72,6 +77,13 @@ def test_every_job_of_the_serving_stream():
                     not np.array_equal(bm.cpu().numpy().view("<u8"), _bitmap_of(plot, req.threshold))):
                 bad.append(("oracle", req.jid))
             seen["oracle"] += 1
+        if req.jid in rows_checked:
+            d = ind.cpu().numpy().view(np.uint16)
+            picks = np.sort(workloads.rng(5070 + req.jid).choice(d.shape[0], 2, replace=False))
+            want = oracle_mod.wlcs_rows(req.x, req.y, req.w, picks)
+            if not np.array_equal((req.w - d[picks] // 2).astype(np.uint8), want):
+                bad.append(("oracle rows", req.jid))
+            seen["oracle_rows"] += 1
         if req.jid in sample:
             pair = res["_pair"]  # the job's own resident strings
             alone = pair.plot(req.w, threshold=req.threshold, indel=True, want_plot=False, stream=alone_stream)
@@ -89,5 +101,5 @@ def test_every_job_of_the_serving_stream():
     torch.cuda.synchronize()
     print("report", rep, "checked", seen, flush=True)
     assert rep["rejected"] == 0 and rep["overlapped_launches"] > 0
-    assert seen == {"oracle": 636, "alone": 520}
+    assert seen == {"oracle": 636, "alone": 520, "oracle_rows": 20}
     assert not bad, bad[:20]
