@@ -327,8 +327,10 @@ def main():
         f"(published {PEAK_U16_OPS / 1e12:.1f})")
     # the library's issue-rate probe: wave64 VALU instructions per second per
     # SIMD at one to four resident waves per SIMD, for packed 16-bit and plain
-    # 32-bit streams and for the seaweed cell's own dependency chain
-    issue = {kind: [ctx.measure_valu_issue(kind, k) for k in (1, 2, 3, 4)] for kind in ("pk16", "b32", "cell")}
+    # 32-bit streams and for the seaweed cell's own dependency chain (and the
+    # same chain with the letter comparison as a 32-bit XOR)
+    issue = {kind: [ctx.measure_valu_issue(kind, k) for k in (1, 2, 3, 4)]
+             for kind in ("pk16", "b32", "cell", "cell_xor")}
     log("VALU issue probe (M instructions/s per SIMD, 1..4 waves): " +
         "; ".join(f"{k} " + " ".join(f"{r / 1e6:.0f}" for r in v) for k, v in issue.items()))
     launch_s = avg_kernel_ms / 1e3

@@ -226,12 +226,13 @@ class Context:
             raise WlcsError(st, "wlcs_measure_valu_peak", _load().wlcs_ctx_last_hip_error(self._h))
         return v.value
 
-    VALU_KINDS = {"pk16": 0, "b32": 1, "cell": 2}
+    VALU_KINDS = {"pk16": 0, "b32": 1, "cell": 2, "cell_xor": 3}
 
     def measure_valu_issue(self, kind: str, waves_per_simd: int, iters: int = 100000) -> float:
         """wlcs_measure_valu_issue: wave64 VALU instructions issued per second
         per SIMD with waves_per_simd (1..4) waves resident on every SIMD, for
-        one kind of stream ("pk16", "b32" or "cell"; a measurement helper)."""
+        one kind of stream ("pk16", "b32", "cell" or "cell_xor"; a measurement
+        helper)."""
         v = ctypes.c_double(0.0)
         st = _load().wlcs_measure_valu_issue(self._h, self.VALU_KINDS[kind], int(waves_per_simd), int(iters),
                                              ctypes.byref(v))

@@ -63,8 +63,25 @@ namespace {
                  : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)          \
                  : "v"(b))
 
+// The seaweed cell with Z formed by v_xor_b32 instead of v_pk_add_u16: x and
+// y codes equal for equal letters, x's code repeated in both halves of its own
+// register (a register per row instead of per two rows).  Probe only.
+__device__ __forceinline__ uint32_t xor_cell(uint32_t& s, uint32_t t, uint32_t xr, uint32_t y) {
+    uint32_t down;
+    asm volatile(
+        "v_xor_b32 %1, %3, %4\n\t"
+        "v_pk_min_u16 %1, %2, %1\n\t"
+        "v_pk_max_u16 %1, %0, %1\n\t"
+        "v_xor_b32 %0, %0, %2\n\t"
+        "v_xor_b32 %0, %0, %1"
+        : "+v"(s), "=&v"(down)
+        : "v"(t), "v"(xr), "s"(y));
+    return down;
+}
+
 // KIND 0: 16 v_pk_max_u16 per round, KIND 1: 16 v_xor_b32, KIND 2: eight
-// seaweed cells (40 instructions) down one column.
+// seaweed cells (40 instructions) down one column, KIND 3: the same with Z by
+// v_xor_b32 (xor_cell).
 template <int KIND>
 __global__ __launch_bounds__(1024) void valu_issue_kernel(uint32_t* __restrict__ out, int32_t iters) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,6 +95,18 @@ __global__ __launch_bounds__(1024) void valu_issue_kernel(uint32_t* __restrict__
         } else if constexpr (KIND == 1) {
             WLCS_ISSUE_ROUND("v_xor_b32");
             WLCS_ISSUE_ROUND("v_xor_b32");
+        } else if constexpr (KIND == 3) {
+            const uint32_t y = (uint32_t)__builtin_amdgcn_readfirstlane(i * 0x00010001);
+            uint32_t d = (uint32_t)__builtin_amdgcn_readfirstlane(i);
+            d = xor_cell(a0, d, b, y);
+            d = xor_cell(a1, d, t, y);
+            d = xor_cell(a2, d, b, y);
+            d = xor_cell(a3, d, t, y);
+            d = xor_cell(a4, d, b, y);
+            d = xor_cell(a5, d, t, y);
+            d = xor_cell(a6, d, b, y);
+            d = xor_cell(a7, d, t, y);
+            a0 ^= d & 1u;
         } else {
             // labels a0..a7 of eight rows, their letters in two registers,
             // the column's letter (uniform) and top label from the round
@@ -100,7 +129,7 @@ __global__ __launch_bounds__(1024) void valu_issue_kernel(uint32_t* __restrict__
 }  // namespace
 
 // blocks x (256 k) threads; wave64 VALU instructions per wave and round:
-// 16 (kinds 0, 1) or 40 (kind 2)
+// 16 (kinds 0, 1) or 40 (kinds 2, 3)
 hipError_t launch_valu_issue(uint32_t* out, int32_t kind, int32_t blocks, int32_t k, int32_t iters,
                              hipStream_t stream) {
     const dim3 grid((uint32_t)blocks), block((uint32_t)(256 * k));
@@ -108,8 +137,10 @@ hipError_t launch_valu_issue(uint32_t* out, int32_t kind, int32_t blocks, int32_
         hipLaunchKernelGGL(valu_issue_kernel<0>, grid, block, 0, stream, out, iters);
     else if (kind == 1)
         hipLaunchKernelGGL(valu_issue_kernel<1>, grid, block, 0, stream, out, iters);
-    else
+    else if (kind == 2)
         hipLaunchKernelGGL(valu_issue_kernel<2>, grid, block, 0, stream, out, iters);
+    else
+        hipLaunchKernelGGL(valu_issue_kernel<3>, grid, block, 0, stream, out, iters);
     return hipGetLastError();
 }
 
