@@ -154,8 +154,9 @@ def write_counters(prof_dir: str, workload: str, commands: list) -> str:
         name = max(plot, key=lambda d: d.get("SQ_INSTS_VALU", d.get("FETCH_SIZE", d.get("WRITE_SIZE", 0))))["name"]
         return [d for d in plot if d["name"] == name]
 
-    def copy_kernel(ds):  # the largest device copy of the run
-        return [max((d for d in ds if "copyBuffer" in d["name"]), key=lambda d: list(d.values())[-1])]
+    def copy_kernel(ds):  # the largest device copy of the run (the 1 GiB calibration copy)
+        return [max((d for d in ds if "copyBuffer" in d["name"]),
+                    key=lambda d: d.get("FETCH_SIZE", d.get("WRITE_SIZE", 0.0)))]
 
     fetch = dispatches("bytes_FETCH_SIZE", timed_kernel)
     write = dispatches("bytes_WRITE_SIZE", timed_kernel)
