@@ -27,9 +27,10 @@ TUNING_CACHE = os.path.join(ROOT, "paper_0909_2000_amd", "tuning_gfx950.json")
 FIXED_RATE = 1100.0  # serving: jobs/s of the fixed-rate latency point
 sys.path.insert(0, ROOT)
 
-# HIP events over the timed region; per-cell operation count of the method
-# (equality test, min, max and the two-way exchange of the seaweed cell)
-OPS_PER_CELL = 5
+# HIP events over the timed region; per-cell operation count of the seaweed
+# cell: the equality test, min, max and the exchange of the two labels (one
+# three-input XOR)
+OPS_PER_CELL = 4
 # MI355X: 256 CUs x 64 lanes x 2 packed 16-bit elements x 2.4 GHz
 PEAK_U16_OPS = 256 * 64 * 2 * 2.4e9
 METRIC = "window-cells/s (m*n*w/s) vs plain DP on same GPU; p50/p99 job latency"
@@ -78,7 +79,7 @@ def measured_traffic(workload: str, cells: float = 0.0):
     FETCH_SIZE / WRITE_SIZE runs, each scaled by what the same counter read for
     a plain 1 GiB device copy; None when the kernel sources changed since.
     The detail also carries the VALU counters of the same kernel: wave
-    instructions x 64 lanes per cell (5 instructions per two cells is 2.5),
+    instructions x 64 lanes per cell (4 instructions per two cells is 2.0),
     and, from the counter run's own launch time and GRBM_COUNT, the shader
     clock and the SIMD cycles per wave64 VALU instruction."""
     import hashlib
@@ -331,7 +332,7 @@ def main():
     # 32-bit streams and for the seaweed cell's own dependency chain (and the
     # same chain with the letter comparison as a 32-bit XOR)
     issue = {kind: [ctx.measure_valu_issue(kind, k) for k in (1, 2, 3, 4)]
-             for kind in ("pk16", "b32", "cell", "cell_xor")}
+             for kind in ("pk16", "b32", "bitop3", "cell", "cell_xor", "cell_two_xor")}
     log("VALU issue probe (M instructions/s per SIMD, 1..4 waves): " +
         "; ".join(f"{k} " + " ".join(f"{r / 1e6:.0f}" for r in v) for k, v in issue.items()))
     launch_s = avg_kernel_ms / 1e3

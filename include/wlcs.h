@@ -91,14 +91,17 @@ int wlcs_measure_valu_peak(wlcs_ctx *ctx, int32_t iters, double *ops_per_s);
 /* Measurement helper, not part of the method: wave64 VALU instructions issued
  * per second per SIMD (four per CU) with waves_per_simd (1..4) waves resident
  * on every SIMD, for one kind of instruction stream: 0 packed 16-bit
- * (v_pk_max_u16) and 1 plain 32-bit (v_xor_b32), each on eight independent
- * accumulators; 2 the seaweed cell down a column of eight rows (five
- * instructions per cell, three packed and two plain, each cell waiting for
- * the label of the cell above, as in the plot kernels); 3 the same chain with
- * the letter comparison done by v_xor_b32 on codes repeated in both halves
- * (two packed and three plain; not what the kernels run).  One workgroup of
- * 256 x waves_per_simd threads per CU runs iters (1..10^6) rounds of 16
- * (kinds 0, 1) or 40 (kinds 2, 3) instructions per wave, once to warm up (at most
+ * (v_pk_max_u16), 1 plain 32-bit (v_xor_b32) and 5 three-input bitwise
+ * (v_bitop3_b32), each on eight independent accumulators; 2 the seaweed cell
+ * down a column of eight rows (four instructions per cell, three packed and
+ * one v_bitop3_b32, each cell waiting for the label of the cell above, as in
+ * the plot kernels); 3 the same chain with the letter comparison done by
+ * v_xor_b32 on codes repeated in both halves (two packed, two plain; not what
+ * the kernels run); 4 the same chain with the right label formed by two
+ * v_xor_b32 (five instructions per cell; the cell's earlier form).  One
+ * workgroup of 256 x waves_per_simd threads per CU runs iters (1..10^6)
+ * rounds of 16 (kinds 0, 1, 5), 32 (kinds 2, 3) or 40 (kind 4) instructions
+ * per wave, once to warm up (at most
  * 1,000 rounds) and once timed with HIP events.  Synchronous, like
  * wlcs_measure_valu_peak.  WLCS_EINVAL for a null context or pointer or an
  * argument out of range (nothing runs). */

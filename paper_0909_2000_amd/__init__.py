@@ -226,7 +226,7 @@ class Context:
             raise WlcsError(st, "wlcs_measure_valu_peak", _load().wlcs_ctx_last_hip_error(self._h))
         return v.value
 
-    VALU_KINDS = {"pk16": 0, "b32": 1, "cell": 2, "cell_xor": 3}
+    VALU_KINDS = {"pk16": 0, "b32": 1, "cell": 2, "cell_xor": 3, "cell_two_xor": 4, "bitop3": 5}
 
     def measure_valu_issue(self, kind: str, waves_per_simd: int, iters: int = 100000) -> float:
         """wlcs_measure_valu_issue: wave64 VALU instructions issued per second

@@ -874,7 +874,7 @@ int wlcs_measure_valu_peak(wlcs_ctx* ctx, int32_t iters, double* ops_per_s) {
 
 int wlcs_measure_valu_issue(wlcs_ctx* ctx, int32_t kind, int32_t waves_per_simd, int32_t iters,
                             double* instr_per_s) {
-    if (!ctx || !instr_per_s || kind < 0 || kind > 3 || waves_per_simd < 1 || waves_per_simd > 4 || iters < 1 ||
+    if (!ctx || !instr_per_s || kind < 0 || kind > 5 || waves_per_simd < 1 || waves_per_simd > 4 || iters < 1 ||
         iters > 1000000)
         return WLCS_EINVAL;
     DeviceGuard guard(ctx->device);
@@ -896,7 +896,7 @@ int wlcs_measure_valu_issue(wlcs_ctx* ctx, int32_t kind, int32_t waves_per_simd,
     float ms = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
     if (e == hipSuccess && ms > 0.0f) {
-        const double per_round = kind >= 2 ? 40.0 : 16.0;
+        const double per_round = kind == 4 ? 40.0 : (kind == 2 || kind == 3) ? 32.0 : 16.0;
         // waves x rounds x instructions, over the device's SIMDs (four per CU)
         *instr_per_s = (double)blocks * 4.0 * k * (double)iters * per_round / (4.0 * ctx->cus) / (ms * 1e-3);
     }

@@ -1,6 +1,8 @@
 // Packed 16-bit helpers for gfx950: two independent lanes of work per VGPR,
 // on the VOP3P instructions (v_pk_add_u16, v_pk_sub_u16, v_pk_min_u16,
-// v_pk_max_u16, v_pk_lshlrev_b16).
+// v_pk_max_u16, v_pk_lshlrev_b16), and gfx950's three-input bitwise
+// v_bitop3_b32, whose 8-bit immediate is the truth table of the operation
+// (0x96: the XOR of all three operands).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -47,8 +49,9 @@ __device__ __forceinline__ uint32_t pk_add_bcast(uint32_t x, uint32_t y) {
 // One seaweed cell for two tiles at once (see seaweed.hip):
 //     z     = x_code (half HI of x, both lanes) + y_codes
 //     down  = max(s, min(t, z))
-//     s     = s ^ t ^ down          (the seaweed leaving to the right)
-// Written as one volatile block so that the five instructions stay together
+//     s     = s ^ t ^ down          (the seaweed leaving to the right: one
+//                                    v_bitop3_b32; down is s or t in each half)
+// Written as one volatile block so that the four instructions stay together
 // and the compiler cannot hoist the letter sums of a whole column into
 // registers ahead of time.  The y codes of a column are the same in every
 // lane, so they come from a scalar register.  Pure ALU, no memory access.
@@ -60,8 +63,7 @@ __device__ __forceinline__ uint32_t seaweed_cell(uint32_t& s, uint32_t t, uint32
             "v_pk_add_u16 %1, %3, %4 op_sel:[1,0]\n\t"
             "v_pk_min_u16 %1, %2, %1\n\t"
             "v_pk_max_u16 %1, %0, %1\n\t"
-            "v_xor_b32 %0, %0, %2\n\t"
-            "v_xor_b32 %0, %0, %1"
+            "v_bitop3_b32 %0, %0, %2, %1 bitop3:0x96"
             : "+v"(s), "=&v"(down)
             : "v"(t), "v"(x), "s"(y));
     else
@@ -69,8 +71,7 @@ __device__ __forceinline__ uint32_t seaweed_cell(uint32_t& s, uint32_t t, uint32
             "v_pk_add_u16 %1, %3, %4 op_sel_hi:[0,1]\n\t"
             "v_pk_min_u16 %1, %2, %1\n\t"
             "v_pk_max_u16 %1, %0, %1\n\t"
-            "v_xor_b32 %0, %0, %2\n\t"
-            "v_xor_b32 %0, %0, %1"
+            "v_bitop3_b32 %0, %0, %2, %1 bitop3:0x96"
             : "+v"(s), "=&v"(down)
             : "v"(t), "v"(x), "s"(y));
     return down;
@@ -83,8 +84,7 @@ __device__ __forceinline__ uint32_t seaweed_cell_top(uint32_t& s, uint32_t t, ui
         "v_pk_add_u16 %1, %3, %4 op_sel_hi:[0,1]\n\t"
         "v_pk_min_u16 %1, %2, %1\n\t"
         "v_pk_max_u16 %1, %0, %1\n\t"
-        "v_xor_b32 %0, %2, %0\n\t"
-        "v_xor_b32 %0, %0, %1"
+        "v_bitop3_b32 %0, %0, %2, %1 bitop3:0x96"
         : "+v"(s), "=&v"(down)
         : "s"(t), "v"(x), "s"(y));
     return down;
@@ -100,8 +100,8 @@ __device__ __forceinline__ uint32_t seaweed_cell_top(uint32_t& s, uint32_t t, ui
 //                      a = min(c, t), where c is the label the separator
 //                      column sent down from the slot above; its letter row is
 //                      the general cell:  z = x + y,  down = max(b, min(d, z)),
-//                      b = b ^ d ^ down,  t = down
-// Returns mx (the next slot's c).  Pure ALU.
+//                      b = b ^ d ^ down (one v_bitop3_b32),  t = down
+// Eight instructions per slot.  Returns mx (the next slot's c).  Pure ALU.
 #define WLCS_FUSED_SLOT_BODY(XSEL)                 \
     "v_pk_add_u16 %5, %7, %8 " XSEL "\n\t"       \
     "v_pk_max_u16 %3, %0, %1\n\t"                \
@@ -110,8 +110,7 @@ __device__ __forceinline__ uint32_t seaweed_cell_top(uint32_t& s, uint32_t t, ui
     "v_pk_min_u16 %0, %6, %2\n\t"                \
     "v_pk_min_u16 %5, %4, %5\n\t"                \
     "v_pk_max_u16 %2, %1, %5\n\t"                \
-    "v_xor_b32 %1, %1, %4\n\t"                   \
-    "v_xor_b32 %1, %1, %2"
+    "v_bitop3_b32 %1, %1, %4, %2 bitop3:0x96"
 template <int HI>
 __device__ __forceinline__ uint32_t fused_slot(uint32_t& a, uint32_t& b, uint32_t& t, uint32_t c, uint32_t x,
                                                uint32_t y) {
@@ -148,10 +147,8 @@ __device__ __forceinline__ uint32_t fused_slot(uint32_t& a, uint32_t& b, uint32_
     "v_pk_min_u16 %11, %10, %11\n\t"                \
     "v_pk_max_u16 %2, %1, %5\n\t"                   \
     "v_pk_max_u16 %8, %7, %11\n\t"                  \
-    "v_xor_b32 %1, %1, %4\n\t"                      \
-    "v_xor_b32 %7, %7, %10\n\t"                     \
-    "v_xor_b32 %1, %1, %2\n\t"                      \
-    "v_xor_b32 %7, %7, %8"
+    "v_bitop3_b32 %1, %1, %4, %2 bitop3:0x96\n\t"  \
+    "v_bitop3_b32 %7, %7, %10, %8 bitop3:0x96"
 #define WLCS_FUSED_SLOT2_OPS                                                                        \
     : "+v"(pa), "+v"(pb), "+v"(pt), "=&v"(pmx), "=&v"(pd), "=&v"(pz), "+v"(qa), "+v"(qb), "+v"(qt), \
       "=&v"(qmx), "=&v"(qd), "=&v"(qz)                                                               \

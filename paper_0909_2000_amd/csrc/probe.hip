@@ -9,10 +9,10 @@
 // The second helper measures the issue rate of wave64 VALU instructions with
 // a chosen number of waves resident on every SIMD: one workgroup of 256 k
 // threads per CU puts k waves on each of its four SIMDs at once.  Each wave
-// runs rounds of one kind of instruction stream: packed 16-bit or plain 32-bit
-// instructions on eight independent accumulators, or the seaweed cell down a
-// column of eight rows (each cell waits for the label the cell above sends
-// down, the dependency of the plot kernels).
+// runs rounds of one kind of instruction stream: packed 16-bit, plain 32-bit
+// or three-input bitwise instructions on eight independent accumulators, or
+// the seaweed cell down a column of eight rows (each cell waits for the label
+// the cell above sends down, the dependency of the plot kernels).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -63,6 +63,14 @@ namespace {
                  : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)          \
                  : "v"(b))
 
+#define WLCS_ISSUE_ROUND3(OP)                                                                        \
+    asm volatile(OP " %0, %0, %8, %9 bitop3:0x96\n\t" OP " %1, %1, %8, %9 bitop3:0x96\n\t"          \
+                 OP " %2, %2, %8, %9 bitop3:0x96\n\t" OP " %3, %3, %8, %9 bitop3:0x96\n\t"          \
+                 OP " %4, %4, %8, %9 bitop3:0x96\n\t" OP " %5, %5, %8, %9 bitop3:0x96\n\t"          \
+                 OP " %6, %6, %8, %9 bitop3:0x96\n\t" OP " %7, %7, %8, %9 bitop3:0x96"                \
+                 : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)          \
+                 : "v"(b), "v"(t))
+
 // The seaweed cell with Z formed by v_xor_b32 instead of v_pk_add_u16: x and
 // y codes equal for equal letters, x's code repeated in both halves of its own
 // register (a register per row instead of per two rows).  Probe only.
@@ -72,16 +80,42 @@ __device__ __forceinline__ uint32_t xor_cell(uint32_t& s, uint32_t t, uint32_t x
         "v_xor_b32 %1, %3, %4\n\t"
         "v_pk_min_u16 %1, %2, %1\n\t"
         "v_pk_max_u16 %1, %0, %1\n\t"
-        "v_xor_b32 %0, %0, %2\n\t"
-        "v_xor_b32 %0, %0, %1"
+        "v_bitop3_b32 %0, %0, %2, %1 bitop3:0x96"
         : "+v"(s), "=&v"(down)
         : "v"(t), "v"(xr), "s"(y));
     return down;
 }
 
+// The seaweed cell as first written, its right label by two v_xor_b32 (five
+// instructions).  Probe only.
+template <int HI>
+__device__ __forceinline__ uint32_t two_xor_cell(uint32_t& s, uint32_t t, uint32_t x, uint32_t y) {
+    uint32_t down;
+    if (HI)
+        asm volatile(
+            "v_pk_add_u16 %1, %3, %4 op_sel:[1,0]\n\t"
+            "v_pk_min_u16 %1, %2, %1\n\t"
+            "v_pk_max_u16 %1, %0, %1\n\t"
+            "v_xor_b32 %0, %0, %2\n\t"
+            "v_xor_b32 %0, %0, %1"
+            : "+v"(s), "=&v"(down)
+            : "v"(t), "v"(x), "s"(y));
+    else
+        asm volatile(
+            "v_pk_add_u16 %1, %3, %4 op_sel_hi:[0,1]\n\t"
+            "v_pk_min_u16 %1, %2, %1\n\t"
+            "v_pk_max_u16 %1, %0, %1\n\t"
+            "v_xor_b32 %0, %0, %2\n\t"
+            "v_xor_b32 %0, %0, %1"
+            : "+v"(s), "=&v"(down)
+            : "v"(t), "v"(x), "s"(y));
+    return down;
+}
+
 // KIND 0: 16 v_pk_max_u16 per round, KIND 1: 16 v_xor_b32, KIND 2: eight
-// seaweed cells (40 instructions) down one column, KIND 3: the same with Z by
-// v_xor_b32 (xor_cell).
+// seaweed cells (32 instructions) down one column, KIND 3: the same with Z by
+// v_xor_b32 (xor_cell, 32), KIND 4: the same with two_xor_cell (40), KIND 5:
+// 16 v_bitop3_b32.
 template <int KIND>
 __global__ __launch_bounds__(1024) void valu_issue_kernel(uint32_t* __restrict__ out, int32_t iters) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -95,6 +129,21 @@ __global__ __launch_bounds__(1024) void valu_issue_kernel(uint32_t* __restrict__
         } else if constexpr (KIND == 1) {
             WLCS_ISSUE_ROUND("v_xor_b32");
             WLCS_ISSUE_ROUND("v_xor_b32");
+        } else if constexpr (KIND == 5) {
+            WLCS_ISSUE_ROUND3("v_bitop3_b32");
+            WLCS_ISSUE_ROUND3("v_bitop3_b32");
+        } else if constexpr (KIND == 4) {
+            const uint32_t y = (uint32_t)__builtin_amdgcn_readfirstlane(i * 0x00010001);
+            uint32_t d = (uint32_t)__builtin_amdgcn_readfirstlane(i);
+            d = two_xor_cell<0>(a0, d, b, y);
+            d = two_xor_cell<1>(a1, d, b, y);
+            d = two_xor_cell<0>(a2, d, t, y);
+            d = two_xor_cell<1>(a3, d, t, y);
+            d = two_xor_cell<0>(a4, d, b, y);
+            d = two_xor_cell<1>(a5, d, b, y);
+            d = two_xor_cell<0>(a6, d, t, y);
+            d = two_xor_cell<1>(a7, d, t, y);
+            a0 ^= d & 1u;
         } else if constexpr (KIND == 3) {
             const uint32_t y = (uint32_t)__builtin_amdgcn_readfirstlane(i * 0x00010001);
             uint32_t d = (uint32_t)__builtin_amdgcn_readfirstlane(i);
@@ -125,11 +174,12 @@ __global__ __launch_bounds__(1024) void valu_issue_kernel(uint32_t* __restrict__
     out[t] = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
 }
 #undef WLCS_ISSUE_ROUND
+#undef WLCS_ISSUE_ROUND3
 
 }  // namespace
 
 // blocks x (256 k) threads; wave64 VALU instructions per wave and round:
-// 16 (kinds 0, 1) or 40 (kinds 2, 3)
+// 16 (kinds 0, 1, 5), 32 (kinds 2, 3) or 40 (kind 4)
 hipError_t launch_valu_issue(uint32_t* out, int32_t kind, int32_t blocks, int32_t k, int32_t iters,
                              hipStream_t stream) {
     const dim3 grid((uint32_t)blocks), block((uint32_t)(256 * k));
@@ -139,8 +189,12 @@ hipError_t launch_valu_issue(uint32_t* out, int32_t kind, int32_t blocks, int32_
         hipLaunchKernelGGL(valu_issue_kernel<1>, grid, block, 0, stream, out, iters);
     else if (kind == 2)
         hipLaunchKernelGGL(valu_issue_kernel<2>, grid, block, 0, stream, out, iters);
-    else
+    else if (kind == 3)
         hipLaunchKernelGGL(valu_issue_kernel<3>, grid, block, 0, stream, out, iters);
+    else if (kind == 4)
+        hipLaunchKernelGGL(valu_issue_kernel<4>, grid, block, 0, stream, out, iters);
+    else
+        hipLaunchKernelGGL(valu_issue_kernel<5>, grid, block, 0, stream, out, iters);
     return hipGetLastError();
 }
 

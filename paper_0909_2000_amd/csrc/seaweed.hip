@@ -22,10 +22,11 @@
 //  * two tiles per lane: each 32-bit register holds two 16-bit labels, the
 //    low half for tile A of the strip and the high half for tile B (a
 //    disjoint y range), so every instruction of the cell advances two cells.
-//  * the cell in five packed operations: Z = f(x) + g(y) is 0 on a match and
+//  * the cell in four instructions: Z = f(x) + g(y) is 0 on a match and
 //    >= 1024 on a mismatch (letter codes of kernels.hpp), labels are < 1024,
 //        down  = max(s, min(t, Z))          (match: s; mismatch: max(s, t))
-//        right = s ^ t ^ down               (the other of the two)
+//        right = s ^ t ^ down               (the other of the two, in one
+//                                            three-input v_bitop3_b32)
 //    The x code of a row is read from one half of a shared register through
 //    the op_sel modifiers of v_pk_add_u16.
 //  * labels are start columns relative to a moving origin and are clamped at

@@ -231,12 +231,12 @@ def test_valu_issue_probe(lib, ctx):
     for each kind of stream and one to four waves per SIMD, between one per
     24 cycles and one per cycle of a 2.4 GHz clock; its argument checks."""
     import ctypes
-    for kind in ("pk16", "b32", "cell", "cell_xor"):
+    for kind in ("pk16", "b32", "bitop3", "cell", "cell_xor", "cell_two_xor"):
         rates = [ctx.measure_valu_issue(kind, k, 20000) for k in (1, 2, 3, 4)]
         _say(f"VALU issue {kind}: " + ", ".join(f"{r / 1e6:.0f} M/s" for r in rates))
         assert all(1e8 < r < 2.4e9 for r in rates), (kind, rates)
     v = ctypes.c_double(0.0)
-    for kind, k, iters in ((4, 1, 100), (-1, 1, 100), (0, 0, 100), (0, 5, 100), (0, 1, 0), (0, 1, 2_000_000)):
+    for kind, k, iters in ((6, 1, 100), (-1, 1, 100), (0, 0, 100), (0, 5, 100), (0, 1, 0), (0, 1, 2_000_000)):
         assert lib._load().wlcs_measure_valu_issue(ctx.handle, kind, k, iters, ctypes.byref(v)) == -1
     assert lib._load().wlcs_measure_valu_issue(ctx.handle, 0, 1, 10, None) == -1
 
