@@ -209,6 +209,16 @@ __device__ __forceinline__ uint32_t pk_below(uint32_t w2, uint32_t p2, uint32_t 
     return v;
 }
 
+// Per half: 1 if a > b (unsigned), else 0 -- min(sat(a - b), 1).  b is
+// wave-uniform and is read from a scalar register.
+__device__ __forceinline__ uint32_t pk_above(uint32_t a2, uint32_t b2, uint32_t one2) {
+    uint32_t v;
+    asm("v_pk_sub_u16 %0, %1, %2 clamp\n\tv_pk_min_u16 %0, %0, %3"
+        : "=&v"(v)
+        : "v"(a2), "s"(__builtin_amdgcn_readfirstlane(b2)), "v"(one2));
+    return v;
+}
+
 // Per half: a >> 1.
 __device__ __forceinline__ uint32_t pk_shr1(uint32_t a) {
     return as_u(as_v(a) >> (u16x2){(unsigned short)1, (unsigned short)1});

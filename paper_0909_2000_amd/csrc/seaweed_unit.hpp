@@ -21,6 +21,22 @@ __device__ __forceinline__ uint32_t sub_bytes(uint32_t x, uint32_t b4) {
     const uint32_t H = 0x80808080u;
     return ((x | H) - b4) ^ ((x ^ ~b4) & H);
 }
+// One 32-bit word of a strip's bitmap: bit b is set iff byte b % 4 of
+// d[b / 4] is at least the threshold T, for bytes below 128.  k4 holds
+// 128 - T (T clamped to [0, 128]) in every byte: v + 128 - T keeps bit 7 iff
+// v >= T, with no carry between the bytes.  v_dot4_u32_u8 weighs the four
+// bit-7 flags of a dword by 1, 2, 4, 8 (16 .. 128 for the second dword of an
+// eight-window chunk), which gives 128 times a byte of the word.
+__device__ __forceinline__ uint32_t bitmap_word(const uint32_t* d, uint32_t k4) {
+    auto chunk = [&](int i, uint32_t acc) -> uint32_t {  // 128 x windows 8i .. 8i + 7, plus acc
+        const uint32_t a = (d[2 * i] + k4) & 0x80808080u, b = (d[2 * i + 1] + k4) & 0x80808080u;
+        return __builtin_amdgcn_udot4(b, 0x80402010u, __builtin_amdgcn_udot4(a, 0x08040201u, acc, false), false);
+    };
+    const uint32_t lo = chunk(0, chunk(1, 0u) << 8);  // 128 x bits 0..15
+    const uint32_t hi = chunk(2, chunk(3, 0u) << 8);  // 128 x bits 16..31
+    return (lo >> 7) | (hi << 9);
+}
+
 // LDS ring words (16 start columns each) per lane: the ring must cover the
 // w + 1 start columns that can be pending at once, with a margin that keeps
 // the word being cleared apart from the newest marks.
@@ -293,16 +309,23 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
             f2 = (ring_pf >> (pc & 15)) & 0x00010001u;
             if ((pc & 15) == 15) ring_lane[((pc >> 4) & (RW - 1)) * 64] = 0;
         }
-        // p = start - (l - w + 1) lies in [0, w) iff the exit's span is below w
-        const uint32_t p2 = pk_sub(t, pk_rep(l - org + 2 - w));
-        const uint32_t v2 = pk_below(w2, p2, one2);
+        uint32_t p2 = 0, v2;
+        if constexpr (RMASK) {
+            // p = start - (l - w + 1) lies in [0, w) iff the exit's span is below w
+            p2 = pk_sub(t, pk_rep(l - org + 2 - w));
+            v2 = pk_below(w2, p2, one2);
+        } else {
+            // the same test on the label: the exit's seaweed started in the
+            // window iff t >= label(l - w + 1) = l - w + 2 - org (>= 2 here)
+            v2 = pk_above(t, pk_rep(l - w + 1 - org), one2);
+        }
         if constexpr (RMASK && WC <= 16) {
             m2 = pk_shr1(m2) | pk_lshl(p2, v2);  // p < w <= 16 wherever v = 1
         } else if constexpr (RMASK) {
             mA = (mA >> 1) | ((v2 & 0xFFFFu) << (p2 & 31u));  // p < w <= 32 wherever v = 1
             mB = (mB >> 1) | ((v2 >> 16) << ((p2 >> 16) & 31u));
         } else {
-            const uint32_t pos2 = pk_add(p2, pk_rep(l - w + 1));
+            const uint32_t pos2 = pk_add(t, pk_rep(org - 1));  // the start column: label + org - 1
             const uint32_t bit2 = pk_lshl(pos2, v2);
             // ring word of each mark: bits 4.. of its start column
             const uint32_t wlo = bfe<4, RB>(pos2), whi = bfe<20, RB>(pos2);
@@ -558,16 +581,23 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                 }
             }
             if (bm32 && s < g.rows) {
+                const int kt = 128 - g.threshold;
+                const uint32_t k4 = (uint32_t)(kt < 0 ? 0 : kt > 128 ? 128 : kt) * 0x01010101u;
 #pragma unroll
                 for (int sub = 0; sub < FO / 32; ++sub) {
                     const uint32_t wi = (uint32_t)(o0 >> 5) + sub;
                     if (wi < bm_words) {
                         const int nv = nvalid - 32 * sub;
                         uint32_t bits = 0;
+                        if constexpr (WC <= 64) {  // values at most 64
+                            bits = bitmap_word(d + 8 * sub, k4);
+                        } else {
 #pragma unroll
-                        for (int b = 0; b < 32; ++b)
-                            bits |= (uint32_t)((int)((d[8 * sub + (b >> 2)] >> (8 * (b & 3))) & 0xFFu) >= g.threshold)
-                                    << b;
+                            for (int b = 0; b < 32; ++b)
+                                bits |= (uint32_t)((int)((d[8 * sub + (b >> 2)] >> (8 * (b & 3))) & 0xFFu) >=
+                                                   g.threshold)
+                                        << b;
+                        }
                         if (nv < 32) bits &= nv > 0 ? (0xFFFFFFFFu >> (32 - nv)) : 0u;
                         bm32[s * g.ld_words32 + wi] = bits;
                     }
