@@ -305,6 +305,30 @@ def test_epilogues(ctx, oracle_mod, w, thr):
         np.testing.assert_array_equal(_cpu(res2["indel"]).view(np.uint16), oracle_mod.indel(want, w))
 
 
+@pytest.mark.parametrize("w", [16, 32, 40, 64])
+def test_bitmap_threshold_extremes(ctx, oracle_mod, w):
+    """Bitmap words built from byte flags (windows of at most 64 letters):
+    thresholds at both ends of 0..255 and on either side of the largest value
+    w, for classes filled exactly (16, 32, 64) and padded (40 in the 64-row
+    class), on two strip blocks (the second ragged) and rows whose last word is
+    partial; y holds mutated copies of x windows so values near w occur."""
+    g = workloads.rng(4700 + w)
+    x = workloads.iid(g, w + 70, workloads.DNA)
+    y = workloads.iid(g, w + 301, workloads.DNA)
+    for k, ys in enumerate((40, 150, 260)):  # one exact copy, two mutated
+        seg = x[20 * k:20 * k + w].copy()
+        hit = g.random(w) < 0.05 * k
+        seg[hit] = workloads.iid(g, int(hit.sum()), workloads.DNA)
+        y[ys:ys + w] = seg
+    want = oracle_mod.wlcs(x, y, w)
+    assert want.max() == w and (want == w - 1).any() and want.shape[1] % 64 != 0
+    for thr in (0, 1, w // 2, w - 1, w, w + 1, 127, 128, 129, 255):
+        _say(f"bitmap thresholds w={w} thr={thr}")
+        res = ctx.plot(x, y, w, threshold=thr)
+        np.testing.assert_array_equal(_cpu(res["wlcs"]), want)
+        np.testing.assert_array_equal(_bitmap_u64(res["bitmap"]), oracle_mod.dot_bitmap(want, thr))
+
+
 def test_bitmap_padding_words(ctx, oracle_mod):
     # cols not a multiple of 64: padding bits of the last word must be 0
     import torch
