@@ -1163,11 +1163,7 @@ int wlcs_pair_dots_filtered(wlcs_ctx* ctx, const wlcs_pair* pair, int32_t w, int
         f.dot_cap = dots ? dot_cap : 0;
         f.dot_count = (unsigned long long*)dot_count;
         f.fallback = fallback;
-        // sixteen single-wave workgroups per CU (four per SIMD where the
-        // letter masks fit the LDS): a candidate's steps wait on LDS and on
-        // each other, and one wave per SIMD left the VALU idle four cycles
-        // in five
-        f.grid = 16 * ctx->cus;
+        f.cus = ctx->cus;
         e = wlcs::launch_candidates(f, stream);
     }
     if (e == hipSuccess) {

@@ -24,6 +24,8 @@
 // If the probe entries exceed the probe list, the kernel lists nothing and
 // raises a flag instead; a gated launch of the plain dot list over every strip
 // (which returns at once unless the flag is up) then gives the exact list.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "packed.hpp"
 
@@ -161,6 +163,12 @@ __global__ __launch_bounds__(64) void candidates_kernel(const uint16_t* __restri
     }
 }
 
+// The grid: every single-wave workgroup that fits on the device at once (the
+// letter masks take sigma x NW words of LDS per lane, the registers allow up
+// to eight waves per SIMD), at most 32 per CU.  A candidate's steps wait on
+// LDS and on each other: with one wave per SIMD the VALU stood idle four
+// cycles in five.  The entries are split evenly over the grid, so no
+// workgroup of it may wait for another to finish.
 template <int NW>
 hipError_t candidates_nw(const FilterArgs& f, hipStream_t stream) {
     const size_t lds = (size_t)f.sigma * NW * 64 * sizeof(uint32_t);  // <= 63 * 8 * 256 bytes
@@ -169,7 +177,12 @@ hipError_t candidates_nw(const FilterArgs& f, hipStream_t stream) {
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((candidates_kernel<NW>), dim3((uint32_t)f.grid), dim3(64), lds, stream, f.xf,
+    int per_cu = 0;
+    const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)candidates_kernel<NW>, 64, lds);
+    if (e != hipSuccess) return e;
+    const int64_t grid = (int64_t)std::max(1, std::min(per_cu, 32)) * f.cus;
+    hipLaunchKernelGGL((candidates_kernel<NW>), dim3((uint32_t)grid), dim3(64), lds, stream, f.xf,
                        (const uint32_t*)f.yg, f.probe, f.probe_cap, f.probe_count, f.rows, f.first, f.w, f.sigma, f.h,
                        f.threshold, f.dots, f.dot_cap, f.dot_count, f.fallback);
     return hipGetLastError();
@@ -178,7 +191,7 @@ hipError_t candidates_nw(const FilterArgs& f, hipStream_t stream) {
 }  // namespace
 
 hipError_t launch_candidates(const FilterArgs& f, hipStream_t stream) {
-    if (f.grid <= 0) return hipSuccess;
+    if (f.cus <= 0) return hipSuccess;
     switch ((f.w + 31) / 32) {
         case 1: return candidates_nw<1>(f, stream);
         case 2: return candidates_nw<2>(f, stream);

@@ -240,7 +240,8 @@ struct FilterArgs {
     int64_t dot_cap;
     unsigned long long* dot_count;
     uint32_t* fallback;
-    int32_t grid;        // workgroups of 64 lanes (the kernel strides over the entries)
+    int32_t cus;         // CUs of the device: the grid is every workgroup of 64 lanes that fits on them at
+                         // once, at most 32 per CU (the kernel strides over the entries)
 };
 hipError_t launch_candidates(const FilterArgs& f, hipStream_t stream);
 
