@@ -72,24 +72,28 @@ int64_t n_windows(int64_t len, int32_t w, bool full) {
 // 32-window flush and 3 at 12.8 KB for the 64-window one).  A score-plot
 // class that splits a strip over two waves counts one unit per SIMD: its
 // waves fit 2 or 3 per SIMD, but the tilings measured fastest on the GPU are
-// the ones the model picks with one.
-double units_per_simd(int wc, int ws) {
+// the ones the model picks with one.  The 256-row class chains four waves per
+// unit at three waves per SIMD: 0.75 units per SIMD, which puts the model's
+// choices next to the tilings measured fastest (wlcs_tune_plot) on 30,000 x
+// 30,000 protein plots.
+double units_per_simd(int wc, int ws, int w) {
     if (ws == 2) {  // score plots: the separator schedule, classes of 8 rows
         const int dc = (wc + 7) / 8 * 8;
         return wlcs::dl_split(dc) ? 1.0 : (double)wlcs::min_waves_per_simd_dl(dc);
     }
+    if (wc == 256) return 3.0 / wlcs::kWideWaves;
     const int regs = wc <= 32 ? 4 : wc == 64 ? 3 : wc == 128 ? 2 : 1;
     const int lds = wc >= 64 ? 3 : 4;
     return std::min(regs, lds);
 }
 
 // Units (workgroups) that fit on one CU at once.
-int units_per_cu(int wc, int ws) {
+int units_per_cu(int wc, int ws, int w) {
     if (ws == 2) {
         const int dc = (wc + 7) / 8 * 8;
         return wlcs::dl_split(dc) ? 4 * wlcs::min_waves_per_simd_dl_split(dc) / 2 : 4 * wlcs::min_waves_per_simd_dl(dc);
     }
-    return 4 * (int)units_per_simd(wc, ws);
+    return (int)(4 * units_per_simd(wc, ws, w));
 }
 
 // Tile pairs of a row of cols windows with long tiles of `tile` windows for
@@ -190,14 +194,14 @@ void choose_tiles(wlcs_ctx* ctx, wlcs::PlotArgs& a, int64_t rows, int64_t cols, 
     static const int32_t cand[] = {64, 128, 192, 256, 384, 512, 768, 1024, 1280, 1536, 2048, 2560, 3072, 4096, 6144, 8192, 12288, 16384};
     const int64_t nblocks = (rows + 63) / 64;
     const int wcl = ws == 2 ? w : wlcs::w_class(w);
-    const int64_t slots = (int64_t)(4.0 * ctx->cus * units_per_simd(wcl, ws));
+    const int64_t slots = (int64_t)(4.0 * ctx->cus * units_per_simd(wcl, ws, w));
     // long tiles only with about as many long units as fit on the GPU at once
     // (at least 85%): then every CU starts (nearly) full of long units,
     // whichever CUs the units land on.  With far fewer, some CUs can end up
     // with several long units and others with none, and the launch waits for
     // the former (measured: 64% of the resident units gave launches of either
     // 4.4 or 5.7 ms; 91-92% gave steady times).
-    const int64_t resident = (int64_t)ctx->cus * units_per_cu(wcl, ws);
+    const int64_t resident = (int64_t)ctx->cus * units_per_cu(wcl, ws, w);
     const int64_t cap = std::max<int64_t>(64, (cols + 63) / 64 * 64);
     int64_t best_t = INT64_MAX;
     wlcs::PlotArgs best = a;

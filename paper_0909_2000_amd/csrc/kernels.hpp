@@ -174,6 +174,26 @@ constexpr int kDlHandDwords = 2 * 4 * 64;
 // slower than one wave holding the whole strip.)
 constexpr bool general_split(int wc) { return wc == 128; }
 constexpr int min_waves_per_simd_split(int wc) { return wc <= 128 ? 3 : 2; }
+// Plots in the 256-row class (windows of 129..255 letters) chain four waves
+// down every strip, each holding at most 64 rows (one wave holding the strip
+// needs its labels in accumulation registers, at one wave per SIMD; chains of
+// three waves measured slower and less steady from run to run).  The strip
+// is padded at the top to wpad = w rounded up to 8 rows, and its rows are
+// dealt out to the waves in blocks of 8, the earlier waves taking the extra
+// blocks (the last wave also counts and stores): every wave gets 32 to 64
+// rows.
+constexpr int kWideWaves = 4;
+constexpr int kWideRowsPerWave = 64;
+constexpr int kWideRowBlock = 8;
+constexpr int kWideMinRows = 32;
+__host__ __device__ constexpr int wide_pad_rows(int w) { return (w + kWideRowBlock - 1) / kWideRowBlock * kWideRowBlock; }
+// rows [*r0, *r0 + *nr) of the padded strip go to wave q (0-based) of the chain
+__host__ __device__ inline void wide_rows(int w, int q, int* r0, int* nr) {
+    const int blocks = wide_pad_rows(w) / kWideRowBlock;
+    const int base = blocks / kWideWaves, extra = blocks % kWideWaves;
+    *r0 = kWideRowBlock * (q * base + (q < extra ? q : extra));
+    *nr = kWideRowBlock * (base + (q < extra ? 1 : 0));
+}
 
 // Window capacity class of a window length: 16, 32, 64, 128 or 256.
 inline int w_class(int w) { return w <= 16 ? 16 : w <= 32 ? 32 : w <= 64 ? 64 : w <= 128 ? 128 : 256; }

@@ -130,6 +130,44 @@ __global__ __launch_bounds__(128, min_waves_per_simd_split(WC)) void seaweed_ker
                                                hand);
 }
 
+// Plots in the 256-row class: a chain of kWideWaves waves per strip
+// (wide_rows), one unit per workgroup.
+template <bool SP>
+__global__ __launch_bounds__(64 * kWideWaves, 3) void seaweed_kernel_wide(
+    const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32, uint8_t* __restrict__ out,
+    uint32_t* __restrict__ bm32, uint16_t* __restrict__ indel, DotRec* __restrict__ dots,
+    unsigned long long* __restrict__ dot_count, Geom g, const uint32_t* __restrict__ gate) {
+    static_assert(kWideWaves == 4, "one case per wave of the chain");
+    if constexpr (SP) {
+        if (gate && *gate == 0u) return;
+    }
+    __shared__ uint32_t ring[ring_words(256) * 64];
+    __shared__ uint32_t stage[stage_dwords(256, 1)];
+    __shared__ uint32_t hand[(kWideWaves - 1) * kDlHandDwords];
+    const int64_t nblocks = (g.rows + 63) / 64;
+    const int64_t unit = blockIdx.x;
+    const int pr = (int)(unit / nblocks);
+    const int64_t sb = unit - (int64_t)pr * nblocks;
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+        case 0:
+            comb_unit<256, false, 1, SP, false, 1, kWideWaves>(xf, yg32, out, bm32, indel, dots, dot_count, g, sb, pr,
+                                                               ring, stage, hand);
+            break;
+        case 1:
+            comb_unit<256, false, 1, SP, false, 2, kWideWaves>(xf, yg32, out, bm32, indel, dots, dot_count, g, sb, pr,
+                                                               ring, stage, hand);
+            break;
+        case 2:
+            comb_unit<256, false, 1, SP, false, 3, kWideWaves>(xf, yg32, out, bm32, indel, dots, dot_count, g, sb, pr,
+                                                               ring, stage, hand);
+            break;
+        default:
+            comb_unit<256, false, 1, SP, false, 4, kWideWaves>(xf, yg32, out, bm32, indel, dots, dot_count, g, sb, pr,
+                                                               ring, stage, hand);
+            break;
+    }
+}
+
 __global__ void zero_u64(unsigned long long* p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
 }
@@ -137,7 +175,10 @@ __global__ void zero_u64(unsigned long long* p) {
 template <int WC, int WS, bool SP>
 void launch_ws(const PlotArgs& a, const Geom& g, uint32_t units, hipStream_t stream) {
     const uint32_t* yg32 = (const uint32_t*)a.yg;
-    if constexpr (WS == 1 && general_split(WC)) {
+    if constexpr (WS == 1 && WC == 256) {
+        hipLaunchKernelGGL((seaweed_kernel_wide<SP>), dim3(units), dim3(64 * kWideWaves), 0, stream, a.xf, yg32,
+                           a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g, a.gate);
+    } else if constexpr (WS == 1 && general_split(WC)) {
         if (a.w == WC)
             hipLaunchKernelGGL((seaweed_kernel_rsplit<WC, true, SP>), dim3(units), dim3(128), 0, stream, a.xf, yg32,
                                a.wlcs, a.bitmap32, a.indel, a.dots, a.dot_count, g, a.gate);

@@ -184,7 +184,12 @@ __device__ __forceinline__ void list_dots(DotRec* __restrict__ dots, unsigned lo
 // lower rows one group behind, counts and stores.  Both waves meet at one
 // workgroup barrier per group (the upper after writing, the lower before
 // reading), and the same sequence of groups in both makes the barriers match.
-template <int WC, bool EXACT, int WS = 1, bool SP = false, bool DL = false, int PART = 0>
+// NPART > 2 (the 256-row class, see wide_rows): a chain of NPART waves, wave
+// PART taking its rows of the strip from the one above through its own pair
+// of hand-over buffers, PART - 1 groups behind the first; every wave ends each
+// group with the workgroup barrier, after PART - 1 barriers before its first
+// group and NPART - PART after its last, so the counts match.
+template <int WC, bool EXACT, int WS = 1, bool SP = false, bool DL = false, int PART = 0, int NPART = 2>
 __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const uint32_t* __restrict__ yg32,
                                           uint8_t* __restrict__ out, uint32_t* __restrict__ bm32,
                                           uint16_t* __restrict__ indel, DotRec* __restrict__ dots,
@@ -193,9 +198,13 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                                           uint32_t* __restrict__ hand = nullptr) {
     static_assert(!SP || WS == 1, "strided and sparse plots store single windows");
     static_assert(!DL || (WS == 2 && !EXACT && WC % (2 * kDlSlots) == 0), "the score-plot schedule");
-    static_assert(PART == 0 || (DL ? dl_split(WC) : (WS == 1 && general_split(WC))),
+    // the chain of waves of the 256-row class
+    constexpr bool WIDE = !DL && PART != 0 && NPART > 2;
+    static_assert(PART == 0 || (DL ? dl_split(WC) : (WS == 1 && (general_split(WC) || WIDE))),
                   "two waves per strip: score plots above kDlSplitRows rows, other plots of 128 rows");
-    constexpr bool UPPER = PART == 1;  // combs only: no count, no stores
+    static_assert(!WIDE || (WC == 256 && !EXACT && PART <= NPART && NPART == kWideWaves), "the 256-row chain");
+    static_assert(NPART == 2 || WIDE, "a chain of more than two waves is the 256-row class");
+    constexpr bool UPPER = PART != 0 && PART < NPART;  // combs only: no count, no stores
     constexpr int RW = ring_words(WC);
     constexpr int FL = flush_windows(WC, WS);
     constexpr int PITCH = stage_pitch(WC, WS);
@@ -214,7 +223,7 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     // straight down -- the padded strip has the same exits as the strip of
     // height w.  Rows from wpad on are skipped 16 at a time by one uniform
     // branch, so no cell carries a test of its own.
-    const int pad = (EXACT || DL) ? 0 : ((w + 15) & ~15) - w;
+    const int pad = (EXACT || DL) ? 0 : (WIDE ? wide_pad_rows(w) : (w + 15) & ~15) - w;
     const int wpad = (EXACT || DL) ? WC : w + pad;
     constexpr int NP = WC / 2;                 // DL: pair slots
     const int ppad = DL ? NP - w / 2 : 0;      // DL: unused slots at the top (< kDlSlots)
@@ -222,10 +231,14 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     constexpr int S0 = (DL && PART == 2) ? dl_upper_slots(WC) : 0;
     constexpr int NS = (!DL || PART == 0) ? NP : PART == 1 ? dl_upper_slots(WC) : NP - dl_upper_slots(WC);
     static_assert(!DL || (NS % 2 == 0 && S0 >= (PART == 2 ? kDlSlots : 0)), "slot split");
-    // general: this wave's rows, R0 .. R0 + NR - 1 of the strip
-    constexpr int R0 = (!DL && PART == 2) ? WC / 2 : 0;
-    constexpr int NR = (DL || PART == 0) ? WC : WC / 2;
+    // general: this wave's rows, R0 .. R0 + NR - 1 of the strip (WIDE: NR
+    // is the capacity, the wave's rows are r0 .. r0 + nrw - 1)
+    constexpr int R0 = (!DL && !WIDE && PART == 2) ? WC / 2 : 0;
+    constexpr int NR = WIDE ? kWideRowsPerWave : (DL || PART == 0) ? WC : WC / 2;
     constexpr int HN = DL ? 2 * NS : NR;       // labels held by this wave
+    int r0 = R0, nrw = NR;
+    if constexpr (WIDE) wide_rows(w, PART - 1, &r0, &nrw);
+    constexpr bool TOP = PART <= 1;            // this wave holds row 0 of the strip
     // x letters of this lane's strip, two rows per register (lanes past the
     // last strip comb a copy of the last one; their results are never stored);
     // DL: the letters of this wave's letter rows only, two slots per register
@@ -243,7 +256,7 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                 lo = i0 >= 0 ? (uint32_t)xp[2 * i0 + 1] : PADF;
                 hi = i1 >= 0 ? (uint32_t)xp[2 * i1 + 1] : PADF;
             } else {
-                const int i0 = R0 + 2 * j - pad, i1 = R0 + 2 * j + 1 - pad;
+                const int i0 = r0 + 2 * j - pad, i1 = r0 + 2 * j + 1 - pad;
                 lo = (EXACT || i0 >= 0) ? (uint32_t)xp[EXACT ? R0 + 2 * j : i0] : PADF;
                 hi = (EXACT || i1 >= 0) ? (uint32_t)xp[EXACT ? R0 + 2 * j + 1 : i1] : PADF;
             }
@@ -347,10 +360,15 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         const uint32_t Y = ynext;
         ynext = yload(l + 1);
         uint32_t t = t_in;
-        if constexpr (R0 == 0) t = seaweed_cell_top(h[0], pk_rep(l - org + 1), xc[0], Y);
+        if constexpr (TOP) t = seaweed_cell_top(h[0], pk_rep(l - org + 1), xc[0], Y);
 #pragma unroll
-        for (int k = R0 == 0 ? 1 : 0; k < NR; ++k) {
-            if (!EXACT && ((R0 + k) & 15) == 0 && R0 + k >= wpad) break;  // uniform, once per 16 rows
+        for (int k = TOP ? 1 : 0; k < NR; ++k) {
+            if constexpr (WIDE) {
+                // uniform, once per block of rows past the fewest a wave holds
+                if (k >= kWideMinRows && (k % kWideRowBlock) == 0 && k >= nrw) break;
+            } else {
+                if (!EXACT && ((R0 + k) & 15) == 0 && R0 + k >= wpad) break;  // uniform, once per 16 rows
+            }
             t = (k & 1) ? seaweed_cell<1>(h[k], t, xc[k >> 1], Y) : seaweed_cell<0>(h[k], t, xc[k >> 1], Y);
         }
         return t;
@@ -365,7 +383,29 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     // unrolls and puts the label arrays in scratch memory.)
     int hand_buf_g = 0;
     auto group = [&](int l0, int n, uint32_t (&r)[4]) {
-        if constexpr (PART != 0) {
+        if constexpr (WIDE) {
+            // this wave's pair of buffers from the wave above, and to the one below
+            const int hb = (hand_buf_g & 1) * 256 + lane;
+            const uint32_t* const hin = hand + (TOP ? 0 : (PART - 2) * 512) + hb;
+            uint32_t* const hout = hand + (UPPER ? (PART - 1) * 512 : 0) + hb;
+            ++hand_buf_g;
+            uint32_t t_in[4] = {0u, 0u, 0u, 0u};
+            if constexpr (!TOP) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) t_in[i] = hin[i * 64];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i < n) {
+                    const uint32_t t = comb_rows(l0 + i, t_in[i]);
+                    if constexpr (UPPER)
+                        hout[i * 64] = t;
+                    else
+                        r[i] = count(l0 + i, t);
+                }
+            }
+            __syncthreads();
+        } else if constexpr (PART != 0) {
             uint32_t* const hb = hand + (hand_buf_g & 1) * 256 + lane;
             ++hand_buf_g;
             if constexpr (UPPER) {
@@ -481,6 +521,9 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     } else if constexpr (PART == 0) {
         for (int l = 0; l < w - 1; ++l) (void)column(l);
     } else {
+        if constexpr (WIDE) {
+            for (int q = 1; q < PART; ++q) __syncthreads();  // the chain fills: one group per wave above
+        }
         uint32_t r[4];
         for (int l = 0; l < w - 1; l += 4) group(l, w - 1 - l < 4 ? w - 1 - l : 4, r);
     }
@@ -665,6 +708,9 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
             }
         }
         stage_sync();
+    }
+    if constexpr (WIDE) {
+        for (int q = PART; q < NPART; ++q) __syncthreads();  // the chain drains: one group per wave below
     }
 }
 

@@ -162,8 +162,19 @@ void check_unit(Spec& s, int job, int64_t unit, const wlcs::Geom& g, const uint1
     // a copy of it) loads rows up to wc - 1 - pad of its window
     if (xf != s.pair.xf) die("x codes of another pair", job, unit, 0, 0);
     const int64_t sx = std::min<int64_t>(s0 + 63, g.rows - 1);
-    const int pad = exact ? 0 : ((w + 15) & ~15) - w;
-    const int64_t xhi = sx * g.xstride + (wc - 1 - pad);
+    // (the 256-row class: each wave of the chain loads the 64 rows from its
+    // first one, in a strip padded to whole 8-row blocks)
+    int last_row = wc - 1, pad = exact ? 0 : ((w + 15) & ~15) - w;
+    if (wc == 256) {
+        pad = wlcs::wide_pad_rows(w) - w;
+        last_row = 0;
+        for (int q = 0; q < wlcs::kWideWaves; ++q) {
+            int r0, nr;
+            wlcs::wide_rows(w, q, &r0, &nr);
+            last_row = std::max(last_row, r0 + wlcs::kWideRowsPerWave - 1);
+        }
+    }
+    const int64_t xhi = sx * g.xstride + (last_row - pad);
     if (xhi >= s.pair.xf_cap) die("x read past the codes", job, unit, xhi, s.pair.xf_cap);
     // y codes: columns 0 .. nproc + w - 2 of each tile are combed, column
     // nproc + w - 1 is prefetched; each read is the u32 holding two columns
@@ -411,6 +422,26 @@ int main(int argc, char** argv) {
     const uint64_t seed = argc > 1 ? std::strtoull(argv[1], nullptr, 10) : 1;
     const int rounds = argc > 2 ? std::atoi(argv[2]) : 20;
     std::mt19937_64 rng(seed);
+    // the 256-row class: the waves of a strip's chain hold consecutive runs of
+    // whole 16-row blocks that cover the padded strip, at most 64 rows each
+    // and at most the class's 256 rows of codes read, the last wave (which
+    // also counts and stores) holding the fewest
+    for (int w = 129; w <= 255; ++w) {
+        const int np = wlcs::kWideWaves, wpad = wlcs::wide_pad_rows(w);
+        if (wpad < w || wpad > 256 || wpad > 64 * np) die("wide chain length", 0, w, np, wpad);
+        int next = 0, last_nr = 0, min_nr = 1 << 30;
+        for (int q = 0; q < np; ++q) {
+            int r0, nr;
+            wlcs::wide_rows(w, q, &r0, &nr);
+            if (r0 != next || nr < wlcs::kWideMinRows || nr > wlcs::kWideRowsPerWave || nr % wlcs::kWideRowBlock ||
+                r0 + wlcs::kWideRowsPerWave - 1 > 255)
+                die("wide rows", 0, w, r0, nr);
+            next = r0 + nr;
+            last_nr = nr;
+            min_nr = std::min(min_nr, nr);
+        }
+        if (next != wpad || last_nr != min_nr) die("wide rows cover", 0, w, next, wpad);
+    }
     wlcs_ctx* ctx = new wlcs_ctx();
     ctx->cus = 256;
     long long units = 0;

@@ -62,6 +62,10 @@ def test_combing_kernels_keep_their_occupancy(report):
             assert occ >= 3, (name, occ)
             seen.add("rsplit")
             continue
+        if "19seaweed_kernel_wide" in name:
+            assert occ >= 3 and v.get("agprs", 0) == 0, (name, occ)
+            seen.add("wide")
+            continue
         m = re.search(r"12batch_kernelILi(\d)E", name)
         if m:
             want = 4 if m.group(1) == "0" else 3
@@ -71,11 +75,13 @@ def test_combing_kernels_keep_their_occupancy(report):
         if "18batch_kernel_split" in name:
             assert occ >= 3, (name, occ)
             seen.add("batch_split")
-    assert seen >= {"dl", "general16", "general32", "general64", "general256", "dl_split", "rsplit",
+    assert seen >= {"dl", "general16", "general32", "general64", "wide", "dl_split", "rsplit",
                     "batch0", "batch1", "batch_split"}, seen
 
 
-def test_no_exact_kernel_for_the_256_row_class(report):
-    """Windows are at most 255 long, so the 256-row class is only compiled for
-    windows shorter than the class."""
-    assert not [k for k in report if "14seaweed_kernelILi256ELb1E" in k]
+def test_no_single_wave_kernel_for_the_256_row_class(report):
+    """The 256-row class runs as a chain of four waves per strip;
+    no kernel holds a whole 256-row strip in one wave (that needs the
+    accumulation registers, at one wave per SIMD)."""
+    assert not [k for k in report if "14seaweed_kernelILi256E" in k]
+    assert len([k for k in report if "19seaweed_kernel_wide" in k]) == 2  # plain and strided / sparse
