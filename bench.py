@@ -450,6 +450,12 @@ def main():
             others[workloads.config(k).name] = bench_config(ctx, torch, workloads, k)
             log(f"config {k}: {others[workloads.config(k).name]}")
 
+    wide = None
+    if not args.no_configs:
+        wide = bench_wide(ctx, torch, workloads)
+        log("windows of 129..255 letters (30,000 x 30,000 protein): " + ", ".join(
+            f"w={w} {v['ms']:.2f} ms ({v['roofline_frac']:.2f})" for w, v in wide["plots"].items()))
+
     paper_shapes = None
     if not args.no_paper_shapes:
         paper_shapes = bench_paper_shapes(ctx, torch, workloads)
@@ -487,7 +493,7 @@ def main():
                                   source="measured (tuning cache)" if any(ctx.plot_tiling(rows, cols, w))
                                   else "built-in tile model")},
         "roofline": roofline, "cpu_baseline": cpu, "gpu_dp_baseline": dp,
-        "other_configs": others, "paper_shaped_score_plots": paper_shapes,
+        "other_configs": others, "wide_windows": wide, "paper_shaped_score_plots": paper_shapes,
         "batched": batched, "serving": serving, "step5_lcs_plot": step5, "dot_list_filter": dots_filter,
         "encode_ms": encode_ms, "parity_sampled_rows": parity,
         "kernel_ms": {"min": float(np.min(kern_ms)), "median": float(np.median(kern_ms)),
@@ -596,6 +602,36 @@ def bench_config(ctx, torch, workloads, k, steps=10):
     del out, dp_out
     torch.cuda.empty_cache()
     return res
+
+
+def bench_wide(ctx, torch, workloads, widths=(150, 200, 255), steps=5):
+    """Plain plots with windows of 129..255 letters (the 256-row class, a
+    chain of four waves per strip) on the 30,000 x 30,000 protein pair; at
+    w = 200 the plot is compared whole with the GPU BLCS baseline's."""
+    import numpy as np
+    p = workloads.config(3)
+    pair = ctx.pair(p.x, p.y, alphabet=p.alphabet)
+    plots = {}
+    blcs = None
+    for w in widths:
+        rows, cols = p.m - w, p.n - w
+        out = torch.empty((rows, cols), dtype=torch.uint8, device="cuda")
+        pair.plot(w, out=out)
+        ms = float(np.median([_timed_once(torch, lambda: pair.plot(w, out=out)) for _ in range(steps)]))
+        cells = float(rows) * p.n * w
+        plots[w] = {"ms": ms, "value": float(p.m) * p.n * w / (ms / 1e3), "unit": "window-cells/s",
+                    "roofline_frac": cells * OPS_PER_CELL / (ms / 1e3) / PEAK_U16_OPS}
+        if w == 200:
+            ref = torch.empty_like(out)
+            pair.plot_blcs(w, out=ref)
+            blcs_ms = _timed_once(torch, lambda: pair.plot_blcs(w, out=ref))
+            blcs = {"w": w, "ms": blcs_ms, "speedup_seaweed_over_blcs": blcs_ms / ms,
+                    "equals_seaweed": bool(torch.equal(out, ref))}
+            del ref
+        del out
+        torch.cuda.empty_cache()
+    pair.close()
+    return {"workload": f"{p.name}, windows {', '.join(str(w) for w in widths)}", "plots": plots, "blcs": blcs}
 
 
 # The paper's experiments (Section 4, Table 1): alignment-score plots with
