@@ -367,7 +367,9 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                 // uniform, once per block of rows past the fewest a wave holds
                 if (k >= kWideMinRows && (k % kWideRowBlock) == 0 && k >= nrw) break;
             } else {
-                if (!EXACT && ((R0 + k) & 15) == 0 && R0 + k >= wpad) break;  // uniform, once per 16 rows
+                // uniform, once per 16 rows; a window of the class is longer
+                // than half of it, so no row up to the half is ever skipped
+                if (!EXACT && R0 + k > WC / 2 && ((R0 + k) & 15) == 0 && R0 + k >= wpad) break;
             }
             t = (k & 1) ? seaweed_cell<1>(h[k], t, xc[k >> 1], Y) : seaweed_cell<0>(h[k], t, xc[k >> 1], Y);
         }
