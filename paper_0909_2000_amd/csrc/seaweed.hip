@@ -13,7 +13,9 @@
 // columns j..j+w-1 and leave the bottom inside the same columns; the count
 // slides along y in O(1) per column.
 //
-// GPU mapping (one 64-lane wavefront per workgroup):
+// GPU mapping (one 64-lane wavefront per workgroup; strips of 65..128 rows
+// are split over two waves and strips of 129..255 rows over a chain of four,
+// see seaweed_kernel_rsplit and seaweed_kernel_wide):
 //  * lane = strip: the 64 lanes of a wave comb 64 consecutive x-windows, so
 //    the y letter of the current column is the same for every lane (it arrives
 //    through scalar loads, one column ahead) and the x letters of each lane's
