@@ -107,8 +107,9 @@ def _long_window_case(oracle_mod, w):
 @pytest.mark.parametrize("w", [129, 160, 200, 255])
 @pytest.mark.parametrize("tile", [1024, 2048, 4096])
 def test_long_windows_across_rebases(ctx, oracle_mod, w, tile):
-    """Windows of 129..255 (the one-wave 256-row class, whose labels reach
-    511 + 2w < 1024 just before the first relabelling) on rows long enough that
+    """Windows of 129..255 (the 256-row class, a chain of four waves per
+    strip, whose labels reach 511 + 2w < 1024 just before the first
+    relabelling, in every wave of the chain) on rows long enough that
     one tile crosses the relabelling every 512 windows once (1,024-window
     tiles), three times (2,048) or four times (4,096, one evenly split pair of
     2,176): whole plot, bitmap and indel distance against the oracle."""
