@@ -217,12 +217,13 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     const int w = EXACT ? WC : g.w;
 
     // Rows.  A window shorter than its class runs in a strip padded at the
-    // top to wpad = w rounded up to 16 rows: the pad rows hold a code that no
-    // y letter has, so every cell there is a mismatch whose left-boundary
-    // label (0) stays put while each seaweed from the top (label >= 1) passes
-    // straight down -- the padded strip has the same exits as the strip of
-    // height w.  Rows from wpad on are skipped 16 at a time by one uniform
-    // branch, so no cell carries a test of its own.
+    // top to wpad = w rounded up to 16 rows (8 in the 256-row chain): the pad
+    // rows hold a code that no y letter has, so every cell there is a
+    // mismatch whose left-boundary label (0) stays put while each seaweed
+    // from the top (label >= 1) passes straight down -- the padded strip has
+    // the same exits as the strip of height w.  Rows from wpad on are skipped
+    // 16 (8) at a time by one uniform branch, so no cell carries a test of
+    // its own.
     const int pad = (EXACT || DL) ? 0 : (WIDE ? wide_pad_rows(w) : (w + 15) & ~15) - w;
     const int wpad = (EXACT || DL) ? WC : w + pad;
     constexpr int NP = WC / 2;                 // DL: pair slots
@@ -386,10 +387,12 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     int hand_buf_g = 0;
     auto group = [&](int l0, int n, uint32_t (&r)[4]) {
         if constexpr (WIDE) {
-            // this wave's pair of buffers from the wave above, and to the one below
-            const int hb = (hand_buf_g & 1) * 256 + lane;
-            const uint32_t* const hin = hand + (TOP ? 0 : (PART - 2) * 512) + hb;
-            uint32_t* const hout = hand + (UPPER ? (PART - 1) * 512 : 0) + hb;
+            // this wave's pair of buffers from the wave above, and to the one
+            // below (kDlHandDwords per link: two buffers of four columns of
+            // 64 lanes)
+            const int hb = (hand_buf_g & 1) * (kDlHandDwords / 2) + lane;
+            const uint32_t* const hin = hand + (TOP ? 0 : (PART - 2) * kDlHandDwords) + hb;
+            uint32_t* const hout = hand + (UPPER ? (PART - 1) * kDlHandDwords : 0) + hb;
             ++hand_buf_g;
             uint32_t t_in[4] = {0u, 0u, 0u, 0u};
             if constexpr (!TOP) {
