@@ -374,6 +374,16 @@ int wlcs_graph_destroy(wlcs_graph *graph); /* waits for the graph's device memor
 int wlcs_ctx_set_batch_tile(wlcs_ctx *ctx, int32_t w_lo, int32_t w_hi, int32_t tile_windows);
 int wlcs_ctx_set_batch_grid(wlcs_ctx *ctx, int32_t waves_per_cu);
 
+/* Latency of small jobs in a batch: a job whose tiles (as set above, or the
+ * built-in choice) give it fewer than min_units units (64 x-windows by one
+ * pair of tiles each) has its tiles shortened, in whole blocks of 64 windows
+ * down to 64, until it has at least that many, so that it spreads over the
+ * device instead of combing long tiles on a few waves.  Jobs with enough
+ * units keep their tiles; the plots do not depend on the tiling.  min_units
+ * 0 (the default) turns this off; 1..1,048,576 otherwise, else WLCS_EINVAL.
+ * A serving loop sets about one unit per SIMD of the device. */
+int wlcs_ctx_set_batch_min_units(wlcs_ctx *ctx, int64_t min_units);
+
 /* What applies now: the tile set for batched plots of window w (0 if the
  * built-in choice applies), and the persistent grid (0: the default). */
 int wlcs_ctx_get_batch_tile(const wlcs_ctx *ctx, int32_t w, int32_t *tile_windows);

@@ -104,6 +104,7 @@ def _load():
     lib.wlcs_graph_destroy.argtypes = [vp]
     lib.wlcs_ctx_set_batch_tile.argtypes = [vp, i32, i32, i32]
     lib.wlcs_ctx_set_batch_grid.argtypes = [vp, i32]
+    lib.wlcs_ctx_set_batch_min_units.argtypes = [vp, i64]
     lib.wlcs_ctx_get_batch_tile.argtypes = [vp, i32, ctypes.POINTER(i32)]
     lib.wlcs_ctx_get_batch_grid.argtypes = [vp, ctypes.POINTER(i32)]
     lib.wlcs_tune.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint32]
@@ -119,6 +120,7 @@ def _load():
               "wlcs_plot", "wlcs_plot_dp", "wlcs_pair_create", "wlcs_pair_destroy", "wlcs_pair_plot",
               "wlcs_pair_plot_dp", "wlcs_batch", "wlcs_batch_noalloc", "wlcs_batch_graph",
               "wlcs_graph_launch", "wlcs_graph_destroy", "wlcs_ctx_set_batch_tile", "wlcs_ctx_set_batch_grid",
+              "wlcs_ctx_set_batch_min_units",
               "wlcs_score_plot", "wlcs_ctx_get_batch_tile", "wlcs_ctx_get_batch_grid", "wlcs_tune",
               "wlcs_pair_plot_strided", "wlcs_pair_plot_dp_strided", "wlcs_plot_blcs",
               "wlcs_pair_plot_blcs", "wlcs_pair_dots_filtered", "wlcs_tune_plot", "wlcs_ctx_get_plot_tiling"):
@@ -309,6 +311,13 @@ class Context:
         st = _load().wlcs_ctx_set_batch_grid(self._h, waves_per_cu)
         if st != 0:
             raise WlcsError(st, "wlcs_ctx_set_batch_grid")
+
+    def set_batch_min_units(self, min_units: int):
+        """wlcs_ctx_set_batch_min_units: batched jobs with fewer units than
+        this get shorter tiles (0: off)."""
+        st = _load().wlcs_ctx_set_batch_min_units(self._h, int(min_units))
+        if st != 0:
+            raise WlcsError(st, "wlcs_ctx_set_batch_min_units")
 
     def batch_tile(self, w: int) -> int:
         """Tile set for batched plots of window w (0: the built-in choice)."""

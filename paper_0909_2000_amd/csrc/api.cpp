@@ -644,6 +644,18 @@ int32_t batch_tile(const wlcs_ctx* ctx, int64_t cols, int32_t w) {
     return (int32_t)t;
 }
 
+// A batched job with fewer than min_units units (strip blocks x tile pairs)
+// under its tile gets the longest shorter tile, in whole 64-window blocks and
+// at least 64, that gives it min_units units (or 64 if none does).
+void shrink_for_units(wlcs::PlotArgs& a, int64_t rows, int64_t cols, int64_t min_units) {
+    const int64_t nblocks = (rows + 63) / 64;
+    if (nblocks * (int64_t)a.npairs >= min_units || a.tile <= 64) return;
+    const int64_t pairs = (min_units + nblocks - 1) / nblocks;  // pairs per block wanted
+    int64_t t = (cols + 2 * pairs - 1) / (2 * pairs);           // windows per tile for that many
+    t = std::max<int64_t>(64, t / 64 * 64);
+    if (t < a.tile) uniform_tiles(a, cols, (int32_t)t);
+}
+
 // One table entry being planned: a job's tile pairs but the last, or its last pair.
 struct PlanItem {
     wlcs::JobDesc d;
@@ -717,6 +729,7 @@ int plan_batch(wlcs_ctx* ctx, const wlcs_job* jobs, int32_t njobs, BatchPlan& pl
             continue;
         }
         uniform_tiles(a, cols, batch_tile(ctx, cols, j.w));
+        if (ctx->batch_min_units > 0) shrink_for_units(a, rows, cols, ctx->batch_min_units);
         int64_t xf_len, yg_len;
         needed_lengths(Path::Seaweed, rows, cols, j.w, a, xf_len, yg_len);
         if (xf_len > j.pair->xf_cap || yg_len > j.pair->yg_cap) return WLCS_EINVAL;
@@ -1354,6 +1367,12 @@ int wlcs_ctx_set_batch_tile(wlcs_ctx* ctx, int32_t w_lo, int32_t w_hi, int32_t t
 int wlcs_ctx_set_batch_grid(wlcs_ctx* ctx, int32_t waves_per_cu) {
     if (!ctx || waves_per_cu < 0 || waves_per_cu > 16) return WLCS_EINVAL;
     ctx->batch_waves_per_cu = waves_per_cu;
+    return WLCS_OK;
+}
+
+int wlcs_ctx_set_batch_min_units(wlcs_ctx* ctx, int64_t min_units) {
+    if (!ctx || min_units < 0 || min_units > (1 << 20)) return WLCS_EINVAL;
+    ctx->batch_min_units = min_units;
     return WLCS_OK;
 }
 

@@ -77,6 +77,7 @@ struct wlcs_ctx {
     wlcs_rt::TileRule batch_rules[16];
     int nbatch_rules = 0;
     int batch_waves_per_cu = 0;  // 0: each batched kernel's resident capacity
+    int64_t batch_min_units = 0;  // > 0: a batched job's tiles shrink until it has this many units
     wlcs_rt::TileChoice tile_cache[wlcs_rt::kTileCache];  // recent built-in tilings
     int tile_cache_next = 0;
     wlcs_rt::TileChoice tuned[wlcs_rt::kTuned];  // measured tilings by shape (general plots, ws = 1)

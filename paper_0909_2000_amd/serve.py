@@ -129,6 +129,10 @@ def job_cost(js) -> float:
 # job spreads over the device even when few others run beside it.
 LATENCY_TILES = {(1, 64): 512, (65, 128): 1024}
 LATENCY_GRID = 16
+# A job with fewer units than this under those tiles gets shorter ones
+# (wlcs_ctx_set_batch_min_units): a small job then spreads over about one
+# unit per SIMD of the device instead of combing its tiles on a few waves.
+LATENCY_MIN_UNITS = 1024
 
 
 # Streams of the executors, per device, shared by every executor of the
@@ -150,7 +154,8 @@ class GpuExecutor:
     """Runs batches on one GPU through libwlcs, one stream per concurrent batch
     (from the process's shared stream pool), each batch as sub-batches with
     their own completion events.  Without a context of its own it makes one
-    with the latency tiles.  With d2h_bitmaps each job's bitmap is also copied
+    with the latency tiles (and shorter ones for jobs too small to fill the
+    device, LATENCY_MIN_UNITS).  With d2h_bitmaps each job's bitmap is also copied
     to pinned host memory on the stream before its sub-batch's completion event
     (result "bitmap_host"), so that a job's latency runs until its result is on
     the host."""
@@ -166,6 +171,7 @@ class GpuExecutor:
             for (lo, hi), t in LATENCY_TILES.items():
                 ctx.set_batch_tile(lo, hi, t)
             ctx.set_batch_grid(LATENCY_GRID)
+            ctx.set_batch_min_units(LATENCY_MIN_UNITS)
         self.ctx = ctx
         self.d2h = d2h_bitmaps
         self.streams = _streams(torch, self.dev, streams)

@@ -284,6 +284,9 @@ void random_rules(std::mt19937_64& rng, wlcs_ctx& ctx) {
             if (uni(0, 1)) add_rule(ctx.batch_rules, ctx.nbatch_rules, TileRule{lo + (k > 0), hi, tiles[uni(0, 8)]});
         }
     }
+    // batched jobs with too few units on shorter tiles (wlcs_ctx_set_batch_min_units)
+    static const int64_t min_units[] = {0, 0, 1, 64, 1024, 4096, 1 << 20};
+    ctx.batch_min_units = min_units[uni(0, 6)];
 }
 
 wlcs_job to_job(const Spec& s) {
@@ -453,6 +456,7 @@ int main(int argc, char** argv) {
     }
     // the sizes of the benchmark's plots and batch, with the built-in tilings
     ctx->nrules = ctx->nbatch_rules = 0;
+    ctx->batch_min_units = 0;
     for (const auto& shp : {std::make_tuple(50000, 50000, 64), std::make_tuple(30000, 30000, 128),
                             std::make_tuple(1000, 1000, 16), std::make_tuple(20000, 20000, 255)}) {
         Spec s;

@@ -107,6 +107,7 @@ def test_pair_and_ctx_argument_checks(lib):
     assert lib.wlcs_ctx_destroy(None) == 0
     assert lib.wlcs_ctx_set_tile(None, 1, 16, 64) == EINVAL
     assert lib.wlcs_ctx_set_tiles(None, 1, 16, 1024, 64, 2) == EINVAL
+    assert lib.wlcs_ctx_set_batch_min_units(None, 1024) == EINVAL
     v = ctypes.c_double(-1.0)
     assert lib.wlcs_measure_valu_peak(None, 100, ctypes.byref(v)) == EINVAL and v.value == -1.0
     assert lib.wlcs_measure_valu_issue(None, 0, 1, 100, ctypes.byref(v)) == EINVAL and v.value == -1.0

@@ -107,6 +107,31 @@ def test_grid_and_tile_do_not_change_results(ctx, grid, tile):
         assert torch.equal(a["wlcs"], b["wlcs"])
 
 
+@pytest.mark.parametrize("min_units", [1, 1024, 1 << 20])
+def test_min_units_shortens_tiles_without_changing_results(ctx, oracle_mod, min_units):
+    """wlcs_ctx_set_batch_min_units: jobs with fewer units than asked for run
+    on shorter tiles (down to 64 windows for 1 << 20); every plot still equals
+    the batch without the setting, and the oracle on a few of them."""
+    import torch
+    specs, inputs = _mixed_specs(ctx, 14, 16, 100, 2500, (16, 32, 64, 128, 50), extras=True)
+    ctx.set_batch_tile(1, 128, 4096)  # long tiles: few units per job
+    try:
+        ref = ctx.batch(specs)
+        ctx.set_batch_min_units(min_units)
+        try:
+            got = ctx.batch(specs)
+        finally:
+            ctx.set_batch_min_units(0)
+    finally:
+        ctx.set_batch_tile(1, 128, 0)
+    _say(f"min units {min_units}: {len(specs)} plots")
+    for a, b in zip(ref, got):
+        for key in a:
+            assert torch.equal(a[key], b[key]), key
+    for k in (0, 5, 11):
+        _check_vs_oracle(oracle_mod, got[k], specs[k], *inputs[k])
+
+
 def test_batch_row_strides_and_empty_jobs(ctx, oracle_mod):
     import torch
     g = workloads.rng(14)
