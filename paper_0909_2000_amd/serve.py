@@ -135,6 +135,14 @@ LATENCY_GRID = 16
 LATENCY_MIN_UNITS = 1024
 
 
+# The serving loop's waits.  While batches run it polls their events without
+# sleeping (POLL_SLEEP_S 0).  With nothing running it sleeps until the next
+# arrival, waking ARRIVAL_EARLY_S early and polling the clock from there,
+# since a sleep overshoots by tens of microseconds.
+POLL_SLEEP_S = 0.0
+ARRIVAL_EARLY_S = 200e-6
+
+
 # Streams of the executors, per device, shared by every executor of the
 # process: torch's caching allocator keeps freed blocks per stream, so
 # executors on new streams could not reuse the output memory their
@@ -275,7 +283,12 @@ class GpuExecutor:
         return [bid for bid, _, done in self.poll_jobs() if done]
 
     def idle_wait(self):
-        time.sleep(20e-6)
+        """Between polls while batches run: with POLL_SLEEP_S 0 the loop keeps
+        polling the completion events (one host core busy); a sleep, however
+        short, lasts tens of microseconds more than asked (timer slack), which
+        every job's latency pays."""
+        if POLL_SLEEP_S > 0:
+            time.sleep(POLL_SLEEP_S)
 
 
 class Server:
@@ -494,7 +507,9 @@ class Server:
                 nxt = reqs[k].arrival if k < len(reqs) else None
                 self.ex.advance(nxt)
             elif k < len(reqs) and not self.busy():
-                time.sleep(max(0.0, min(reqs[k].arrival - self.ex.now(), 1e-3)))
+                gap = reqs[k].arrival - self.ex.now() - ARRIVAL_EARLY_S
+                if gap > 0:
+                    time.sleep(min(gap, 1e-3))
             else:
                 self.ex.idle_wait()
         return self.report()
