@@ -187,6 +187,15 @@ constexpr int kWideRowsPerWave = 64;
 constexpr int kWideRowBlock = 8;
 constexpr int kWideMinRows = 32;
 __host__ __device__ constexpr int wide_pad_rows(int w) { return (w + kWideRowBlock - 1) / kWideRowBlock * kWideRowBlock; }
+// Rows of the strip a window shorter than its class is combed in (padded at
+// the top with rows that match nothing): w rounded up to a block of
+// kPadRowBlock rows, the rows past it skipped one block at a time.
+constexpr int kPadRowBlock = 8;
+__host__ __device__ constexpr int pad_rows(int w) { return (w + kPadRowBlock - 1) / kPadRowBlock * kPadRowBlock; }
+// The fewest rows a window of class wc is combed in (class 16 holds windows
+// of 1..16 letters, every larger class those longer than half of it): no row
+// below it is ever skipped.
+constexpr int min_pad_rows(int wc) { return pad_rows(wc <= 16 ? 1 : wc / 2 + 1); }
 // rows [*r0, *r0 + *nr) of the padded strip go to wave q (0-based) of the chain
 __host__ __device__ inline void wide_rows(int w, int q, int* r0, int* nr) {
     const int blocks = wide_pad_rows(w) / kWideRowBlock;

@@ -217,14 +217,14 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
     const int w = EXACT ? WC : g.w;
 
     // Rows.  A window shorter than its class runs in a strip padded at the
-    // top to wpad = w rounded up to 16 rows (8 in the 256-row chain): the pad
+    // top to wpad = w rounded up to 8 rows (pad_rows, wide_pad_rows): the pad
     // rows hold a code that no y letter has, so every cell there is a
     // mismatch whose left-boundary label (0) stays put while each seaweed
     // from the top (label >= 1) passes straight down -- the padded strip has
     // the same exits as the strip of height w.  Rows from wpad on are skipped
-    // 16 (8) at a time by one uniform branch, so no cell carries a test of
-    // its own.
-    const int pad = (EXACT || DL) ? 0 : (WIDE ? wide_pad_rows(w) : (w + 15) & ~15) - w;
+    // 8 at a time by one uniform branch, so no cell carries a test of its
+    // own.
+    const int pad = (EXACT || DL) ? 0 : (WIDE ? wide_pad_rows(w) : pad_rows(w)) - w;
     const int wpad = (EXACT || DL) ? WC : w + pad;
     constexpr int NP = WC / 2;                 // DL: pair slots
     const int ppad = DL ? NP - w / 2 : 0;      // DL: unused slots at the top (< kDlSlots)
@@ -368,9 +368,10 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
                 // uniform, once per block of rows past the fewest a wave holds
                 if (k >= kWideMinRows && (k % kWideRowBlock) == 0 && k >= nrw) break;
             } else {
-                // uniform, once per 16 rows; a window of the class is longer
-                // than half of it, so no row up to the half is ever skipped
-                if (!EXACT && R0 + k > WC / 2 && ((R0 + k) & 15) == 0 && R0 + k >= wpad) break;
+                // uniform, once per block of rows from the fewest a window of
+                // the class is combed in
+                if (!EXACT && R0 + k >= min_pad_rows(WC) && ((R0 + k) % kPadRowBlock) == 0 && R0 + k >= wpad)
+                    break;
             }
             t = (k & 1) ? seaweed_cell<1>(h[k], t, xc[k >> 1], Y) : seaweed_cell<0>(h[k], t, xc[k >> 1], Y);
         }

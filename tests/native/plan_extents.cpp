@@ -164,7 +164,7 @@ void check_unit(Spec& s, int job, int64_t unit, const wlcs::Geom& g, const uint1
     const int64_t sx = std::min<int64_t>(s0 + 63, g.rows - 1);
     // (the 256-row class: each wave of the chain loads the 64 rows from its
     // first one, in a strip padded to whole 8-row blocks)
-    int last_row = wc - 1, pad = exact ? 0 : ((w + 15) & ~15) - w;
+    int last_row = wc - 1, pad = exact ? 0 : wlcs::pad_rows(w) - w;
     if (wc == 256) {
         pad = wlcs::wide_pad_rows(w) - w;
         last_row = 0;
