@@ -195,7 +195,17 @@ __host__ __device__ constexpr int pad_rows(int w) { return (w + kPadRowBlock - 1
 // The fewest rows a window of class wc is combed in (class 16 holds windows
 // of 1..16 letters, every larger class those longer than half of it): no row
 // below it is ever skipped.
-constexpr int min_pad_rows(int wc) { return pad_rows(wc <= 16 ? 1 : wc / 2 + 1); }
+__host__ __device__ constexpr int min_pad_rows(int wc) { return pad_rows(wc <= 16 ? 1 : wc / 2 + 1); }
+// Whether a window shorter than class wc, combed in wpad rows, stops before
+// row r of the strip: tested once per block of rows from the fewest rows a
+// window of the class is combed in.
+__host__ __device__ constexpr bool stops_at_row(int wc, int r, int wpad) {
+    return r >= min_pad_rows(wc) && r % kPadRowBlock == 0 && r >= wpad;
+}
+// The same for row k of a wave of the 256-row chain holding nrw rows.
+__host__ __device__ constexpr bool wide_stops_at_row(int k, int nrw) {
+    return k >= kWideMinRows && k % kWideRowBlock == 0 && k >= nrw;
+}
 // rows [*r0, *r0 + *nr) of the padded strip go to wave q (0-based) of the chain
 __host__ __device__ inline void wide_rows(int w, int q, int* r0, int* nr) {
     const int blocks = wide_pad_rows(w) / kWideRowBlock;

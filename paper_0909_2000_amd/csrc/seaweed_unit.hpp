@@ -364,14 +364,11 @@ __device__ __forceinline__ void comb_unit(const uint16_t* __restrict__ xf, const
         if constexpr (TOP) t = seaweed_cell_top(h[0], pk_rep(l - org + 1), xc[0], Y);
 #pragma unroll
         for (int k = TOP ? 1 : 0; k < NR; ++k) {
+            // uniform, once per block of rows past the fewest a wave holds
             if constexpr (WIDE) {
-                // uniform, once per block of rows past the fewest a wave holds
-                if (k >= kWideMinRows && (k % kWideRowBlock) == 0 && k >= nrw) break;
+                if (wide_stops_at_row(k, nrw)) break;
             } else {
-                // uniform, once per block of rows from the fewest a window of
-                // the class is combed in
-                if (!EXACT && R0 + k >= min_pad_rows(WC) && ((R0 + k) % kPadRowBlock) == 0 && R0 + k >= wpad)
-                    break;
+                if (!EXACT && stops_at_row(WC, R0 + k, wpad)) break;
             }
             t = (k & 1) ? seaweed_cell<1>(h[k], t, xc[k >> 1], Y) : seaweed_cell<0>(h[k], t, xc[k >> 1], Y);
         }

@@ -445,6 +445,39 @@ int main(int argc, char** argv) {
         }
         if (next != wpad || last_nr != min_nr) die("wide rows cover", 0, w, next, wpad);
     }
+    // every window is combed in exactly its padded rows: each wave's row loop
+    // (as comb_rows runs it, with the kernels' own stop tests) covers its
+    // rows of the strip and no more, for every window length and class
+    for (int w = 1; w <= 255; ++w) {
+        const int wc = wlcs::w_class(w);
+        if (wc < 256) {
+            const bool exact = w == wc;
+            const int wpad = exact ? wc : wlcs::pad_rows(w);
+            // one wave holds the strip, or two halves (the 128-row class)
+            const int nparts = wc == 128 ? 2 : 1, nr = wc / nparts;
+            int combed = 0;
+            for (int q = 0; q < nparts; ++q) {
+                const int r0 = q * nr;
+                for (int k = 0; k < nr; ++k) {
+                    if (!exact && wlcs::stops_at_row(wc, r0 + k, wpad)) break;
+                    if (r0 + k != combed) die("rows combed out of order", 0, w, r0 + k, combed);
+                    ++combed;
+                }
+            }
+            if (combed != wpad || wpad < w || wpad - w >= wlcs::kPadRowBlock) die("padded rows", 0, w, combed, wpad);
+        } else {
+            int next = 0;
+            for (int q = 0; q < wlcs::kWideWaves; ++q) {
+                int r0, nr;
+                wlcs::wide_rows(w, q, &r0, &nr);
+                int k = 0;
+                while (k < wlcs::kWideRowsPerWave && !wlcs::wide_stops_at_row(k, nr)) ++k;
+                if (r0 != next || k != nr) die("wide wave rows combed", 0, w, k, nr);
+                next += k;
+            }
+            if (next != wlcs::wide_pad_rows(w)) die("wide padded rows", 0, w, next, wlcs::wide_pad_rows(w));
+        }
+    }
     wlcs_ctx* ctx = new wlcs_ctx();
     ctx->cus = 256;
     long long units = 0;
